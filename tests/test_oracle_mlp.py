@@ -1,0 +1,68 @@
+"""Pins of the oracle's control-variate network: gradients by finite differences,
+Adam against its textbook first step, and a fit that actually learns."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2301_05780_amd import workloads
+
+
+def _data(n=64, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0, 1, size=(n, 2))
+    T = np.sin(3 * X[:, 0]) + X[:, 1] ** 2
+    return X, T
+
+
+def test_param_count_and_layout():
+    theta = workloads.mlp_init(0)
+    assert theta.size == mlp.N_PARAMS == workloads.MLP_PARAMS == 4417
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(theta)
+    assert W1.shape == (64, 2) and W2.shape == (64, 64) and w3.shape == (64,)
+    assert np.array_equal(mlp.pack(W1, b1, W2, b2, w3, b3), theta)
+
+
+def test_loss_gradient_finite_differences():
+    rng = np.random.default_rng(1)
+    theta = workloads.mlp_init(3) + rng.normal(0, 0.05, mlp.N_PARAMS)
+    X, T = _data()
+    _, g = mlp.loss_and_grad(theta, X, T)
+    idx = rng.choice(mlp.N_PARAMS, 200, replace=False)
+    idx = np.concatenate([idx, [0, 1, 128, 192, 4288, 4416]])
+    e = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += e
+        tm[i] -= e
+        fd = (mlp.loss_and_grad(tp, X, T)[0] - mlp.loss_and_grad(tm, X, T)[0]) / (2 * e)
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+def test_input_gradient_finite_differences():
+    theta = workloads.mlp_init(4)
+    X, _ = _data(32, 2)
+    gx = mlp.grad_input(theta, X)
+    e = 1e-6
+    for d in range(2):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[:, d] += e
+        Xm[:, d] -= e
+        fd = (mlp.forward(theta, Xp)[0] - mlp.forward(theta, Xm)[0]) / (2 * e)
+        assert np.allclose(gx[:, d], fd, rtol=1e-6, atol=1e-10)
+
+
+def test_adam_first_step():
+    """Bias correction makes the first step lr * g / (|g| + eps) per coordinate."""
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    new, m, s = mlp.adam_step(theta, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    assert np.allclose(new, theta - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    assert np.allclose(m, 0.1 * g) and np.allclose(s, 0.001 * g * g)
+
+
+def test_training_reduces_loss():
+    X, T = _data(512, 3)
+    theta0 = workloads.mlp_init(0)
+    order = workloads.minibatch_order(512, 40, seed=1)
+    theta, losses = mlp.train(theta0, X, T, order, batch=64, lr=3e-3)
+    assert losses[-20:].mean() < 0.05 * losses[:5].mean()
