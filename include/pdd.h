@@ -1,0 +1,211 @@
+/*
+ * pdd.h -- C ABI of the MI355X (gfx950) Monte Carlo assembler of the
+ * PDDSparse interfacial system G u = b (Bernal, Moron-Vidal, Acebron,
+ * arXiv 2301.05780).
+ *
+ * Conventions shared by every entry point
+ *   - Plain C types only.  "device" pointers are HIP device memory (for
+ *     example the data pointer of a torch tensor on cuda:0); "host" pointers
+ *     are ordinary CPU memory.
+ *   - Ownership: the caller allocates and owns every input and output; the
+ *     library borrows them for the duration of the call (or, for enqueued
+ *     device work, until that work has completed on the context's stream).
+ *     The library owns only context-internal scratch, released by pdd_destroy.
+ *   - Asynchrony: device work is enqueued on the context's stream and the call
+ *     returns; results are valid after pdd_sync or after the caller
+ *     synchronises that stream.  pdd_solve is the exception: it reads back
+ *     convergence scalars and therefore returns after the solve has finished.
+ *   - Errors: host-side validation fails fast with PDD_EINVAL before touching
+ *     any output; HIP failures give PDD_EDEVICE (asynchronous kernel faults
+ *     surface at the next synchronising call).  pdd_last_error returns a
+ *     message for the last non-OK status of a context.  Nothing is printed
+ *     and no exception or abort crosses the ABI.
+ *   - Threads: a context may be used by one host thread at a time.
+ */
+#ifndef PDD_H
+#define PDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pdd_status {
+  PDD_OK = 0,
+  PDD_EINVAL = 1,        /* invalid argument (nothing was written) */
+  PDD_ENOMEM = 2,        /* device or host allocation failed */
+  PDD_EDEVICE = 3,       /* a HIP runtime call or kernel failed */
+  PDD_ENOTCONV = 4,      /* iterative solve stopped before the tolerance */
+  PDD_EUNSUPPORTED = 5   /* combination of options not implemented */
+} pdd_status;
+
+typedef struct pdd_ctx pdd_ctx;
+
+/* ---- problem description ------------------------------------------------ */
+
+/* Coefficient families of problem (6) (Sec. 2.2): the diffusion sigma (taken
+ * symmetric, A = sigma sigma^T as in eq. 7), drift d, reaction c <= 0, source
+ * f and Dirichlet datum g.
+ *   POISSON    sigma = sqrt(2) I, d = 0, c = 0, u* = sin(pi x) sin(pi y) + x^2 y,
+ *              f = Laplacian of u*, g = u*
+ *   VARCOEF    sigma = diag(sqrt(2 + sin 2 pi x), sqrt(2 + cos 2 pi y)),
+ *              d = (sin 2 pi y, cos 2 pi x), c = -(1 + x^2), u* = e^x cos 2y,
+ *              f = L u*, g = u*
+ *   AMPLITUDE  sigma = diag(sqrt(2 (1 + a sin 2 pi x)), sqrt(2 (1 + a cos 2 pi y))),
+ *              a = param[0] in [0, 1), d = 0, c = 0, u* as POISSON, f = L u*
+ *   LUT        the seven fields (sxx, sxy, syy, dx, dy, c, f) read by bilinear
+ *              interpolation from a float32 table on an lut_n x lut_n grid of
+ *              nodes spanning the partition's domain, node (i, j) at
+ *              (x0 + i (x1-x0)/(lut_n-1), y0 + j (y1-y0)/(lut_n-1)); layout
+ *              lut[(j * lut_n + i) * PDD_LUT_STRIDE + field], device pointer;
+ *              g = u* of POISSON
+ *   CONSTSOL   sigma, d, c of VARCOEF, f = c, g = 1 (u = 1 is the solution)
+ *   EXITTIME   sigma = sqrt(2) I, d = 0, c = 0, f = -1, g = 0 (u = mean exit
+ *              time, eq. 26) */
+enum {
+  PDD_COEF_POISSON = 0,
+  PDD_COEF_VARCOEF = 1,
+  PDD_COEF_AMPLITUDE = 2,
+  PDD_COEF_LUT = 3,
+  PDD_COEF_CONSTSOL = 4,
+  PDD_COEF_EXITTIME = 5
+};
+enum { PDD_LUT_STRIDE = 8 };
+
+typedef struct pdd_coeffs {
+  int32_t kind;          /* PDD_COEF_* */
+  int32_t lut_n;         /* LUT nodes per direction (>= 2), LUT kind only */
+  double param[4];       /* family parameters (AMPLITUDE: param[0] = a) */
+  const float* lut;      /* device, LUT kind only */
+} pdd_coeffs;
+
+/* Omega = [x0, x1] x [y0, y1] cut into H x H subdomains (eq. 12). */
+typedef struct pdd_partition {
+  double x0, x1, y0, y1;
+  int32_t H;             /* >= 2 */
+  int32_t _pad;
+} pdd_partition;
+
+/* Knots (Sec. 3.1): m lattice intervals per subdomain side, so the knot
+ * spacing is (x1 - x0) / (H m); knots are the lattice points inside Omega on
+ * grid lines, crossings included.  Unknowns are numbered in lexicographic
+ * (y, x) order.  Each interface side's stencil (eq. 17) is its line's knots
+ * within the side widened by ext lattice units at both ends, clipped to the
+ * domain (Sec. 5.1 widens by half a segment; Sec. 3.3 beyond corners). */
+typedef struct pdd_knots {
+  int32_t m;             /* >= 1 */
+  int32_t ext;           /* >= 0 */
+} pdd_knots;
+
+/* ---- run options --------------------------------------------------------- */
+
+enum {
+  PDD_FP64_SAME_STREAM = 0,  /* float64 paths: matches the CPU definition to rounding */
+  PDD_FP32_PRODUCTION = 1    /* float32 paths, float64 accumulation of G and b */
+};
+enum {
+  PDD_EXIT_NAIVE = 0,        /* exit when strictly outside the closed patch (Sec. 2.3) */
+  PDD_EXIT_GM = 1            /* Gobet-Menozzi inward shift 0.5826 sqrt(a_nn h) (Sec. 2.3) */
+};
+enum {
+  PDD_CV_NONE = 0,
+  PDD_CV_NETWORK = 1,        /* grad v of the 2-64-64-1 tanh network at every step */
+  PDD_CV_GRAD_LUT = 2        /* grad v baked into a float32 table, bilinear read */
+};
+enum { PDD_DIAG_WIDTH = 8 };   /* per knot: sum K, N, exits E/N/W/S, sum s, sum s^2 */
+enum { PDD_DUMP_WIDTH = 8 };   /* per dumped path: K, x_K, y_K, Y_K, Z_K, Xi_K, side, t */
+enum { PDD_MLP_WIDTH = 64, PDD_MLP_PARAMS = 4417 };
+
+/* Control variate of eqs. (37)-(38): Xi accumulates -Y (sigma^T grad v) . dW
+ * and is added to b only; the mean of the estimator is unchanged for any v.
+ * NETWORK: params = float32[PDD_MLP_PARAMS] laid out W1[64][2], b1[64],
+ * W2[64][64] (out, in), b2[64], w3[64], b3 (device).
+ * GRAD_LUT: grad_lut = float32 [lut_n][lut_n][2] node-centred over the domain
+ * (device). */
+typedef struct pdd_cv {
+  int32_t mode;              /* PDD_CV_* */
+  int32_t lut_n;
+  const float* params;
+  const float* grad_lut;
+} pdd_cv;
+
+typedef struct pdd_run {
+  uint64_t seed;                   /* Philox key = (seed lo 32 bits, seed hi 32 bits) */
+  uint32_t instance;               /* fourth Philox counter word */
+  int32_t precision;               /* PDD_FP64_SAME_STREAM | PDD_FP32_PRODUCTION */
+  int32_t exit_rule;               /* PDD_EXIT_NAIVE | PDD_EXIT_GM */
+  int32_t dump_paths;              /* >0: record the first dump_paths paths of every knot */
+  int64_t n_paths;                 /* paths per knot when n_paths_per_knot is NULL */
+  const int32_t* n_paths_per_knot; /* host, length n, entries >= 1; nullable */
+  double h;                        /* Euler-Maruyama time step, > 0 */
+  const pdd_cv* cv;                /* nullable: plain estimator */
+  const double* u_ref;             /* device, length n, nullable: knot values used in
+                                      the per-path score diagnostics (sum s, sum s^2) */
+  double* dump;                    /* device, n * dump_paths * PDD_DUMP_WIDTH, when dump_paths > 0 */
+} pdd_run;
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the null stream).  *ctx receives the handle. */
+pdd_status pdd_create(pdd_ctx** ctx, int32_t device, void* stream);
+void pdd_destroy(pdd_ctx* ctx);
+pdd_status pdd_set_stream(pdd_ctx* ctx, void* stream);
+/* Block until all work enqueued on the context's stream has finished. */
+pdd_status pdd_sync(pdd_ctx* ctx);
+/* Message of the last non-OK status of ctx (ctx may be NULL for failures of
+ * calls that take no context); never NULL, valid until the next call. */
+const char* pdd_last_error(const pdd_ctx* ctx);
+
+/* ---- discretisation (host only, no device work) -------------------------- */
+
+/* Sizes of the system and, when row_ptr/col_idx are non-NULL, its sparsity
+ * pattern: row k holds column k and the stencil of every interface side of
+ * knot k's patch (support of eq. 24), ascending, structural zeros kept.
+ * row_ptr: host int32[n + 1]; col_idx: host int32[nnz]. */
+pdd_status pdd_pattern(const pdd_partition* part, const pdd_knots* knots,
+                       int64_t* n, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx);
+
+/* Knot coordinates in canonical order: xy = host double[2 n] (x0, y0, x1, y1, ...). */
+pdd_status pdd_knot_xy(const pdd_partition* part, const pdd_knots* knots, double* xy);
+
+/* ---- assembly (eqs. 20-25) ------------------------------------------------ */
+
+/* Monte Carlo assembly of G (CSR) and b: for every knot k, N_k paths of the
+ * diffusion (9) start at x_k and are integrated by Euler-Maruyama until they
+ * first leave the knot's patch (eq. 15); the exit point is projected onto the
+ * closest tripped side line and linearly interpolated onto that line's knot
+ * lattice (eq. 21 with footnote 8's linear scheme).  Row k: G_kk = 1,
+ * G_kj = -mean(Y_K w_j), b_k = mean(Z_K + Xi_K + Y_K * boundary data reached).
+ * Random numbers: Philox4x32-10, counter = (draw j, path p, knot k, instance),
+ * draw j feeding steps 2j and 2j+1 through Box-Muller.
+ * Outputs (device): row_ptr int32[n+1], col_idx int32[nnz], val double[nnz],
+ * b double[n], diag double[n * PDD_DIAG_WIDTH] (nullable). */
+pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                        const pdd_knots* knots, const pdd_run* run,
+                        int32_t* row_ptr, int32_t* col_idx, double* val, double* b,
+                        double* diag);
+
+/* ---- launch control and measurement ------------------------------------ */
+
+/* Override the assembly launch shape (0 = automatic): threads per block (a
+ * multiple of 64, at most 256), workgroups in the persistent grid, and paths
+ * per ticket (the unit a wave takes from the work list).  Results do not
+ * depend on these except through float64 summation order. */
+pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket);
+/* Shape of the last assembly launch: grid, block and number of tickets. */
+pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets);
+/* enable != 0: bracket every assembly kernel launched from now on with a pair
+ * of HIP events on the context's stream (up to 4096 launches; the list is
+ * cleared by every call of pdd_set_timing).  pdd_kernel_ms waits for the
+ * recorded launches and returns the summed kernel time in milliseconds and
+ * the number of launches timed. */
+pdd_status pdd_set_timing(pdd_ctx* ctx, int32_t enable);
+pdd_status pdd_kernel_ms(pdd_ctx* ctx, double* total_ms, int32_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDD_H */

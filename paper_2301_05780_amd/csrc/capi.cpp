@@ -1,0 +1,256 @@
+// C ABI of libpdd: context, validation, geometry/ticket caches and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "context.h"
+#include "geometry.h"
+#include "kernels.h"
+
+using namespace pdd;
+
+namespace {
+
+thread_local std::string g_err;   // message of calls that have no context
+
+pdd_status fail(pdd_ctx* ctx, pdd_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg; else g_err = msg;
+  return st;
+}
+
+bool same_part(const pdd_partition& a, const pdd_partition& b) {
+  return a.x0 == b.x0 && a.x1 == b.x1 && a.y0 == b.y0 && a.y1 == b.y1 && a.H == b.H;
+}
+
+}  // namespace
+
+namespace pdd {
+
+DeviceBuffer::~DeviceBuffer() { release(); }
+void DeviceBuffer::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+hipError_t DeviceBuffer::reserve(size_t want) {
+  if (want <= bytes) return hipSuccess;
+  release();
+  hipError_t e = hipMalloc(&ptr, want);
+  if (e != hipSuccess) { ptr = nullptr; return e; }
+  bytes = want;
+  return hipSuccess;
+}
+
+pdd_status check_hip(pdd_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return PDD_OK;
+  ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+  return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PDD_ENOMEM : PDD_EDEVICE;
+}
+
+// Geometry of (part, knots), built on the host once and uploaded.
+pdd_status get_geometry(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn, GeoCache** out) {
+  for (auto& gc : ctx->geo) {
+    if (same_part(gc->part, part) && gc->kn.m == kn.m && gc->kn.ext == kn.ext) {
+      *out = gc.get();
+      return PDD_OK;
+    }
+  }
+  auto gc = std::make_unique<GeoCache>();
+  gc->part = part;
+  gc->kn = kn;
+  std::string err;
+  pdd_status st = build_geometry(part, kn, gc->g, err);
+  if (st != PDD_OK) return fail(ctx, st, err);
+  const Geometry& g = gc->g;
+  if ((int64_t)g.slot_len * 4 + EX_COUNT > 8000)
+    return fail(ctx, PDD_EUNSUPPORTED, "stencils too long for the LDS tally row (reduce m or ext)");
+
+  std::vector<KnotDesc> desc(g.n);
+  std::vector<int32_t> ij(2 * g.n);
+  for (int64_t k = 0; k < g.n; ++k) {
+    KnotDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.sx = g.x0 + (double)g.ix[k] * g.dx;
+    d.sy = g.y0 + (double)g.iy[k] * g.dy;
+    d.bmask = 0;
+    for (int o = 0; o < 4; ++o) {
+      SideInfo s = g.side(k, o);
+      d.line[o] = s.vertical ? g.x0 + (double)s.at * g.dx : g.y0 + (double)s.at * g.dy;
+      d.at[o] = s.at;
+      d.clo[o] = s.clo;
+      d.chi[o] = s.chi;
+      if (s.boundary) d.bmask |= 1 << o;
+    }
+    d.knot = (int32_t)k;
+    desc[k] = d;
+    ij[2 * k] = g.ix[k];
+    ij[2 * k + 1] = g.iy[k];
+  }
+  hipError_t e;
+  if ((e = gc->desc.reserve(desc.size() * sizeof(KnotDesc))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(desc)");
+  if ((e = gc->knot_ij.reserve(ij.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(knot_ij)");
+  if ((e = gc->row_ptr.reserve(g.row_ptr.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(row_ptr)");
+  if ((e = gc->col_idx.reserve(std::max<size_t>(1, g.col_idx.size()) * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(col_idx)");
+  // synchronous uploads: the host vectors die at the end of this function
+  if ((e = hipMemcpy(gc->desc.ptr, desc.data(), desc.size() * sizeof(KnotDesc), hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload desc");
+  if ((e = hipMemcpy(gc->knot_ij.ptr, ij.data(), ij.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload knot_ij");
+  if ((e = hipMemcpy(gc->row_ptr.ptr, g.row_ptr.data(), g.row_ptr.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload row_ptr");
+  if (!g.col_idx.empty() && (e = hipMemcpy(gc->col_idx.ptr, g.col_idx.data(), g.col_idx.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload col_idx");
+  if (ctx->geo.size() >= 8) ctx->geo.erase(ctx->geo.begin());
+  ctx->geo.push_back(std::move(gc));
+  *out = ctx->geo.back().get();
+  return PDD_OK;
+}
+
+pdd_status get_lattice(pdd_ctx* ctx, GeoCache* gc) {
+  if (gc->lattice.ptr) return PDD_OK;
+  hipError_t e = gc->lattice.reserve(gc->g.index.size() * 4);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipMalloc(lattice)");
+  e = hipMemcpy(gc->lattice.ptr, gc->g.index.data(), gc->g.index.size() * 4, hipMemcpyHostToDevice);
+  return check_hip(ctx, e, "upload lattice");
+}
+
+}  // namespace pdd
+
+extern "C" {
+
+pdd_status pdd_create(pdd_ctx** out, int32_t device, void* stream) {
+  if (!out) return fail(nullptr, PDD_EINVAL, "pdd_create: null output pointer");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) return fail(nullptr, PDD_EDEVICE, "pdd_create: no HIP device");
+  if (device < 0 || device >= count) return fail(nullptr, PDD_EINVAL, "pdd_create: device index out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, PDD_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return fail(nullptr, PDD_EDEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+  pdd_ctx* ctx = new (std::nothrow) pdd_ctx();
+  if (!ctx) return fail(nullptr, PDD_ENOMEM, "pdd_create: out of host memory");
+  ctx->device = device;
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  ctx->cu_count = prop.multiProcessorCount;
+  ctx->arch = prop.gcnArchName;
+  *out = ctx;
+  return PDD_OK;
+}
+
+void pdd_destroy(pdd_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+pdd_status pdd_set_stream(pdd_ctx* ctx, void* stream) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_stream: null context");
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  return PDD_OK;
+}
+
+pdd_status pdd_sync(pdd_ctx* ctx) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_sync: null context");
+  return check_hip(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+}
+
+const char* pdd_last_error(const pdd_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+pdd_status pdd_pattern(const pdd_partition* part, const pdd_knots* knots, int64_t* n, int64_t* nnz,
+                       int32_t* row_ptr, int32_t* col_idx) {
+  if (!part || !knots || !n || !nnz) return fail(nullptr, PDD_EINVAL, "pdd_pattern: null argument");
+  Geometry g;
+  std::string err;
+  pdd_status st = build_geometry(*part, *knots, g, err);
+  if (st != PDD_OK) return fail(nullptr, st, err);
+  *n = g.n;
+  *nnz = g.nnz;
+  if (row_ptr) std::copy(g.row_ptr.begin(), g.row_ptr.end(), row_ptr);
+  if (col_idx) std::copy(g.col_idx.begin(), g.col_idx.end(), col_idx);
+  return PDD_OK;
+}
+
+pdd_status pdd_knot_xy(const pdd_partition* part, const pdd_knots* knots, double* xy) {
+  if (!part || !knots || !xy) return fail(nullptr, PDD_EINVAL, "pdd_knot_xy: null argument");
+  Geometry g;
+  std::string err;
+  pdd_status st = build_geometry(*part, *knots, g, err, false);
+  if (st != PDD_OK) return fail(nullptr, st, err);
+  for (int64_t k = 0; k < g.n; ++k) {
+    xy[2 * k] = g.x0 + (double)g.ix[k] * g.dx;
+    xy[2 * k + 1] = g.y0 + (double)g.iy[k] * g.dy;
+  }
+  return PDD_OK;
+}
+
+pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                        const pdd_knots* knots, const pdd_run* run, int32_t* row_ptr,
+                        int32_t* col_idx, double* val, double* b, double* diag) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_assemble: null context");
+  if (!coeffs || !part || !knots || !run) return fail(ctx, PDD_EINVAL, "pdd_assemble: null argument");
+  if (!row_ptr || !col_idx || !val || !b) return fail(ctx, PDD_EINVAL, "pdd_assemble: null output");
+  pdd_status st = validate_run(ctx, *coeffs, *run);
+  if (st != PDD_OK) return st;
+  AssembleJob job;
+  job.coeffs = *coeffs;
+  job.part = *part;
+  job.knots = *knots;
+  job.run = *run;
+  job.row_ptr = row_ptr;
+  job.col_idx = col_idx;
+  job.val = val;
+  job.b = b;
+  job.diag = diag;
+  return run_assemble(ctx, job);
+}
+
+pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_launch: null context");
+  if (block < 0 || block > 256 || block % 64 != 0 || grid < 0 || paths_per_ticket < 0)
+    return fail(ctx, PDD_EINVAL, "pdd_set_launch: block must be 0 or a multiple of 64 up to 256; grid, paths_per_ticket >= 0");
+  ctx->force_block = block;
+  ctx->force_grid = grid;
+  ctx->force_per_ticket = paths_per_ticket;
+  return PDD_OK;
+}
+
+pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets) {
+  if (!ctx || !grid || !block || !tickets) return fail(nullptr, PDD_EINVAL, "pdd_last_launch: null argument");
+  *grid = ctx->last_grid;
+  *block = ctx->last_block;
+  *tickets = ctx->last_tickets;
+  return PDD_OK;
+}
+
+pdd_status pdd_set_timing(pdd_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_timing: null context");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  return PDD_OK;
+}
+
+pdd_status pdd_kernel_ms(pdd_ctx* ctx, double* total_ms, int32_t* launches) {
+  if (!ctx || !total_ms || !launches) return fail(ctx, PDD_EINVAL, "pdd_kernel_ms: null argument");
+  double sum = 0.0;
+  for (int i = 0; i < ctx->ev_used; ++i) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(ctx->ev_pool[2 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->ev_pool[2 * i], ctx->ev_pool[2 * i + 1]);
+    if (e != hipSuccess) return check_hip(ctx, e, "hipEventElapsedTime");
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = ctx->ev_used;
+  return PDD_OK;
+}
+
+}  // extern "C"

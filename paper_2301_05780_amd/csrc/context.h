@@ -1,0 +1,92 @@
+// Library context: device, stream, caches and scratch owned by one pdd_ctx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "geometry.h"
+#include "kernels.h"
+#include "pdd.h"
+
+namespace pdd {
+
+// Owning device allocation that only grows.
+struct DeviceBuffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DeviceBuffer() = default;
+  DeviceBuffer(const DeviceBuffer&) = delete;
+  DeviceBuffer& operator=(const DeviceBuffer&) = delete;
+  ~DeviceBuffer();
+  hipError_t reserve(size_t want);
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Host geometry of one (partition, knots) pair and its device copies.
+struct GeoCache {
+  pdd_partition part{};
+  pdd_knots kn{};
+  Geometry g;
+  DeviceBuffer desc, knot_ij, row_ptr, col_idx, lattice;
+};
+
+// Tickets of one (geometry, path counts, ticket size) combination.
+struct TicketCache {
+  const GeoCache* geo = nullptr;
+  std::vector<int32_t> npk;       // paths per knot
+  int32_t per_ticket = 0;
+  uint32_t inst = 0;
+  int64_t n_tickets = 0;
+  DeviceBuffer tickets, ticket_begin, n_paths;
+};
+
+struct AssembleJob {
+  pdd_coeffs coeffs;
+  pdd_partition part;
+  pdd_knots knots;
+  pdd_run run;
+  int32_t* row_ptr;
+  int32_t* col_idx;
+  double* val;
+  double* b;
+  double* diag;
+};
+
+}  // namespace pdd
+
+struct pdd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cu_count = 0;
+  std::string arch;
+  std::string err;
+  std::vector<std::unique_ptr<pdd::GeoCache>> geo;
+  std::unique_ptr<pdd::TicketCache> tickets;
+  pdd::DeviceBuffer partial;
+  // launch overrides (0 = automatic), set by the tuner
+  int force_block = 0, force_grid = 0, force_per_ticket = 0;
+  // shape of the last assembly launch (reported by pdd_last_launch)
+  int last_grid = 0, last_block = 0;
+  int64_t last_tickets = 0;
+  // optional event pairs around the assembly kernels
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;   // 2 per timed launch, reused
+  int ev_used = 0;                   // pairs recorded since pdd_set_timing
+  ~pdd_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace pdd {
+
+pdd_status check_hip(pdd_ctx* ctx, hipError_t e, const char* what);
+pdd_status get_geometry(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn, GeoCache** out);
+pdd_status get_lattice(pdd_ctx* ctx, GeoCache* gc);
+pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r);
+pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);
+
+}  // namespace pdd

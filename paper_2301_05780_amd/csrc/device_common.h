@@ -1,0 +1,239 @@
+// Device helpers of the assembly kernels: the Philox4x32-10 stream, the
+// uniform and Box-Muller maps, and the coefficient families of problem (6).
+//
+// Two numeric flavours share one code base:
+//   FP64 "same stream": float64 throughout, library transcendentals, FMA
+//     contraction switched off in the arithmetic that mirrors the CPU
+//     definition, so results agree with it to rounding;
+//   FP32 "production": float32 paths with the CDNA transcendental units
+//     (v_sin/v_cos take revolutions, v_log/v_exp are base 2, v_sqrt).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace pdd {
+
+constexpr double kPi = 3.141592653589793;
+constexpr double kGM = 0.5825971579390106;  // -zeta(1/2)/sqrt(2 pi), Gobet-Menozzi
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------
+// Round: (hi0, lo0) = M0 c0, (hi1, lo1) = M1 c2 as full 64-bit products;
+// c <- (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); key bumped by the Weyl
+// constants between rounds.
+struct U4 { uint32_t a, b, c, d; };
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// ---- uniforms ---------------------------------------------------------------
+// float64: u = (r + 1/2) 2^-32, exact, in (0, 1).
+__device__ __forceinline__ double uniform64(uint32_t r) {
+  return ((double)r + 0.5) * 0x1p-32;
+}
+// float32: the top 23 bits, u = (2 (r >> 9) + 1) 2^-24, exact, in (0, 1).
+__device__ __forceinline__ float uniform32(uint32_t r) {
+  return (float)(((r >> 9) << 1) | 1u) * 0x1p-24f;
+}
+
+// ---- CDNA transcendental units (float32) ------------------------------------
+__device__ __forceinline__ float sin_rev(float r) {   // sin(2 pi r)
+  return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(r));
+}
+__device__ __forceinline__ float cos_rev(float r) {   // cos(2 pi r)
+  return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(r));
+}
+__device__ __forceinline__ float fsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ float fexp(float v) { return __builtin_amdgcn_exp2f(v * 1.4426950408889634f); }
+__device__ __forceinline__ float flog2(float v) { return __builtin_amdgcn_logf(v); }
+
+// Box-Muller: two N(0,1) from two uniforms, rho = sqrt(-2 ln u0), theta = 2 pi u1.
+__device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
+  const float rho = fsqrt(-1.3862943611198906f * flog2(u0));   // -2 ln 2 log2(u0)
+  z0 = rho * cos_rev(u1);
+  z1 = rho * sin_rev(u1);
+}
+__device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
+#pragma clang fp contract(off)
+  const double rho = sqrt(-2.0 * log(u0));
+  const double th = 2.0 * kPi * u1;
+  z0 = rho * cos(th);
+  z1 = rho * sin(th);
+}
+
+// ---- coefficients -----------------------------------------------------------
+template <typename R>
+struct Coef {
+  R sxx, sxy, syy, dx, dy, c, f;
+};
+
+// Bilinear read of the node-centred LUT (seven fields).  Position -> node
+// coordinate clamped to [0, n-1], cell index clamped to n-2.
+__device__ __forceinline__ void lut_fetch(const CoefParams& cp, double x, double y, Coef<double>& o) {
+#pragma clang fp contract(off)
+  const int n = cp.lut_n;
+  double fx = (x - cp.x0) / (cp.x1 - cp.x0) * (double)(n - 1);
+  double fy = (y - cp.y0) / (cp.y1 - cp.y0) * (double)(n - 1);
+  fx = fmin(fmax(fx, 0.0), (double)(n - 1));
+  fy = fmin(fmax(fy, 0.0), (double)(n - 1));
+  const int i = (int)fmin(floor(fx), (double)(n - 2));
+  const int j = (int)fmin(floor(fy), (double)(n - 2));
+  const double tx = fx - (double)i, ty = fy - (double)j;
+  const float* p00 = cp.lut + ((size_t)j * n + i) * PDD_LUT_STRIDE;
+  const float* p01 = p00 + (size_t)n * PDD_LUT_STRIDE;
+  double v[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const double v00 = p00[q], v10 = p00[PDD_LUT_STRIDE + q];
+    const double v01 = p01[q], v11 = p01[PDD_LUT_STRIDE + q];
+    v[q] = (1.0 - ty) * ((1.0 - tx) * v00 + tx * v10) + ty * ((1.0 - tx) * v01 + tx * v11);
+  }
+  o.sxx = v[0]; o.sxy = v[1]; o.syy = v[2]; o.dx = v[3]; o.dy = v[4]; o.c = v[5]; o.f = v[6];
+}
+
+__device__ __forceinline__ void lut_fetch(const CoefParams& cp, float x, float y, Coef<float>& o) {
+  const int n = cp.lut_n;
+  float fx = (x - (float)cp.x0) * cp.lut_sx;
+  float fy = (y - (float)cp.y0) * cp.lut_sy;
+  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
+  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  const int i = min((int)fx, n - 2);
+  const int j = min((int)fy, n - 2);
+  const float tx = fx - (float)i, ty = fy - (float)j;
+  const float4* p00 = reinterpret_cast<const float4*>(cp.lut + ((size_t)j * n + i) * PDD_LUT_STRIDE);
+  const float4* p01 = p00 + (size_t)n * (PDD_LUT_STRIDE / 4);
+  const float4 a0 = p00[0], a1 = p00[1], b0 = p00[2], b1 = p00[3];
+  const float4 c0 = p01[0], c1 = p01[1], d0 = p01[2], d1 = p01[3];
+  auto bl = [&](float v00, float v10, float v01, float v11) {
+    const float lo = v00 + tx * (v10 - v00);
+    const float hi = v01 + tx * (v11 - v01);
+    return lo + ty * (hi - lo);
+  };
+  o.sxx = bl(a0.x, b0.x, c0.x, d0.x);
+  o.sxy = bl(a0.y, b0.y, c0.y, d0.y);
+  o.syy = bl(a0.z, b0.z, c0.z, d0.z);
+  o.dx = bl(a0.w, b0.w, c0.w, d0.w);
+  o.dy = bl(a1.x, b1.x, c1.x, d1.x);
+  o.c = bl(a1.y, b1.y, c1.y, d1.y);
+  o.f = bl(a1.z, b1.z, c1.z, d1.z);
+}
+
+// Coefficients at (x, y).  float64 versions mirror the CPU definition's
+// expression order; float32 versions use the transcendental units.
+template <int KIND>
+__device__ __forceinline__ void coef_at(const CoefParams& cp, double x, double y, Coef<double>& o) {
+#pragma clang fp contract(off)
+  if constexpr (KIND == PDD_COEF_POISSON || KIND == PDD_COEF_EXITTIME) {
+    o.sxx = sqrt(2.0); o.sxy = 0.0; o.syy = sqrt(2.0);
+    o.dx = 0.0; o.dy = 0.0; o.c = 0.0;
+    if constexpr (KIND == PDD_COEF_POISSON)
+      o.f = -2.0 * kPi * kPi * sin(kPi * x) * sin(kPi * y) + 2.0 * y;
+    else
+      o.f = -1.0;
+  } else if constexpr (KIND == PDD_COEF_VARCOEF || KIND == PDD_COEF_CONSTSOL) {
+    const double s2px = sin(2.0 * kPi * x), c2px = cos(2.0 * kPi * x);
+    const double s2py = sin(2.0 * kPi * y), c2py = cos(2.0 * kPi * y);
+    o.sxx = sqrt(2.0 * (1.0 + 0.5 * s2px));
+    o.sxy = 0.0;
+    o.syy = sqrt(2.0 * (1.0 + 0.5 * c2py));
+    o.dx = s2py;
+    o.dy = c2px;
+    o.c = -(1.0 + x * x);
+    if constexpr (KIND == PDD_COEF_VARCOEF) {
+      const double ex = exp(x), c2y = cos(2.0 * y), s2y = sin(2.0 * y);
+      o.f = ex * ((1.0 + 0.5 * s2px) * c2y - 4.0 * (1.0 + 0.5 * c2py) * c2y + s2py * c2y -
+                  2.0 * c2px * s2y - (1.0 + x * x) * c2y);
+    } else {
+      o.f = -(1.0 + x * x);
+    }
+  } else if constexpr (KIND == PDD_COEF_AMPLITUDE) {
+    const double a = cp.a;
+    const double s2px = sin(2.0 * kPi * x), c2py = cos(2.0 * kPi * y);
+    o.sxx = sqrt(2.0 * (1.0 + a * s2px));
+    o.sxy = 0.0;
+    o.syy = sqrt(2.0 * (1.0 + a * c2py));
+    o.dx = 0.0; o.dy = 0.0; o.c = 0.0;
+    const double ss = sin(kPi * x) * sin(kPi * y);
+    o.f = (1.0 + a * s2px) * (-kPi * kPi * ss + 2.0 * y) + (1.0 + a * c2py) * (-kPi * kPi * ss);
+  } else {
+    lut_fetch(cp, x, y, o);
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ void coef_at(const CoefParams& cp, float x, float y, Coef<float>& o) {
+  constexpr float kPiF = 3.14159265358979f;
+  if constexpr (KIND == PDD_COEF_POISSON || KIND == PDD_COEF_EXITTIME) {
+    o.sxx = 1.41421356237f; o.sxy = 0.0f; o.syy = 1.41421356237f;
+    o.dx = 0.0f; o.dy = 0.0f; o.c = 0.0f;
+    if constexpr (KIND == PDD_COEF_POISSON)
+      o.f = -2.0f * kPiF * kPiF * sin_rev(0.5f * x) * sin_rev(0.5f * y) + 2.0f * y;
+    else
+      o.f = -1.0f;
+  } else if constexpr (KIND == PDD_COEF_VARCOEF || KIND == PDD_COEF_CONSTSOL) {
+    const float s2px = sin_rev(x), c2px = cos_rev(x);
+    const float s2py = sin_rev(y), c2py = cos_rev(y);
+    o.sxx = fsqrt(2.0f + s2px);
+    o.sxy = 0.0f;
+    o.syy = fsqrt(2.0f + c2py);
+    o.dx = s2py;
+    o.dy = c2px;
+    o.c = -(1.0f + x * x);
+    if constexpr (KIND == PDD_COEF_VARCOEF) {
+      const float r = y * 0.3183098861837907f;       // 2y in revolutions
+      const float ex = fexp(x), c2y = cos_rev(r), s2y = sin_rev(r);
+      o.f = ex * ((1.0f + 0.5f * s2px - 4.0f - 2.0f * c2py + s2py - 1.0f - x * x) * c2y -
+                  2.0f * c2px * s2y);
+    } else {
+      o.f = -(1.0f + x * x);
+    }
+  } else if constexpr (KIND == PDD_COEF_AMPLITUDE) {
+    const float a = (float)cp.a;
+    const float s2px = sin_rev(x), c2py = cos_rev(y);
+    const float ax = 1.0f + a * s2px, ay = 1.0f + a * c2py;
+    o.sxx = fsqrt(2.0f * ax);
+    o.sxy = 0.0f;
+    o.syy = fsqrt(2.0f * ay);
+    o.dx = 0.0f; o.dy = 0.0f; o.c = 0.0f;
+    const float ss = sin_rev(0.5f * x) * sin_rev(0.5f * y);
+    o.f = -kPiF * kPiF * ss * (ax + ay) + 2.0f * y * ax;
+  } else {
+    lut_fetch(cp, x, y, o);
+  }
+}
+
+// Dirichlet datum g at (x, y).
+template <int KIND>
+__device__ __forceinline__ double g_at(double x, double y) {
+#pragma clang fp contract(off)
+  if constexpr (KIND == PDD_COEF_VARCOEF) return exp(x) * cos(2.0 * y);
+  else if constexpr (KIND == PDD_COEF_CONSTSOL) return 1.0;
+  else if constexpr (KIND == PDD_COEF_EXITTIME) return 0.0;
+  else return sin(kPi * x) * sin(kPi * y) + x * x * y;
+}
+template <int KIND>
+__device__ __forceinline__ float g_at(float x, float y) {
+  if constexpr (KIND == PDD_COEF_VARCOEF) return fexp(x) * cos_rev(y * 0.3183098861837907f);
+  else if constexpr (KIND == PDD_COEF_CONSTSOL) return 1.0f;
+  else if constexpr (KIND == PDD_COEF_EXITTIME) return 0.0f;
+  else return sin_rev(0.5f * x) * sin_rev(0.5f * y) + x * x * y;
+}
+
+}  // namespace pdd

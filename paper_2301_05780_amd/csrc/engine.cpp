@@ -1,0 +1,210 @@
+// Host engine of the assembly: run validation, ticket construction, launch
+// shape, and the enqueue of the assembly and finalize kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "context.h"
+
+namespace pdd {
+
+namespace {
+
+pdd_status bad(pdd_ctx* ctx, pdd_status st, const char* msg) {
+  ctx->err = msg;
+  return st;
+}
+
+}  // namespace
+
+pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
+  if (c.kind < PDD_COEF_POISSON || c.kind > PDD_COEF_EXITTIME)
+    return bad(ctx, PDD_EINVAL, "coeffs.kind: unknown coefficient family");
+  if (c.kind == PDD_COEF_AMPLITUDE && !(c.param[0] >= 0.0 && c.param[0] < 1.0))
+    return bad(ctx, PDD_EINVAL, "coeffs.param[0]: amplitude must lie in [0, 1)");
+  if (c.kind == PDD_COEF_LUT && (!c.lut || c.lut_n < 2 || c.lut_n > 65536))
+    return bad(ctx, PDD_EINVAL, "coeffs: LUT kind needs a device table and 2 <= lut_n <= 65536");
+  if (r.precision != PDD_FP64_SAME_STREAM && r.precision != PDD_FP32_PRODUCTION)
+    return bad(ctx, PDD_EINVAL, "run.precision: unknown precision mode");
+  if (r.exit_rule != PDD_EXIT_NAIVE && r.exit_rule != PDD_EXIT_GM)
+    return bad(ctx, PDD_EINVAL, "run.exit_rule: unknown exit rule");
+  if (!(r.h > 0.0) || !std::isfinite(r.h)) return bad(ctx, PDD_EINVAL, "run.h: need a finite h > 0");
+  if (!r.n_paths_per_knot && (r.n_paths < 1 || r.n_paths > INT32_MAX))
+    return bad(ctx, PDD_EINVAL, "run.n_paths: need 1 <= n_paths <= 2^31 - 1");
+  if (r.dump_paths < 0 || (r.dump_paths > 0 && !r.dump))
+    return bad(ctx, PDD_EINVAL, "run.dump_paths: need dump_paths >= 0 and a dump buffer when > 0");
+  if (r.cv && r.cv->mode != PDD_CV_NONE)
+    return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variate not available in this entry point");
+  if (c.kind == PDD_COEF_LUT && r.exit_rule == PDD_EXIT_GM)
+    return bad(ctx, PDD_EUNSUPPORTED, "LUT coefficients with the Gobet-Menozzi rule are not implemented");
+  return PDD_OK;
+}
+
+pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  GeoCache* gc = nullptr;
+  pdd_status st = get_geometry(ctx, job.part, job.knots, &gc);
+  if (st != PDD_OK) return st;
+  const Geometry& g = gc->g;
+  const pdd_run& run = job.run;
+
+  // paths per knot
+  std::vector<int32_t> npk(g.n);
+  int64_t total = 0;
+  for (int64_t k = 0; k < g.n; ++k) {
+    const int64_t v = run.n_paths_per_knot ? run.n_paths_per_knot[k] : run.n_paths;
+    if (v < 1 || v > INT32_MAX) return bad(ctx, PDD_EINVAL, "run.n_paths_per_knot: entries must be >= 1");
+    npk[k] = (int32_t)v;
+    total += v;
+  }
+  if (run.u_ref) {
+    st = get_lattice(ctx, gc);
+    if (st != PDD_OK) return st;
+  }
+
+  // launch shape
+  const int slot_len = g.slot_len;
+  const int row_len = 4 * slot_len + EX_COUNT;
+  int block = ctx->force_block ? ctx->force_block : 256;
+  size_t lds = assemble_lds_bytes(row_len, block);
+  while (lds > 65536 && block > 64) {
+    block /= 2;
+    lds = assemble_lds_bytes(row_len, block);
+  }
+  if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
+  int per_cu = 0;
+  e = assemble_occupancy(run.precision, job.coeffs.kind, block, lds, &per_cu);
+  if (e != hipSuccess) return check_hip(ctx, e, "occupancy query");
+  per_cu = std::max(per_cu, 1);
+  int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
+  const int64_t waves = grid * (block / 64);
+
+  int64_t per_ticket = ctx->force_per_ticket;
+  if (per_ticket <= 0) per_ticket = std::max<int64_t>(256, (total + 4 * waves - 1) / (4 * waves));
+
+  // tickets (cached while geometry, path counts and ticket size repeat)
+  TicketCache* tc = ctx->tickets.get();
+  if (!tc || tc->geo != gc || tc->per_ticket != per_ticket || tc->npk != npk || tc->inst != run.instance) {
+    auto fresh = std::make_unique<TicketCache>();
+    fresh->geo = gc;
+    fresh->npk = npk;
+    fresh->per_ticket = (int32_t)per_ticket;
+    fresh->inst = run.instance;
+    std::vector<Ticket> tk;
+    std::vector<int32_t> tb(g.n + 1, 0);
+    for (int64_t k = 0; k < g.n; ++k) {
+      const int64_t N = npk[k];
+      const int64_t c = (N + per_ticket - 1) / per_ticket;
+      for (int64_t i = 0; i < c; ++i) {
+        Ticket t;
+        t.knot = (int32_t)k;
+        t.p0 = (int32_t)(N * i / c);
+        t.p1 = (int32_t)(N * (i + 1) / c);
+        t.inst = run.instance;
+        tk.push_back(t);
+      }
+      if ((int64_t)tk.size() > INT32_MAX) return bad(ctx, PDD_EUNSUPPORTED, "too many tickets");
+      tb[k + 1] = (int32_t)tk.size();
+    }
+    fresh->n_tickets = (int64_t)tk.size();
+    if ((e = fresh->tickets.reserve(tk.size() * sizeof(Ticket))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(tickets)");
+    if ((e = fresh->ticket_begin.reserve(tb.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(ticket_begin)");
+    if ((e = fresh->n_paths.reserve(npk.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(n_paths)");
+    // the stream may still read the previous cache's arrays
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(fresh->tickets.ptr, tk.data(), tk.size() * sizeof(Ticket), hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload tickets");
+    if ((e = hipMemcpy(fresh->ticket_begin.ptr, tb.data(), tb.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload ticket_begin");
+    if ((e = hipMemcpy(fresh->n_paths.ptr, npk.data(), npk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload n_paths");
+    ctx->tickets = std::move(fresh);
+    tc = ctx->tickets.get();
+  }
+  const int64_t need_waves = tc->n_tickets;
+  grid = std::min<int64_t>(grid, (need_waves + block / 64 - 1) / (block / 64));
+  grid = std::max<int64_t>(grid, 1);
+
+  const size_t partial_bytes = (size_t)tc->n_tickets * row_len * sizeof(double);
+  if (partial_bytes > ctx->partial.bytes) {
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    if ((e = ctx->partial.reserve(partial_bytes)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(partial)");
+  }
+
+  // pattern into the caller's arrays
+  if ((e = hipMemcpyAsync(job.row_ptr, gc->row_ptr.ptr, (g.n + 1) * 4, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess)
+    return check_hip(ctx, e, "copy row_ptr");
+  if (g.nnz > 0 && (e = hipMemcpyAsync(job.col_idx, gc->col_idx.ptr, g.nnz * 4, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess)
+    return check_hip(ctx, e, "copy col_idx");
+
+  AsmParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.desc = gc->desc.as<KnotDesc>();
+  P.tickets = tc->tickets.as<Ticket>();
+  P.n_tickets = (int32_t)tc->n_tickets;
+  P.row_len = row_len;
+  P.slot_len = slot_len;
+  P.L = g.L;
+  P.partial = ctx->partial.as<double>();
+  P.key0 = (uint32_t)(run.seed & 0xFFFFFFFFu);
+  P.key1 = (uint32_t)(run.seed >> 32);
+  P.exit_rule = run.exit_rule;
+  P.dump_paths = run.dump_paths;
+  P.h = run.h;
+  P.sqrt_h = std::sqrt(run.h);
+  P.x0 = g.x0; P.x1 = g.x1; P.y0 = g.y0; P.y1 = g.y1; P.dx = g.dx; P.dy = g.dy;
+  P.coef.kind = job.coeffs.kind;
+  P.coef.lut_n = job.coeffs.lut_n;
+  P.coef.a = job.coeffs.param[0];
+  P.coef.lut = job.coeffs.lut;
+  P.coef.x0 = g.x0; P.coef.x1 = g.x1; P.coef.y0 = g.y0; P.coef.y1 = g.y1;
+  if (job.coeffs.kind == PDD_COEF_LUT) {
+    P.coef.lut_sx = (float)((job.coeffs.lut_n - 1) / (g.x1 - g.x0));
+    P.coef.lut_sy = (float)((job.coeffs.lut_n - 1) / (g.y1 - g.y0));
+  }
+  P.u_ref = run.u_ref;
+  P.lattice = gc->lattice.as<int32_t>();
+  P.dump = run.dump_paths > 0 ? run.dump : nullptr;
+  P.max_steps = 1u << 24;
+
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (ctx->timing && ctx->ev_used < 4096) {
+    while ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {
+      hipEvent_t ev;
+      if ((e = hipEventCreate(&ev)) != hipSuccess) return check_hip(ctx, e, "hipEventCreate");
+      ctx->ev_pool.push_back(ev);
+    }
+    t0 = ctx->ev_pool[2 * ctx->ev_used];
+    t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
+    if ((e = hipEventRecord(t0, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
+  }
+  e = launch_assemble(P, run.precision, (int)grid, block, lds, ctx->stream);
+  if (e != hipSuccess) return check_hip(ctx, e, "launch assemble");
+  if (t1) {
+    if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
+    ctx->ev_used += 1;
+  }
+
+  FinalizeParams F;
+  F.partial = P.partial;
+  F.ticket_begin = tc->ticket_begin.as<int32_t>();
+  F.desc = P.desc;
+  F.knot_ij = gc->knot_ij.as<int32_t>();
+  F.row_ptr = gc->row_ptr.as<int32_t>();
+  F.col_idx = gc->col_idx.as<int32_t>();
+  F.n_paths = tc->n_paths.as<int32_t>();
+  F.row_len = row_len;
+  F.slot_len = slot_len;
+  F.n = g.n;
+  F.val = job.val;
+  F.b = job.b;
+  F.diag = job.diag;
+  e = launch_finalize(F, ctx->stream);
+  if (e != hipSuccess) return check_hip(ctx, e, "launch finalize");
+  ctx->last_grid = (int)grid;
+  ctx->last_block = block;
+  ctx->last_tickets = tc->n_tickets;
+  return PDD_OK;
+}
+
+}  // namespace pdd

@@ -1,0 +1,87 @@
+// Parameter blocks shared by the host engine and the HIP kernels, and the
+// host-callable launchers.  Plain structs only; no torch types anywhere.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "pdd.h"
+
+namespace pdd {
+
+// Per-knot descriptor read by the assembly kernels (one per unknown).
+struct KnotDesc {
+  double sx, sy;          // start point x_k
+  double line[4];         // physical coordinate of the line of side E, N, W, S
+  int32_t at[4];          // lattice coordinate of the line of side E, N, W, S
+  int32_t clo[4], chi[4]; // clamp range of each side along its line (lattice units)
+  int32_t bmask;          // bit o set: side o lies on the domain boundary
+  int32_t knot;           // canonical index
+  int32_t pad[6];
+};
+static_assert(sizeof(KnotDesc) == 128, "KnotDesc must stay 128 bytes");
+
+// A unit of work: paths [p0, p1) of one knot of one instance.
+struct Ticket {
+  int32_t knot;
+  int32_t p0, p1;
+  uint32_t inst;
+};
+
+struct CoefParams {
+  int32_t kind;
+  int32_t lut_n;
+  double a;                   // AMPLITUDE parameter
+  const float* lut;           // LUT kind
+  double x0, x1, y0, y1;      // domain (LUT node grid spans it)
+  float lut_sx, lut_sy;       // (n-1)/(x1-x0), (n-1)/(y1-y0)
+};
+
+struct AsmParams {
+  const KnotDesc* desc;
+  const Ticket* tickets;
+  int32_t n_tickets;
+  int32_t row_len;            // doubles per partial row: 4 slot_len + 8
+  int32_t slot_len;           // G slots per side
+  int32_t L;                  // lattice intervals per direction
+  double* partial;            // n_tickets * row_len
+  uint32_t key0, key1;
+  int32_t exit_rule;
+  int32_t dump_paths;
+  double h, sqrt_h;
+  double x0, x1, y0, y1, dx, dy;
+  CoefParams coef;
+  const double* u_ref;        // nullable
+  const int32_t* lattice;     // (L+1)^2 lattice -> knot index (for u_ref)
+  double* dump;               // nullable
+  uint32_t max_steps;         // safety cap on the steps of one path
+};
+
+// Extras stored after the 4 slot_len G slots of a partial row.
+enum { EX_B = 0, EX_S = 1, EX_S2 = 2, EX_K = 3, EX_E = 4, EX_N = 5, EX_W = 6, EX_S_SIDE = 7, EX_COUNT = 8 };
+
+struct FinalizeParams {
+  const double* partial;
+  const int32_t* ticket_begin;   // n + 1, tickets of knot k are [tb[k], tb[k+1])
+  const KnotDesc* desc;
+  const int32_t* knot_ij;        // 2 per knot: lattice ix, iy
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const int32_t* n_paths;        // per knot
+  int32_t row_len, slot_len;
+  int64_t n;
+  double* val;
+  double* b;
+  double* diag;                  // nullable
+};
+
+// Launchers (defined in assemble.hip).  Return hipSuccess or the launch error.
+hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block,
+                           size_t lds_bytes, hipStream_t stream);
+hipError_t launch_finalize(const FinalizeParams& p, hipStream_t stream);
+// Dynamic LDS bytes per workgroup for a given row length and block size.
+size_t assemble_lds_bytes(int row_len, int block);
+// Kernel attribute query for occupancy-based grid sizing.
+hipError_t assemble_occupancy(int precision, int kind, int block, size_t lds_bytes, int* blocks_per_cu);
+
+}  // namespace pdd

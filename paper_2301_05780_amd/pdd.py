@@ -1,0 +1,229 @@
+"""Thin ctypes binding of libpdd (include/pdd.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts Python
+values and torch tensors into the C structures and device pointers of the
+ABI and raises ``PddError`` on any non-OK status.  There is no fallback:
+if libpdd.so is missing the import of the library fails loudly.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EUNSUPPORTED = range(6)
+KIND = {"poisson": 0, "varcoef": 1, "amplitude": 2, "lut": 3, "constsol": 4, "exittime": 5}
+PRECISION = {"fp64": 0, "fp32": 1}
+EXIT = {"naive": 0, "gm": 1}
+CV_MODE = {"none": 0, "network": 1, "grad_lut": 2}
+DIAG_WIDTH = 8
+DUMP_WIDTH = 8
+MLP_PARAMS = 4417
+
+
+class PddError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pdd status {status}: {msg}")
+        self.status = status
+
+
+class Coeffs(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("lut_n", C.c_int32), ("param", C.c_double * 4),
+                ("lut", C.c_void_p)]
+
+
+class Partition(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("H", C.c_int32), ("_pad", C.c_int32)]
+
+
+class Knots(C.Structure):
+    _fields_ = [("m", C.c_int32), ("ext", C.c_int32)]
+
+
+class CV(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("lut_n", C.c_int32), ("params", C.c_void_p),
+                ("grad_lut", C.c_void_p)]
+
+
+class Run(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32), ("precision", C.c_int32),
+                ("exit_rule", C.c_int32), ("dump_paths", C.c_int32), ("n_paths", C.c_int64),
+                ("n_paths_per_knot", C.c_void_p), ("h", C.c_double), ("cv", C.c_void_p),
+                ("u_ref", C.c_void_p), ("dump", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpdd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2301_05780_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "pdd_create": [C.POINTER(vp), i32, vp],
+            "pdd_destroy": [vp],
+            "pdd_set_stream": [vp, vp],
+            "pdd_sync": [vp],
+            "pdd_last_error": [vp],
+            "pdd_pattern": [C.POINTER(Partition), C.POINTER(Knots), C.POINTER(i64), C.POINTER(i64), vp, vp],
+            "pdd_knot_xy": [C.POINTER(Partition), C.POINTER(Knots), vp],
+            "pdd_assemble": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots),
+                             C.POINTER(Run), vp, vp, vp, vp, vp],
+            "pdd_set_launch": [vp, i32, i32, i32],
+            "pdd_last_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)],
+            "pdd_set_timing": [vp, i32],
+            "pdd_kernel_ms": [vp, C.POINTER(f64), C.POINTER(i32)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None if name == "pdd_destroy" else (C.c_char_p if name == "pdd_last_error" else C.c_int)
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    """Device (or host) data pointer of a tensor / array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _check(status, ctx=None):
+    if status != OK:
+        msg = lib().pdd_last_error(ctx)
+        raise PddError(status, msg.decode() if msg else "")
+
+
+def partition_of(w):
+    x0, x1, y0, y1 = w["domain"]
+    return Partition(x0, x1, y0, y1, int(w["H"]), 0)
+
+
+def knots_of(w):
+    return Knots(int(w["m"]), int(w["ext"]))
+
+
+def pattern(w):
+    """(n, nnz, row_ptr, col_idx) of the workload's system, computed on the host."""
+    part, kn = partition_of(w), knots_of(w)
+    n, nnz = C.c_int64(), C.c_int64()
+    _check(lib().pdd_pattern(C.byref(part), C.byref(kn), C.byref(n), C.byref(nnz), None, None))
+    rp = np.empty(n.value + 1, dtype=np.int32)
+    ci = np.empty(max(nnz.value, 1), dtype=np.int32)
+    _check(lib().pdd_pattern(C.byref(part), C.byref(kn), C.byref(n), C.byref(nnz),
+                             rp.ctypes.data, ci.ctypes.data))
+    return n.value, nnz.value, rp, ci[:nnz.value]
+
+
+def knot_xy(w):
+    part, kn = partition_of(w), knots_of(w)
+    n, nnz = C.c_int64(), C.c_int64()
+    _check(lib().pdd_pattern(C.byref(part), C.byref(kn), C.byref(n), C.byref(nnz), None, None))
+    xy = np.empty(2 * n.value, dtype=np.float64)
+    _check(lib().pdd_knot_xy(C.byref(part), C.byref(kn), xy.ctypes.data))
+    return xy.reshape(-1, 2)
+
+
+class Context:
+    """A libpdd context bound to a torch device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().pdd_create(C.byref(h), int(device), C.c_void_p(stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().pdd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, status):
+        _check(status, self.h)
+
+    def sync(self):
+        self.check(lib().pdd_sync(self.h))
+
+    def set_launch(self, block=0, grid=0, paths_per_ticket=0):
+        self.check(lib().pdd_set_launch(self.h, block, grid, paths_per_ticket))
+
+    def last_launch(self):
+        g, b, t = C.c_int32(), C.c_int32(), C.c_int64()
+        self.check(lib().pdd_last_launch(self.h, C.byref(g), C.byref(b), C.byref(t)))
+        return g.value, b.value, t.value
+
+    def set_timing(self, enable=True):
+        self.check(lib().pdd_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_ms(self):
+        """(summed assembly-kernel milliseconds, launches) since set_timing."""
+        ms, n = C.c_double(), C.c_int32()
+        self.check(lib().pdd_kernel_ms(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    # ---- assembly ----------------------------------------------------------
+    def coeffs_of(self, w, lut=None):
+        par = (C.c_double * 4)(*(list(w.get("param", ())) + [0.0] * 4)[:4])
+        lut_n = int(w.get("lut_n", 0)) if lut is not None else 0
+        return Coeffs(KIND[w["kind"]], lut_n, par, _ptr(lut))
+
+    def assemble(self, w, out=None, lut=None, n_paths_per_knot=None, u_ref=None,
+                 dump_paths=0, precision=None, exit_rule=None, seed=None, instance=None,
+                 cv=None):
+        """Assemble G (CSR) and b of workload w.  Returns dict of device tensors
+        row_ptr, col_idx, val, b, diag (and dump if requested).  ``out`` may hold
+        preallocated tensors of the same names to write into."""
+        torch = self.torch
+        n, nnz, _, _ = pattern(w) if out is None else (out["n"], out["nnz"], None, None)
+        dev = self.device
+        if out is None:
+            out = dict(n=n, nnz=nnz,
+                       row_ptr=torch.empty(n + 1, dtype=torch.int32, device=dev),
+                       col_idx=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                       val=torch.empty(max(nnz, 1), dtype=torch.float64, device=dev),
+                       b=torch.empty(n, dtype=torch.float64, device=dev),
+                       diag=torch.empty(n * DIAG_WIDTH, dtype=torch.float64, device=dev))
+        if dump_paths:
+            out["dump"] = torch.full((n * dump_paths * DUMP_WIDTH,), float("nan"),
+                                     dtype=torch.float64, device=dev)
+        npk = None
+        if n_paths_per_knot is not None:
+            npk = np.ascontiguousarray(n_paths_per_knot, dtype=np.int32)
+        cvs = None
+        if cv is not None:
+            cvs = cv if isinstance(cv, CV) else cv.struct()
+        run = Run(int(w["seed"] if seed is None else seed) & (2 ** 64 - 1),
+                  int(w.get("instance", 0) if instance is None else instance),
+                  PRECISION[precision or w["precision"]], EXIT[exit_rule or w["exit_rule"]],
+                  int(dump_paths), int(w["n_paths"]), _ptr(npk), float(w["h"]),
+                  C.cast(C.pointer(cvs), C.c_void_p) if cvs is not None else None,
+                  _ptr(u_ref), _ptr(out.get("dump")) if dump_paths else None)
+        co = self.coeffs_of(w, lut)
+        part, kn = partition_of(w), knots_of(w)
+        self.check(lib().pdd_assemble(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
+                                      _ptr(out["row_ptr"]), _ptr(out["col_idx"]), _ptr(out["val"]),
+                                      _ptr(out["b"]), _ptr(out["diag"])))
+        self._keep = (npk, cvs)
+        return out

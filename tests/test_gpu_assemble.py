@@ -1,0 +1,236 @@
+"""GPU parity of the HIP assembly (through the C ABI) against the CPU oracle.
+
+Bars:
+  * CSR pattern bit-exact;
+  * float64 same-stream mode: every G entry and b entry within 1e-12 of the
+    oracle, scaled by the row's mean absolute per-path contribution (the sum
+    orders differ, nothing else); step counts and exit-side counts exact;
+    per-path replay records equal to rounding;
+  * float32 production mode (same random stream, float32 paths): every entry
+    within 3 Monte Carlo standard errors of the oracle, plus 1e-6 for the
+    float32 rounding of each contribution.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from paper_2301_05780_amd import pdd, workloads
+from oracle.geometry import Geometry
+from oracle.coeffs import Coefficients
+from oracle.assemble import assemble as oracle_assemble, to_csr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+def _geom(w):
+    return Geometry(w["domain"], w["H"], w["m"], w["ext"])
+
+
+def _coef(w, lut=None):
+    return Coefficients(w["kind"], w.get("param", ()), lut=lut, lut_n=w.get("lut_n", 0),
+                        domain=w["domain"])
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_cached(key):
+    w = dict(key)
+    w["domain"] = tuple(w["domain"])
+    w["param"] = tuple(w.get("param", ()))
+    g = _geom(w)
+    out = oracle_assemble(g, _coef(w), w["n_paths"], w["h"], w["seed"], instance=w.get("instance", 0),
+                          exit_rule=w["exit_rule"], keep_paths=True)
+    return g, to_csr(g, out["rows"]), out["paths"]
+
+
+def oracle(w):
+    key = tuple(sorted((k, tuple(v) if isinstance(v, (list, tuple)) else v) for k, v in w.items()))
+    return _oracle_cached(key)
+
+
+def fetch(out, g):
+    return dict(row_ptr=out["row_ptr"].cpu().numpy(), col_idx=out["col_idx"].cpu().numpy()[:g.nnz],
+                val=out["val"].cpu().numpy()[:g.nnz], b=out["b"].cpu().numpy(),
+                diag=out["diag"].cpu().numpy().reshape(g.n, pdd.DIAG_WIDTH))
+
+
+def assert_same_stream(got, g, ref, rel=1e-12):
+    assert np.array_equal(got["row_ptr"], g.row_ptr)
+    assert np.array_equal(got["col_idx"], g.col_idx)
+    row_of = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    tol = rel * ref["mass"]
+    dv = np.abs(got["val"] - ref["val"])
+    db = np.abs(got["b"] - ref["b"])
+    assert np.all(dv <= tol[row_of]), f"max G error {np.max(dv / tol[row_of]):.3g} x tol"
+    assert np.all(db <= tol), f"max b error {np.max(db / tol):.3g} x tol"
+    d, r = got["diag"], ref["diag"]
+    assert np.array_equal(d[:, :6], r[:, :6]), "step counts / exit-side counts differ"
+    assert np.allclose(d[:, 6:], r[:, 6:], rtol=1e-11, atol=1e-12 * np.max(np.abs(r[:, 6:])))
+
+
+def assert_within_se(got, g, ref, nse=3.0, floor=1e-6):
+    assert np.array_equal(got["row_ptr"], g.row_ptr)
+    assert np.array_equal(got["col_idx"], g.col_idx)
+    dv = np.abs(got["val"] - ref["val"])
+    db = np.abs(got["b"] - ref["b"])
+    assert np.all(dv <= nse * ref["se_val"] + floor), f"worst G {np.max(dv - nse * ref['se_val']):.3g}"
+    assert np.all(db <= nse * ref["se_b"] + floor * np.maximum(1, np.abs(ref["b"]))), \
+        f"worst b {np.max(db - nse * ref['se_b']):.3g}"
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("rule", ["gm", "naive"])
+def test_poisson_small_fp64_same_stream(ctx, rule):
+    w = workloads.poisson_small(rule)
+    g, ref, paths = oracle(w)
+    out = ctx.assemble(w, dump_paths=8)
+    ctx.sync()
+    assert_same_stream(fetch(out, g), g, ref)
+    # per-path replay: the first 8 paths of every knot
+    dump = out["dump"].cpu().numpy().reshape(g.n, 8, pdd.DUMP_WIDTH)
+    for k in range(g.n):
+        p = paths[k]
+        assert np.array_equal(dump[k, :, 0], p["K"][:8])
+        assert np.array_equal(dump[k, :, 6], p["side"][:8])
+        for col, name in ((1, "x"), (2, "y"), (3, "Y"), (4, "Z"), (5, "Xi")):
+            assert np.allclose(dump[k, :, col], p[name][:8], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind,param", [("varcoef", ()), ("amplitude", (0.6,)), ("constsol", ()),
+                                        ("exittime", ())])
+@pytest.mark.parametrize("rule", ["gm", "naive"])
+def test_families_fp64_same_stream(ctx, kind, param, rule):
+    """Several tiles (4 x 4 subdomains, 8 intervals each: 120 knots) and a
+    ragged path count that does not divide the tickets."""
+    w = dict(kind=kind, param=param, domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=300,
+             h=2e-3, seed=7, precision="fp64", exit_rule=rule, instance=3)
+    g, ref, _ = oracle(w)
+    ctx.set_launch(0, 0, 97)
+    try:
+        out = ctx.assemble(w)
+        ctx.sync()
+    finally:
+        ctx.set_launch(0, 0, 0)
+    assert_same_stream(fetch(out, g), g, ref)
+
+
+@pytest.mark.parametrize("rule", ["gm", "naive"])
+def test_poisson_small_fp32_production_within_se(ctx, rule):
+    w = workloads.poisson_small(rule)
+    g, ref, _ = oracle(w)
+    out = ctx.assemble(w, precision="fp32")
+    ctx.sync()
+    got = fetch(out, g)
+    assert_within_se(got, g, ref)
+    # same stream: the step counts of almost every path agree
+    assert abs(got["diag"][:, 0].sum() / ref["diag"][:, 0].sum() - 1.0) < 1e-3
+
+
+def test_varcoef_small_fp32_production_within_se(ctx):
+    w = dict(kind="varcoef", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=400,
+             h=1e-3, seed=2, precision="fp32", exit_rule="gm")
+    g, ref, _ = oracle(w)
+    out = ctx.assemble(w)
+    ctx.sync()
+    assert_within_se(fetch(out, g), g, ref)
+
+
+def test_launch_shape_does_not_change_results(ctx):
+    """One wave doing every ticket, tiny tickets, or the default shape: equal to rounding."""
+    w = workloads.poisson_small("gm")
+    g, ref, _ = oracle(w)
+    results = []
+    for shape in [(0, 0, 0), (64, 1, 0), (128, 3, 7), (256, 0, 1000)]:
+        ctx.set_launch(*shape)
+        try:
+            out = ctx.assemble(w)
+            ctx.sync()
+        finally:
+            ctx.set_launch(0, 0, 0)
+        got = fetch(out, g)
+        assert_same_stream(got, g, ref)
+        results.append(got)
+
+
+def test_deterministic_for_fixed_shape(ctx):
+    w = workloads.poisson_small("gm")
+    w["precision"] = "fp32"
+    g = _geom(w)
+    a = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    b = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    assert np.array_equal(a["val"], b["val"]) and np.array_equal(a["b"], b["b"])
+
+
+def test_ragged_paths_per_knot_and_single_path(ctx):
+    w = dict(kind="varcoef", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=3, m=6, ext=3, n_paths=1,
+             h=2e-3, seed=5, precision="fp64", exit_rule="gm")
+    g = _geom(w)
+    rng = np.random.default_rng(0)
+    npk = rng.integers(1, 90, g.n).astype(np.int32)
+    npk[0] = 1
+    out = ctx.assemble(w, n_paths_per_knot=npk)
+    ctx.sync()
+    got = fetch(out, g)
+    c = _coef(w)
+    from oracle.assemble import assemble as oa
+    ref = to_csr(g, oa(g, c, npk, w["h"], w["seed"], exit_rule="gm")["rows"])
+    assert_same_stream(got, g, ref)
+    assert np.array_equal(got["diag"][:, 1], npk)
+
+
+def test_row_sum_invariant_on_gpu(ctx):
+    """c = 0: sum_j G_kj equals the mean weight sent to boundary data (1 - mass to knots)."""
+    w = dict(kind="amplitude", param=(0.5,), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=2000,
+             h=1e-3, seed=9, precision="fp32", exit_rule="gm")
+    g = _geom(w)
+    got = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    rs = np.add.reduceat(got["val"], g.row_ptr[:-1])
+    assert np.all(rs > -1e-9) and np.all(rs <= 1.0 + 1e-9)
+    # perimeter knots send mass to the boundary, floating ones only through lattice ends
+    assert rs.max() > 0.2
+
+
+def test_constant_solution_identity_on_gpu(ctx):
+    """u = 1 with f = c, g = 1: G 1 = b path by path (eq. 9 with the Euler form of Y)."""
+    w = dict(kind="constsol", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=3000,
+             h=1e-3, seed=4, precision="fp64", exit_rule="gm")
+    g = _geom(w)
+    got = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    rs = np.add.reduceat(got["val"], g.row_ptr[:-1])
+    assert np.allclose(rs, got["b"], rtol=0, atol=1e-13)
+    w["precision"] = "fp32"
+    got = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    rs = np.add.reduceat(got["val"], g.row_ptr[:-1])
+    assert np.allclose(rs, got["b"], rtol=0, atol=2e-6)
+
+
+def test_invalid_arguments_rejected(ctx):
+    w = workloads.poisson_small()
+    for bad in [dict(h=0.0), dict(h=float("nan")), dict(n_paths=0), dict(kind="amplitude", param=(1.5,)),
+                dict(H=1)]:
+        ww = dict(w)
+        ww.update(bad)
+        with pytest.raises(pdd.PddError) as e:
+            ctx.assemble(ww) if "H" not in bad else ctx.assemble(ww, out=dict(
+                n=1, nnz=1, row_ptr=torch.zeros(2, dtype=torch.int32, device="cuda"),
+                col_idx=torch.zeros(1, dtype=torch.int32, device="cuda"),
+                val=torch.zeros(1, dtype=torch.float64, device="cuda"),
+                b=torch.zeros(1, dtype=torch.float64, device="cuda"),
+                diag=torch.zeros(8, dtype=torch.float64, device="cuda")))
+        assert e.value.status == pdd.EINVAL
