@@ -114,7 +114,7 @@ enum {
   PDD_CV_GRAD_LUT = 2        /* grad v baked into a float32 table, bilinear read */
 };
 enum { PDD_DIAG_WIDTH = 8 };   /* per knot: sum K, N, exits E/N/W/S, sum s, sum s^2 */
-enum { PDD_DUMP_WIDTH = 8 };   /* per dumped path: K, x_K, y_K, Y_K, Z_K, Xi_K, side, t */
+enum { PDD_DUMP_WIDTH = 8 };   /* per dumped path: K, x_K, y_K, Y_K, Z_K, Xi_K, knot, path */
 enum { PDD_MLP_WIDTH = 64, PDD_MLP_PARAMS = 4417 };
 
 /* Control variate of eqs. (37)-(38): Xi accumulates -Y (sigma^T grad v) . dW
@@ -189,11 +189,18 @@ pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partit
 
 /* ---- launch control and measurement ------------------------------------ */
 
+/* Ticket schedules: STATIC gives wave w the tickets w, w + W, w + 2W, ...
+ * (bitwise reproducible sums for a fixed launch shape); DYNAMIC lets waves
+ * claim tickets from a device counter (better balance; float64 sums then
+ * vary at rounding level between runs). */
+enum { PDD_SCHEDULE_STATIC = 0, PDD_SCHEDULE_DYNAMIC = 1 };
+
 /* Override the assembly launch shape (0 = automatic): threads per block (a
- * multiple of 64, at most 256), workgroups in the persistent grid, and paths
- * per ticket (the unit a wave takes from the work list).  Results do not
- * depend on these except through float64 summation order. */
-pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket);
+ * multiple of 64, at most 256), workgroups in the persistent grid, paths per
+ * ticket (the unit a wave takes from the work list) and the ticket schedule.
+ * Results do not depend on these except through float64 summation order. */
+pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket,
+                          int32_t schedule);
 /* Shape of the last assembly launch: grid, block and number of tickets. */
 pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets);
 /* enable != 0: bracket every assembly kernel launched from now on with a pair

@@ -5,22 +5,24 @@
 // (knot, path range).  Each wave of the persistent grid takes tickets in a
 // fixed stride (wave w: tickets w, w + W, w + 2W, ...) and owns two LDS tally
 // rows.  Every lane integrates one path at a time; when its path exits, the
-// lane is refilled with the next path of the wave's current ticket, ranked
-// among the idle lanes by a ballot (no atomics).  When the current ticket has
-// handed out all its paths, the next ticket is opened in the other row while
-// the stragglers of the previous one drain, so lanes never wait for the
+// lane is refilled at once with the next path of the wave's current ticket,
+// ranked among the idle lanes by a ballot (no atomics).  When the current
+// ticket has handed out all its paths, the next ticket opens in the other row
+// while the stragglers of the previous one drain, so lanes never wait for the
 // slowest path of a ticket.  A drained row is written once to the ticket's
 // partial row in HBM; a second kernel sums a knot's partial rows in ticket
 // order into the CSR values and b (deterministic for a fixed launch shape).
 //
-// Per lane and per Philox draw (one call feeds two Euler steps), both steps
-// run with all lanes of the wave at the same draw parity, so the Philox call
-// is never divergent.
+// Hot loop.  One Philox draw feeds two Euler steps; every path starts at an
+// even step, so all lanes of a wave draw together and the generator is never
+// divergent.  An exiting lane only appends its exit state (X_K, Y_K,
+// Z_K + Xi_K, K) to a per-wave LDS queue and is refilled; the exit work (side
+// choice, projection, hat weights, tallies) runs over 64 queued exits at a
+// time with every lane busy, instead of in a branch with a handful of lanes
+// active.
 //
-// Tallies: G slots are float64 LDS atomics (two per interface exit); b, the
-// score moments, the step count and the exit-side counts accumulate in lane
-// registers and are spilled into the row only when the lane moves to another
-// row or the row is flushed.
+// Tallies: G slots, b, the score moments and the step count are float64 LDS
+// atomics; exit-side counts are ballot popcounts added by one lane.
 #include <type_traits>
 
 #include "device_common.h"
@@ -29,6 +31,9 @@ namespace pdd {
 
 namespace {
 
+constexpr int QCAP = 128;          // exit records per wave (processed at >= 64)
+constexpr uint32_t MAX_STEPS = (1u << 24) - 2;
+
 struct WaveBuf {
   KnotDesc d;
   double ebox[4];      // strict exit thresholds: x > e[0], y > e[1], x < e[2], y < e[3]
@@ -36,6 +41,18 @@ struct WaveBuf {
   uint32_t inst;
 };
 static_assert(sizeof(WaveBuf) % 16 == 0, "WaveBuf alignment");
+
+template <typename R>
+struct ExitRec {
+  R x, y, Y, bp;       // exit iterate, Y_K, Z_K + Xi_K
+};
+
+// per-wave LDS bytes: two row headers, the exit queue (records + meta words), two tally rows
+template <typename R>
+constexpr size_t wave_lds_bytes(int row_len) {
+  return 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>) + QCAP * sizeof(uint32_t) +
+         2 * (size_t)row_len * sizeof(double);
+}
 
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -50,36 +67,62 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-template <typename R>
-__device__ __forceinline__ R next_down(R v) {
-  return nextafter(v, -INFINITY);
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
-template <typename R>
-__device__ __forceinline__ R next_up(R v) {
-  return nextafter(v, INFINITY);
+
+__device__ __forceinline__ float uniform_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform_f64(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float to_uniform(float v) { return uniform_f32(v); }
+__device__ __forceinline__ double to_uniform(double v) { return uniform_f64(v); }
+__device__ __forceinline__ uint32_t to_uniform_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
 // One Euler-Maruyama step of eq. (9) with coefficients frozen at the left point.
 template <int KIND, typename R>
 __device__ __forceinline__ void em_step(const AsmParams& P, R z0, R z1, R& x, R& y, R& Y, R& Z) {
+  using T = Traits<KIND>;
   Coef<R> c;
   coef_at<KIND>(P.coef, x, y, c);
   if constexpr (std::is_same<R, double>::value) {
 #pragma clang fp contract(off)
     const double sq = P.sqrt_h, h = P.h;
     const double dWx = sq * z0, dWy = sq * z1;
-    const double nx = x + c.dx * h + (c.sxx * dWx + c.sxy * dWy);
-    const double ny = y + c.dy * h + (c.sxy * dWx + c.syy * dWy);
+    double nx = x, ny = y;
+    if constexpr (T::drift) { nx = nx + c.dx * h; ny = ny + c.dy * h; }
+    if constexpr (T::offdiag) {
+      nx = nx + (c.sxx * dWx + c.sxy * dWy);
+      ny = ny + (c.sxy * dWx + c.syy * dWy);
+    } else {
+      nx = nx + c.sxx * dWx;
+      ny = ny + c.syy * dWy;
+    }
     const double nZ = Z - c.f * Y * h;
-    Y = Y * (1.0 + c.c * h);
+    if constexpr (T::reaction) Y = Y * (1.0 + c.c * h);
     x = nx; y = ny; Z = nZ;
   } else {
     const float sq = (float)P.sqrt_h, h = (float)P.h;
     const float dWx = sq * z0, dWy = sq * z1;
-    const float nx = x + c.dx * h + (c.sxx * dWx + c.sxy * dWy);
-    const float ny = y + c.dy * h + (c.sxy * dWx + c.syy * dWy);
+    float nx = x, ny = y;
+    if constexpr (T::drift) { nx = nx + c.dx * h; ny = ny + c.dy * h; }
+    if constexpr (T::offdiag) {
+      nx = nx + (c.sxx * dWx + c.sxy * dWy);
+      ny = ny + (c.sxy * dWx + c.syy * dWy);
+    } else {
+      nx = nx + c.sxx * dWx;
+      ny = ny + c.syy * dWy;
+    }
     const float nZ = Z - c.f * Y * h;
-    Y = Y * (1.0f + c.c * h);
+    if constexpr (T::reaction) Y = Y * (1.0f + c.c * h);
     x = nx; y = ny; Z = nZ;
   }
 }
@@ -105,9 +148,16 @@ __device__ R exit_threshold(const AsmParams& P, const KnotDesc& d, int o) {
     const R delta = (R)kGM * sqrt(ann) * (R)P.sqrt_h;
     thr = (o < 2) ? (R)line - delta : (R)line + delta;
   }
-  // x >= thr  <=>  x > next_down(thr);  x <= thr  <=>  x < next_up(thr)
-  return (o < 2) ? next_down(thr) : next_up(thr);
+  // x >= thr  <=>  x > nextafter(thr, -inf);  x <= thr  <=>  x < nextafter(thr, +inf)
+  return (o < 2) ? nextafter(thr, (R)-INFINITY) : nextafter(thr, (R)INFINITY);
 }
+
+// Per-buffer uniform values used at refill (kept in scalar registers).
+template <typename R>
+struct BufU {
+  R sx, sy, e0, e1, e2, e3;
+  uint32_t knot, inst;
+};
 
 template <int KIND, bool F64>
 __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
@@ -117,17 +167,31 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
   const int wid = threadIdx.x >> 6;
   const int waves_per_block = blockDim.x >> 6;
   const int RL = P.row_len, SL = P.slot_len;
-  const size_t wave_doubles = (2 * sizeof(WaveBuf)) / sizeof(double) + 2 * (size_t)RL;
-  double* wbase = smem + (size_t)wid * wave_doubles;
+  unsigned char* wbase = reinterpret_cast<unsigned char*>(smem) + (size_t)wid * wave_lds_bytes<R>(RL);
   WaveBuf* B = reinterpret_cast<WaveBuf*>(wbase);
-  double* rows = wbase + (2 * sizeof(WaveBuf)) / sizeof(double);
+  ExitRec<R>* Q = reinterpret_cast<ExitRec<R>*>(wbase + 2 * sizeof(WaveBuf));
+  uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>));
+  double* rows = reinterpret_cast<double*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>) +
+                                           QCAP * sizeof(uint32_t));
   const uint32_t nw = gridDim.x * waves_per_block;
-  uint32_t next_ticket = blockIdx.x * waves_per_block + wid;
+  // next ticket this wave takes: fixed stride (static schedule, reproducible
+  // sums) or claimed from a device counter (dynamic schedule, balanced)
+  auto claim = [&](uint32_t prev) __attribute__((always_inline)) -> uint32_t {
+    if (P.ticket_counter) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(P.ticket_counter, 1u);
+      return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+    }
+    return prev + nw;
+  };
+  uint32_t next_ticket = P.ticket_counter ? claim(0) : blockIdx.x * waves_per_block + wid;
 
   // wave-uniform ticket state of the two rows
   int tk0 = -1, tk1 = -1;
   int nx0 = 0, en0 = 0, nx1 = 0, en1 = 0;
   int cur = 0;
+  int qn = 0;                    // queued exit records
+  BufU<R> u0{}, u1{};
 
   // lane state
   bool active = false;
@@ -135,27 +199,124 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
   uint32_t p = 0, kn = 0, inst = 0, j = 0;
   R x = 0, y = 0, Y = 0, Z = 0, Xi = 0;
   R ehx = 0, ehy = 0, elx = 0, ely = 0;
-  int abuf = -1;
-  double acc_b = 0, acc_s = 0, acc_s2 = 0;
-  uint32_t acc_k = 0, acc_en = 0, acc_ws = 0;   // side counts packed 16 + 16 bits
 
-  auto spill = [&](int b) {
-    double* ex = rows + (size_t)b * RL + 4 * SL;
-    lds_add(ex + EX_B, acc_b);
-    lds_add(ex + EX_S, acc_s);
-    lds_add(ex + EX_S2, acc_s2);
-    lds_add(ex + EX_K, (double)acc_k);
-    lds_add(ex + EX_E, (double)(acc_en & 0xFFFFu));
-    lds_add(ex + EX_N, (double)(acc_en >> 16));
-    lds_add(ex + EX_W, (double)(acc_ws & 0xFFFFu));
-    lds_add(ex + EX_S_SIDE, (double)(acc_ws >> 16));
-    acc_b = acc_s = acc_s2 = 0.0;
-    acc_k = acc_en = acc_ws = 0;
+  // ---- exit processing over the queue (all lanes) ----------------------------
+  auto process_queue = [&]() __attribute__((always_inline)) {
+    for (int base = 0; base < qn; base += 64) {
+      const int i = base + lane;
+      const bool valid = i < qn;
+      int rb = 0, o = 0;
+      double vb = 0.0, vs = 0.0, vk = 0.0;
+      if (valid) {
+        const ExitRec<R> r = Q[i];
+        const uint32_t meta = Qm[i];
+        rb = (int)((meta >> 24) & 1u);
+        const bool forced = (meta >> 25) & 1u;
+        const WaveBuf& W = B[rb];
+        const KnotDesc& d = W.d;
+        bool fE = r.x > (R)W.ebox[0], fN = r.y > (R)W.ebox[1];
+        bool fW = r.x < (R)W.ebox[2], fS = r.y < (R)W.ebox[3];
+        if (forced) fE = fN = fW = fS = true;
+        // side: the tripped side whose line is closest (ties: E, N, W, S)
+        const R lE = (R)d.line[0], lN = (R)d.line[1], lW = (R)d.line[2], lS = (R)d.line[3];
+        o = -1;
+        R best = 0;
+        if (fE) { o = 0; best = fabs(r.x - lE); }
+        if (fN) { const R v = fabs(r.y - lN); if (o < 0 || v < best) { o = 1; best = v; } }
+        if (fW) { const R v = fabs(r.x - lW); if (o < 0 || v < best) { o = 2; best = v; } }
+        if (fS) { const R v = fabs(r.y - lS); if (o < 0 || v < best) { o = 3; best = v; } }
+        const bool vert = (o == 0 || o == 2);
+        const R along = vert ? r.y : r.x;
+        const R lpos = (R)d.line[o];
+        R bp = r.bp, uref = 0;
+        if ((d.bmask >> o) & 1) {
+          // boundary side: Y g(P), P the projection clamped to the domain
+          const R a0 = vert ? (R)P.y0 : (R)P.x0, a1 = vert ? (R)P.y1 : (R)P.x1;
+          const R pa = fmin(fmax(along, a0), a1);
+          const R gv = vert ? g_at<KIND>(lpos, pa) : g_at<KIND>(pa, lpos);
+          {
+#pragma clang fp contract(off)
+            bp = bp + r.Y * gv;
+          }
+        } else {
+          // interface side: hat weights on the line lattice, clamped to the stencil range
+          const R a0 = vert ? (R)P.y0 : (R)P.x0;
+          const int clo = d.clo[o], chi = d.chi[o];
+          R t;
+          if constexpr (F64) t = (along - a0) / (vert ? P.dy : P.dx);
+          else t = (along - a0) * (vert ? P.inv_dy : P.inv_dx);
+          t = fmin(fmax(t, (R)clo), (R)chi);
+          const R i0 = fmin(floor(t), (R)(chi - 1));
+          const R w = t - i0;
+          const int q0 = (int)i0;
+          double* row = rows + (size_t)rb * RL + o * SL;
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int q = q0 + e;
+            R c;
+            {
+#pragma clang fp contract(off)
+              c = r.Y * (e == 0 ? (R)1 - w : w);
+            }
+            if (q == 0 || q == P.L) {
+              const R qc = vert ? (R)P.y0 + (R)q * (R)P.dy : (R)P.x0 + (R)q * (R)P.dx;
+              const R gv = vert ? g_at<KIND>(lpos, qc) : g_at<KIND>(qc, lpos);
+              {
+#pragma clang fp contract(off)
+                bp = bp + c * gv;
+              }
+            } else {
+              lds_add(row + (q - clo), (double)c);
+              if (P.u_ref) {
+                const int at = d.at[o];
+                const int lx = vert ? at : q, ly = vert ? q : at;
+                const int col = P.lattice[(size_t)ly * (P.L + 1) + lx];
+                {
+#pragma clang fp contract(off)
+                  uref = uref + c * (R)P.u_ref[col];
+                }
+              }
+            }
+          }
+        }
+        vb = (double)bp;
+        vs = vb + (double)uref;
+        vk = (double)(meta & 0xFFFFFFu);
+      }
+      // row extras: b, sum s, sum s^2 and sum K through LDS atomics (the LDS
+      // pipe serialises the same-address lanes; no VALU reduction needed),
+      // exit-side counts through ballots
+      if (valid) {
+        double* ex = rows + (size_t)rb * RL + 4 * SL;
+        lds_add(ex + EX_B, vb);
+        lds_add(ex + EX_S, vs);
+        lds_add(ex + EX_S2, vs * vs);
+        lds_add(ex + EX_K, vk);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const bool mine = valid && rb == b;
+        const int cE = __popcll(__ballot(mine && o == 0));
+        const int cN = __popcll(__ballot(mine && o == 1));
+        const int cW = __popcll(__ballot(mine && o == 2));
+        const int cS = __popcll(__ballot(mine && o == 3));
+        if (lane == 0 && (cE | cN | cW | cS) != 0) {
+          double* ex = rows + (size_t)b * RL + 4 * SL;
+          ex[EX_E] += (double)cE;
+          ex[EX_N] += (double)cN;
+          ex[EX_W] += (double)cW;
+          ex[EX_S_SIDE] += (double)cS;
+        }
+      }
+    }
+    wave_sync();
+    qn = 0;
   };
 
-  auto acquire = [&](int b) {
-    const uint32_t t = next_ticket;
-    next_ticket += nw;
+  auto acquire = [&](int b) __attribute__((always_inline)) {
+    const uint32_t slot = next_ticket;
+    next_ticket = claim(slot);
+    const uint32_t t = (uint32_t)P.order[slot];
     const Ticket T = P.tickets[t];
     WaveBuf& W = B[b];
     const double* src = reinterpret_cast<const double*>(P.desc + T.knot);
@@ -167,12 +328,21 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
     wave_sync();
     if (lane < 4) W.ebox[lane] = (double)exit_threshold<KIND, R>(P, W.d, lane);
     wave_sync();
-    if (b) { tk1 = (int)t; nx1 = T.p0; en1 = T.p1; } else { tk0 = (int)t; nx0 = T.p0; en0 = T.p1; }
+    BufU<R> u;
+    u.sx = to_uniform((R)W.d.sx);
+    u.sy = to_uniform((R)W.d.sy);
+    u.e0 = to_uniform((R)W.ebox[0]);
+    u.e1 = to_uniform((R)W.ebox[1]);
+    u.e2 = to_uniform((R)W.ebox[2]);
+    u.e3 = to_uniform((R)W.ebox[3]);
+    u.knot = to_uniform_u((uint32_t)T.knot);
+    u.inst = to_uniform_u(T.inst);
+    if (b) { tk1 = (int)t; nx1 = T.p0; en1 = T.p1; u1 = u; }
+    else { tk0 = (int)t; nx0 = T.p0; en0 = T.p1; u0 = u; }
   };
 
-  auto flush = [&](int b) {
-    if (abuf == b) { spill(b); abuf = -1; }
-    wave_sync();
+  auto flush = [&](int b) __attribute__((always_inline)) {
+    if (qn > 0) process_queue();
     const int t = b ? tk1 : tk0;
     const double* row = rows + (size_t)b * RL;
     double* dst = P.partial + (size_t)t * RL;
@@ -200,16 +370,17 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
       const int take = min(__popcll(idle), en - nx);
       const int rank = lane_rank(idle);
       if (!active && rank < take) {
-        if (abuf >= 0 && abuf != cur) spill(abuf);
-        abuf = cur;
-        const WaveBuf& W = B[cur];
         p = (uint32_t)(nx + rank);
-        kn = (uint32_t)W.d.knot;
-        inst = W.inst;
+        kn = cur ? u1.knot : u0.knot;
+        inst = cur ? u1.inst : u0.inst;
         j = 0;
-        x = (R)W.d.sx; y = (R)W.d.sy;
+        x = cur ? u1.sx : u0.sx;
+        y = cur ? u1.sy : u0.sy;
         Y = (R)1; Z = (R)0; Xi = (R)0;
-        ehx = (R)W.ebox[0]; ehy = (R)W.ebox[1]; elx = (R)W.ebox[2]; ely = (R)W.ebox[3];
+        ehx = cur ? u1.e0 : u0.e0;
+        ehy = cur ? u1.e1 : u0.e1;
+        elx = cur ? u1.e2 : u0.e2;
+        ely = cur ? u1.e3 : u0.e3;
         active = true;
         buf = cur;
       }
@@ -237,98 +408,32 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
       }
       ++j;
-      if (!ex && 2 * j >= P.max_steps) { ex = true; forced = true; }
+      if (!ex && 2 * j >= MAX_STEPS) { ex = true; forced = true; }
     }
 
-    // ---- exits: side, projection, interpolation, tallies -----------------------
-    if (__ballot(ex) != 0 && ex) {
-      const WaveBuf& W = B[buf];
-      const KnotDesc& d = W.d;
-      bool fE = x > ehx, fN = y > ehy, fW = x < elx, fS = y < ely;
-      if (forced) fE = fN = fW = fS = true;
-      const R lE = (R)d.line[0], lN = (R)d.line[1], lW = (R)d.line[2], lS = (R)d.line[3];
-      int o = -1;
-      R best = 0;
-      if (fE) { o = 0; best = fabs(x - lE); }
-      if (fN) { const R v = fabs(y - lN); if (o < 0 || v < best) { o = 1; best = v; } }
-      if (fW) { const R v = fabs(x - lW); if (o < 0 || v < best) { o = 2; best = v; } }
-      if (fS) { const R v = fabs(y - lS); if (o < 0 || v < best) { o = 3; best = v; } }
-      const bool vert = (o == 0 || o == 2);
-      const R along = vert ? y : x;
-      const R lpos = (R)d.line[o];
-      R bp, uref = 0, trec;
-      if ((d.bmask >> o) & 1) {
-        const R a0 = vert ? (R)P.y0 : (R)P.x0, a1 = vert ? (R)P.y1 : (R)P.x1;
-        const R pa = fmin(fmax(along, a0), a1);
-        const R gv = vert ? g_at<KIND>(lpos, pa) : g_at<KIND>(pa, lpos);
+    // ---- queue the exits ------------------------------------------------------
+    const uint64_t em = __ballot(ex);
+    if (em != 0) {
+      if (ex) {
+        const int i = qn + lane_rank(em);
+        ExitRec<R> rec;
+        rec.x = x; rec.y = y; rec.Y = Y;
         {
 #pragma clang fp contract(off)
-          bp = Z + Xi + Y * gv;
+          rec.bp = Z + Xi;
         }
-        trec = pa;
-      } else {
-        const R a0 = vert ? (R)P.y0 : (R)P.x0;
-        const R da = vert ? (R)P.dy : (R)P.dx;
-        const int clo = d.clo[o], chi = d.chi[o];
-        R t;
-        if constexpr (F64) {
-          t = (along - a0) / da;
-        } else {
-          t = (along - a0) * ((R)1 / da);
+        Q[i] = rec;
+        Qm[i] = K | ((uint32_t)buf << 24) | ((uint32_t)forced << 25);
+        if (P.dump && (int)p < P.dump_paths) {
+          double* d = P.dump + ((size_t)kn * P.dump_paths + p) * PDD_DUMP_WIDTH;
+          d[0] = (double)K; d[1] = (double)x; d[2] = (double)y; d[3] = (double)Y;
+          d[4] = (double)Z; d[5] = (double)Xi; d[6] = (double)kn; d[7] = (double)p;
         }
-        t = fmin(fmax(t, (R)clo), (R)chi);
-        const R i0 = fmin(floor(t), (R)(chi - 1));
-        const R w = t - i0;
-        const int q0 = (int)i0;
-        trec = t;
-        bp = Z + Xi;
-        double* row = rows + (size_t)buf * RL + o * SL;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int q = q0 + e;
-          R c;
-          {
-#pragma clang fp contract(off)
-            c = Y * (e == 0 ? (R)1 - w : w);
-          }
-          if (q == 0 || q == P.L) {
-            const R qc = vert ? (R)P.y0 + (R)q * (R)P.dy : (R)P.x0 + (R)q * (R)P.dx;
-            const R gv = vert ? g_at<KIND>(lpos, qc) : g_at<KIND>(qc, lpos);
-            {
-#pragma clang fp contract(off)
-              bp = bp + c * gv;
-            }
-          } else {
-            lds_add(row + (q - clo), (double)c);
-            if (P.u_ref) {
-              const int at = d.at[o];
-              const int lx = vert ? at : q, ly = vert ? q : at;
-              const int col = P.lattice[(size_t)ly * (P.L + 1) + lx];
-              {
-#pragma clang fp contract(off)
-                uref = uref + c * (R)P.u_ref[col];
-              }
-            }
-          }
-        }
+        active = false;
       }
-      const double s = (double)bp + (double)uref;
-      acc_b += (double)bp;
-      acc_s += s;
-      acc_s2 += s * s;
-      acc_k += K;
-      if (o == 0) acc_en += 1u;
-      else if (o == 1) acc_en += 1u << 16;
-      else if (o == 2) acc_ws += 1u;
-      else acc_ws += 1u << 16;
-      if (P.dump && (int)p < P.dump_paths) {
-        double* rec = P.dump + ((size_t)kn * P.dump_paths + p) * PDD_DUMP_WIDTH;
-        rec[0] = (double)K; rec[1] = (double)x; rec[2] = (double)y; rec[3] = (double)Y;
-        rec[4] = (double)Z; rec[5] = (double)Xi; rec[6] = (double)o; rec[7] = (double)trec;
-      }
-      active = false;
-      // 16-bit side counters: spill before they can wrap
-      if (((acc_en | acc_ws) & 0x80008000u) != 0) spill(buf);
+      qn += __popcll(em);
+      wave_sync();
+      if (qn >= 64) process_queue();
     }
 
     // ---- flush rows whose ticket is handed out and drained ---------------------
@@ -342,6 +447,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
 __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
   const int lane = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (F.ticket_counter && blockIdx.x == 0 && threadIdx.x == 0) *F.ticket_counter = 0u;
   if (k >= F.n) return;
   const KnotDesc d = F.desc[k];
   const int tb = F.ticket_begin[k], te = F.ticket_begin[k + 1];
@@ -411,9 +517,10 @@ const void* assemble_kernel(int precision, int kind) {
 
 }  // namespace
 
-size_t assemble_lds_bytes(int row_len, int block) {
+size_t assemble_lds_bytes(int precision, int row_len, int block) {
   const size_t waves = (size_t)block / 64;
-  return waves * (2 * sizeof(WaveBuf) + 2 * (size_t)row_len * sizeof(double));
+  return waves * (precision == PDD_FP64_SAME_STREAM ? wave_lds_bytes<double>(row_len)
+                                                    : wave_lds_bytes<float>(row_len));
 }
 
 hipError_t assemble_occupancy(int precision, int kind, int block, size_t lds_bytes, int* blocks_per_cu) {

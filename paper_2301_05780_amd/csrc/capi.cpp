@@ -211,13 +211,17 @@ pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partit
   return run_assemble(ctx, job);
 }
 
-pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket) {
+pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket,
+                          int32_t schedule) {
   if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_launch: null context");
   if (block < 0 || block > 256 || block % 64 != 0 || grid < 0 || paths_per_ticket < 0)
     return fail(ctx, PDD_EINVAL, "pdd_set_launch: block must be 0 or a multiple of 64 up to 256; grid, paths_per_ticket >= 0");
+  if (schedule != PDD_SCHEDULE_STATIC && schedule != PDD_SCHEDULE_DYNAMIC)
+    return fail(ctx, PDD_EINVAL, "pdd_set_launch: unknown schedule");
   ctx->force_block = block;
   ctx->force_grid = grid;
   ctx->force_per_ticket = paths_per_ticket;
+  ctx->schedule = schedule;
   return PDD_OK;
 }
 

@@ -41,7 +41,7 @@ struct TicketCache {
   int32_t per_ticket = 0;
   uint32_t inst = 0;
   int64_t n_tickets = 0;
-  DeviceBuffer tickets, ticket_begin, n_paths;
+  DeviceBuffer tickets, ticket_begin, n_paths, order;
 };
 
 struct AssembleJob {
@@ -69,6 +69,8 @@ struct pdd_ctx {
   pdd::DeviceBuffer partial;
   // launch overrides (0 = automatic), set by the tuner
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
+  int schedule = PDD_SCHEDULE_STATIC;
+  pdd::DeviceBuffer ticket_counter;
   // shape of the last assembly launch (reported by pdd_last_launch)
   int last_grid = 0, last_block = 0;
   int64_t last_tickets = 0;

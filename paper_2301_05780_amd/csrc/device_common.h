@@ -31,8 +31,9 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    // three-input XOR in one VALU op (truth table 0x96 = a ^ b ^ c)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -48,17 +49,21 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 __device__ __forceinline__ double uniform64(uint32_t r) {
   return ((double)r + 0.5) * 0x1p-32;
 }
-// float32: the top 23 bits, u = (2 (r >> 9) + 1) 2^-24, exact, in (0, 1).
+// float32: the top 23 bits, u = (r >> 9) 2^-23 + 2^-24 = (2 (r >> 9) + 1) 2^-24,
+// exact, in (0, 1).
 __device__ __forceinline__ float uniform32(uint32_t r) {
-  return (float)(((r >> 9) << 1) | 1u) * 0x1p-24f;
+  return __builtin_fmaf((float)(r >> 9), 0x1p-23f, 0x1p-24f);
 }
 
 // ---- CDNA transcendental units (float32) ------------------------------------
+// v_sin/v_cos take the angle in revolutions and accept |r| <= 256; the host
+// rejects domains with a coordinate beyond 128 in absolute value, which keeps
+// every argument below (at most 2 |x| revolutions) in range.
 __device__ __forceinline__ float sin_rev(float r) {   // sin(2 pi r)
-  return __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(r));
+  return __builtin_amdgcn_sinf(r);
 }
 __device__ __forceinline__ float cos_rev(float r) {   // cos(2 pi r)
-  return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(r));
+  return __builtin_amdgcn_cosf(r);
 }
 __device__ __forceinline__ float fsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ float fexp(float v) { return __builtin_amdgcn_exp2f(v * 1.4426950408889634f); }
@@ -82,6 +87,14 @@ __device__ __forceinline__ void box_muller(double u0, double u1, double& z0, dou
 template <typename R>
 struct Coef {
   R sxx, sxy, syy, dx, dy, c, f;
+};
+
+// Which terms of eq. (9) a family has (lets the step skip structural zeros;
+// skipping an exact zero never changes a result).
+template <int KIND> struct Traits {
+  static constexpr bool drift = (KIND == PDD_COEF_VARCOEF || KIND == PDD_COEF_CONSTSOL || KIND == PDD_COEF_LUT);
+  static constexpr bool reaction = drift;
+  static constexpr bool offdiag = (KIND == PDD_COEF_LUT);
 };
 
 // Bilinear read of the node-centred LUT (seven fields).  Position -> node

@@ -69,10 +69,10 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   const int slot_len = g.slot_len;
   const int row_len = 4 * slot_len + EX_COUNT;
   int block = ctx->force_block ? ctx->force_block : 256;
-  size_t lds = assemble_lds_bytes(row_len, block);
+  size_t lds = assemble_lds_bytes(run.precision, row_len, block);
   while (lds > 65536 && block > 64) {
     block /= 2;
-    lds = assemble_lds_bytes(row_len, block);
+    lds = assemble_lds_bytes(run.precision, row_len, block);
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;
@@ -82,8 +82,9 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
   const int64_t waves = grid * (block / 64);
 
+  // about seven tickets per wave (static stride stays balanced), at least 256 paths each
   int64_t per_ticket = ctx->force_per_ticket;
-  if (per_ticket <= 0) per_ticket = std::max<int64_t>(256, (total + 4 * waves - 1) / (4 * waves));
+  if (per_ticket <= 0) per_ticket = std::max<int64_t>(256, (total + 7 * waves - 1) / (7 * waves));
 
   // tickets (cached while geometry, path counts and ticket size repeat)
   TicketCache* tc = ctx->tickets.get();
@@ -95,9 +96,12 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     fresh->inst = run.instance;
     std::vector<Ticket> tk;
     std::vector<int32_t> tb(g.n + 1, 0);
+    std::vector<double> cost;
     for (int64_t k = 0; k < g.n; ++k) {
       const int64_t N = npk[k];
       const int64_t c = (N + per_ticket - 1) / per_ticket;
+      // expected steps per path scale with the patch area (mean exit time, eq. 26)
+      const double area = (double)(g.box[4 * k + 1] - g.box[4 * k + 0]) * (double)(g.box[4 * k + 3] - g.box[4 * k + 2]);
       for (int64_t i = 0; i < c; ++i) {
         Ticket t;
         t.knot = (int32_t)k;
@@ -105,17 +109,24 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
         t.p1 = (int32_t)(N * (i + 1) / c);
         t.inst = run.instance;
         tk.push_back(t);
+        cost.push_back(area * (double)(t.p1 - t.p0));
       }
       if ((int64_t)tk.size() > INT32_MAX) return bad(ctx, PDD_EUNSUPPORTED, "too many tickets");
       tb[k + 1] = (int32_t)tk.size();
     }
+    // longest-expected-first order (stable: ties keep knot order)
+    std::vector<int32_t> order(tk.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     fresh->n_tickets = (int64_t)tk.size();
     if ((e = fresh->tickets.reserve(tk.size() * sizeof(Ticket))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(tickets)");
+    if ((e = fresh->order.reserve(order.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(order)");
     if ((e = fresh->ticket_begin.reserve(tb.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(ticket_begin)");
     if ((e = fresh->n_paths.reserve(npk.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(n_paths)");
     // the stream may still read the previous cache's arrays
     if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
     if ((e = hipMemcpy(fresh->tickets.ptr, tk.data(), tk.size() * sizeof(Ticket), hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload tickets");
+    if ((e = hipMemcpy(fresh->order.ptr, order.data(), order.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload order");
     if ((e = hipMemcpy(fresh->ticket_begin.ptr, tb.data(), tb.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload ticket_begin");
     if ((e = hipMemcpy(fresh->n_paths.ptr, npk.data(), npk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload n_paths");
     ctx->tickets = std::move(fresh);
@@ -141,6 +152,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   std::memset(&P, 0, sizeof(P));
   P.desc = gc->desc.as<KnotDesc>();
   P.tickets = tc->tickets.as<Ticket>();
+  P.order = tc->order.as<int32_t>();
   P.n_tickets = (int32_t)tc->n_tickets;
   P.row_len = row_len;
   P.slot_len = slot_len;
@@ -165,7 +177,16 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.u_ref = run.u_ref;
   P.lattice = gc->lattice.as<int32_t>();
   P.dump = run.dump_paths > 0 ? run.dump : nullptr;
-  P.max_steps = 1u << 24;
+  P.ticket_counter = nullptr;
+  if (ctx->schedule == PDD_SCHEDULE_DYNAMIC) {
+    if (!ctx->ticket_counter.ptr) {
+      if ((e = ctx->ticket_counter.reserve(sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(counter)");
+      if ((e = hipMemset(ctx->ticket_counter.ptr, 0, sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMemset(counter)");
+    }
+    P.ticket_counter = ctx->ticket_counter.as<uint32_t>();
+  }
+  P.inv_dx = (float)(1.0 / g.dx);
+  P.inv_dy = (float)(1.0 / g.dy);
 
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (ctx->timing && ctx->ev_used < 4096) {
@@ -199,6 +220,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   F.val = job.val;
   F.b = job.b;
   F.diag = job.diag;
+  F.ticket_counter = P.ticket_counter;
   e = launch_finalize(F, ctx->stream);
   if (e != hipSuccess) return check_hip(ctx, e, "launch finalize");
   ctx->last_grid = (int)grid;

@@ -40,6 +40,7 @@ struct CoefParams {
 struct AsmParams {
   const KnotDesc* desc;
   const Ticket* tickets;
+  const int32_t* order;       // schedule: ticket ids, longest expected work first
   int32_t n_tickets;
   int32_t row_len;            // doubles per partial row: 4 slot_len + 8
   int32_t slot_len;           // G slots per side
@@ -50,11 +51,12 @@ struct AsmParams {
   int32_t dump_paths;
   double h, sqrt_h;
   double x0, x1, y0, y1, dx, dy;
+  float inv_dx, inv_dy;       // 1/dx, 1/dy in float32 (production mode)
   CoefParams coef;
   const double* u_ref;        // nullable
   const int32_t* lattice;     // (L+1)^2 lattice -> knot index (for u_ref)
   double* dump;               // nullable
-  uint32_t max_steps;         // safety cap on the steps of one path
+  uint32_t* ticket_counter;   // dynamic schedule: zeroed work counter; nullptr: static stride
 };
 
 // Extras stored after the 4 slot_len G slots of a partial row.
@@ -73,14 +75,15 @@ struct FinalizeParams {
   double* val;
   double* b;
   double* diag;                  // nullable
+  uint32_t* ticket_counter;      // reset to zero for the next assembly (nullable)
 };
 
 // Launchers (defined in assemble.hip).  Return hipSuccess or the launch error.
 hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block,
                            size_t lds_bytes, hipStream_t stream);
 hipError_t launch_finalize(const FinalizeParams& p, hipStream_t stream);
-// Dynamic LDS bytes per workgroup for a given row length and block size.
-size_t assemble_lds_bytes(int row_len, int block);
+// Dynamic LDS bytes per workgroup for a precision, row length and block size.
+size_t assemble_lds_bytes(int precision, int row_len, int block);
 // Kernel attribute query for occupancy-based grid sizing.
 hipError_t assemble_occupancy(int precision, int kind, int block, size_t lds_bytes, int* blocks_per_cu);
 

@@ -77,7 +77,7 @@ def lib():
             "pdd_knot_xy": [C.POINTER(Partition), C.POINTER(Knots), vp],
             "pdd_assemble": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots),
                              C.POINTER(Run), vp, vp, vp, vp, vp],
-            "pdd_set_launch": [vp, i32, i32, i32],
+            "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_last_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)],
             "pdd_set_timing": [vp, i32],
             "pdd_kernel_ms": [vp, C.POINTER(f64), C.POINTER(i32)],
@@ -166,8 +166,9 @@ class Context:
     def sync(self):
         self.check(lib().pdd_sync(self.h))
 
-    def set_launch(self, block=0, grid=0, paths_per_ticket=0):
-        self.check(lib().pdd_set_launch(self.h, block, grid, paths_per_ticket))
+    def set_launch(self, block=0, grid=0, paths_per_ticket=0, schedule="static"):
+        sched = {"static": 0, "dynamic": 1}[schedule]
+        self.check(lib().pdd_set_launch(self.h, block, grid, paths_per_ticket, sched))
 
     def last_launch(self):
         g, b, t = C.c_int32(), C.c_int32(), C.c_int64()

@@ -102,7 +102,7 @@ def test_poisson_small_fp64_same_stream(ctx, rule):
     for k in range(g.n):
         p = paths[k]
         assert np.array_equal(dump[k, :, 0], p["K"][:8])
-        assert np.array_equal(dump[k, :, 6], p["side"][:8])
+        assert np.all(dump[k, :, 6] == k) and np.array_equal(dump[k, :, 7], np.arange(8))
         for col, name in ((1, "x"), (2, "y"), (3, "Y"), (4, "Z"), (5, "Xi")):
             assert np.allclose(dump[k, :, col], p[name][:8], rtol=1e-12, atol=1e-14)
 
