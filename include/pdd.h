@@ -187,6 +187,21 @@ pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partit
                         int32_t* row_ptr, int32_t* col_idx, double* val, double* b,
                         double* diag);
 
+/* ---- solve (eq. 23) -------------------------------------------------------- */
+
+/* Solve G u = b for a CSR matrix (device arrays; row_ptr int32[n+1], col_idx
+ * int32[nnz], val double[nnz], b double[n]; u double[n] receives the
+ * solution, starting from u = 0).  Iterative refinement: the residual
+ * b - G u is formed in float64; each correction is computed by BiCGStab on
+ * float32 vectors (float64 dot products) until the float64 relative residual
+ * ||b - G u||_2 / ||b||_2 <= tol.  *iters receives the BiCGStab iterations
+ * used, *relres the final relative residual (host pointers).  Returns
+ * PDD_ENOTCONV, with the best iterate in u, if max_iter BiCGStab iterations
+ * do not reach tol.  Synchronises the context's stream. */
+pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                     const double* val, const double* b, double* u, double tol, int32_t max_iter,
+                     int32_t* iters, double* relres);
+
 /* ---- launch control and measurement ------------------------------------ */
 
 /* Ticket schedules: STATIC gives wave w the tickets w, w + W, w + 2W, ...

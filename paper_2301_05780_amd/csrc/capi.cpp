@@ -211,6 +211,16 @@ pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partit
   return run_assemble(ctx, job);
 }
 
+pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                     const double* val, const double* b, double* u, double tol, int32_t max_iter,
+                     int32_t* iters, double* relres) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_solve: null context");
+  if (n < 1 || !row_ptr || !col_idx || !val || !b || !u || !iters || !relres)
+    return fail(ctx, PDD_EINVAL, "pdd_solve: need n >= 1 and non-null arrays");
+  if (!(tol > 0.0) || max_iter < 1) return fail(ctx, PDD_EINVAL, "pdd_solve: need tol > 0 and max_iter >= 1");
+  return run_solve(ctx, n, row_ptr, col_idx, val, b, u, tol, max_iter, iters, relres);
+}
+
 pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket,
                           int32_t schedule) {
   if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_launch: null context");

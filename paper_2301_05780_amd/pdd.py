@@ -78,6 +78,7 @@ def lib():
             "pdd_assemble": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots),
                              C.POINTER(Run), vp, vp, vp, vp, vp],
             "pdd_set_launch": [vp, i32, i32, i32, i32],
+            "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_last_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)],
             "pdd_set_timing": [vp, i32],
             "pdd_kernel_ms": [vp, C.POINTER(f64), C.POINTER(i32)],
@@ -183,6 +184,19 @@ class Context:
         ms, n = C.c_double(), C.c_int32()
         self.check(lib().pdd_kernel_ms(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    # ---- solve --------------------------------------------------------------
+    def solve(self, row_ptr, col_idx, val, b, u=None, tol=1e-10, max_iter=2000, check=True):
+        """Solve G u = b (device tensors).  Returns (u, iterations, relative residual)."""
+        n = b.numel()
+        if u is None:
+            u = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        it, rr = C.c_int32(), C.c_double()
+        st = lib().pdd_solve(self.h, n, _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(b), _ptr(u),
+                             float(tol), int(max_iter), C.byref(it), C.byref(rr))
+        if check or st != ENOTCONV:
+            self.check(st)
+        return u, it.value, rr.value
 
     # ---- assembly ----------------------------------------------------------
     def coeffs_of(self, w, lut=None):
