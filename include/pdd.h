@@ -202,6 +202,46 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
                      const double* val, const double* b, double* u, double tol, int32_t max_iter,
                      int32_t* iters, double* relres);
 
+/* ---- control-variate network (eqs. 11, 37-38) ---------------------------- */
+
+/* v and/or grad v of the 2-64-64-1 tanh network at n points (float32, device
+ * arrays: params[PDD_MLP_PARAMS], xy[2n], v[n] nullable, grad[2n] nullable). */
+pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad);
+
+/* Gradient of the loss L = mean_i (v(x_i) - t_i)^2 / 2 over the n points with
+ * respect to all parameters (device: grad[PDD_MLP_PARAMS]; loss[1] nullable),
+ * computed by the trainer's forward and backward pass in float32. */
+pdd_status pdd_mlp_grad(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, const float* target,
+                        float* grad, float* loss);
+
+/* `steps` Adam updates (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, the
+ * step counter continuing from step0) of params in place; step s uses the
+ * points order[(s batch + i) mod n_order], i < batch, of the n_points pairs
+ * (xy[2 n_points], target[n_points]; order entries outside [0, n_points) are
+ * skipped; the loss is still averaged over `batch`).  adam_m / adam_s are
+ * the moment vectors (device, PDD_MLP_PARAMS each, zero before the first
+ * call); losses[steps] (nullable) receives each step's loss.  One workgroup
+ * runs the whole sequence (the steps are sequential). */
+pdd_status pdd_mlp_train(pdd_ctx* ctx, float* params, float* adam_m, float* adam_s, int64_t n_points,
+                         const float* xy, const float* target, const int32_t* order, int64_t n_order, int32_t batch,
+                         int32_t steps, int32_t step0, float lr, float* losses);
+
+/* grad v on the lut_n x lut_n node grid of the partition's domain, the table
+ * read by PDD_CV_GRAD_LUT: grad_lut[(j lut_n + i) 2 + d] (device). */
+pdd_status pdd_mlp_bake_grad_lut(pdd_ctx* ctx, const float* params, const pdd_partition* part, int32_t lut_n,
+                                 float* grad_lut);
+
+/* Training pairs from the method's own paths: for every knot k and path
+ * p < paths_per_knot (same random stream and float32 step as the production
+ * assembly), the first points_per_path iterates X_n receive the tail score
+ * (Z_K + Y_K u(exit) - Z_n) / Y_n, u at the exit interpolated from u0 (device,
+ * the solved knot values) or the boundary datum.  Outputs (device, slot
+ * (k paths_per_knot + p) points_per_path + n): xy[2 slots], target[slots];
+ * slots past a path's exit get a NaN target.  run.cv must be NULL. */
+pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                                const pdd_knots* knots, const pdd_run* run, const double* u0, int32_t paths_per_knot,
+                                int32_t points_per_path, float* xy, float* target);
+
 /* ---- launch control and measurement ------------------------------------ */
 
 /* Ticket schedules: STATIC gives wave w the tickets w, w + W, w + 2W, ...

@@ -113,6 +113,30 @@ class NetworkCV:
         return g[:, 0], g[:, 1]
 
 
+class GradLutCV:
+    """grad v read by bilinear interpolation from a float32 table [n, n, 2] on the
+    node-centred grid of the domain (the paper stores F on a look-up table,
+    Sec. 4.2); the table is an input, its values promoted to float64."""
+
+    def __init__(self, table, domain):
+        self.t = np.asarray(table, dtype=np.float32).astype(np.float64)
+        self.n = self.t.shape[0]
+        self.domain = tuple(float(v) for v in domain)
+
+    def grad(self, x, y):
+        n = self.n
+        x0, x1, y0, y1 = self.domain
+        fx = np.clip((x - x0) / (x1 - x0) * (n - 1), 0.0, n - 1)
+        fy = np.clip((y - y0) / (y1 - y0) * (n - 1), 0.0, n - 1)
+        i = np.minimum(np.floor(fx), n - 2).astype(np.int64)
+        j = np.minimum(np.floor(fy), n - 2).astype(np.int64)
+        tx = (fx - i)[..., None]
+        ty = (fy - j)[..., None]
+        t = self.t
+        v = (1.0 - ty) * ((1.0 - tx) * t[j, i] + tx * t[j, i + 1]) + ty * ((1.0 - tx) * t[j + 1, i] + tx * t[j + 1, i + 1])
+        return v[..., 0], v[..., 1]
+
+
 class ExactGradientCV:
     """F built from the exact solution's gradient: the zero-variance choice of eq. (11)."""
 

@@ -26,6 +26,7 @@
 #include <type_traits>
 
 #include "device_common.h"
+#include "net_grad.h"
 
 namespace pdd {
 
@@ -46,6 +47,14 @@ template <typename R>
 struct ExitRec {
   R x, y, Y, bp;       // exit iterate, Y_K, Z_K + Xi_K
 };
+
+// block-level LDS for the control-variate network (staged once per workgroup)
+template <bool F64, int CV>
+constexpr size_t net_lds_bytes() {
+  if constexpr (CV != PDD_CV_NETWORK) return 0;
+  else if constexpr (F64) return ((MLP_PARAMS * sizeof(float) + 15) / 16) * 16;
+  else return ((sizeof(NetLds) + 15) / 16) * 16;
+}
 
 // per-wave LDS bytes: two row headers, the exit queue (records + meta words), two tally rows
 template <typename R>
@@ -87,71 +96,6 @@ __device__ __forceinline__ uint32_t to_uniform_u(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-// One Euler-Maruyama step of eq. (9) with coefficients frozen at the left point.
-template <int KIND, typename R>
-__device__ __forceinline__ void em_step(const AsmParams& P, R z0, R z1, R& x, R& y, R& Y, R& Z) {
-  using T = Traits<KIND>;
-  Coef<R> c;
-  coef_at<KIND>(P.coef, x, y, c);
-  if constexpr (std::is_same<R, double>::value) {
-#pragma clang fp contract(off)
-    const double sq = P.sqrt_h, h = P.h;
-    const double dWx = sq * z0, dWy = sq * z1;
-    double nx = x, ny = y;
-    if constexpr (T::drift) { nx = nx + c.dx * h; ny = ny + c.dy * h; }
-    if constexpr (T::offdiag) {
-      nx = nx + (c.sxx * dWx + c.sxy * dWy);
-      ny = ny + (c.sxy * dWx + c.syy * dWy);
-    } else {
-      nx = nx + c.sxx * dWx;
-      ny = ny + c.syy * dWy;
-    }
-    const double nZ = Z - c.f * Y * h;
-    if constexpr (T::reaction) Y = Y * (1.0 + c.c * h);
-    x = nx; y = ny; Z = nZ;
-  } else {
-    const float sq = (float)P.sqrt_h, h = (float)P.h;
-    const float dWx = sq * z0, dWy = sq * z1;
-    float nx = x, ny = y;
-    if constexpr (T::drift) { nx = nx + c.dx * h; ny = ny + c.dy * h; }
-    if constexpr (T::offdiag) {
-      nx = nx + (c.sxx * dWx + c.sxy * dWy);
-      ny = ny + (c.sxy * dWx + c.syy * dWy);
-    } else {
-      nx = nx + c.sxx * dWx;
-      ny = ny + c.syy * dWy;
-    }
-    const float nZ = Z - c.f * Y * h;
-    if constexpr (T::reaction) Y = Y * (1.0f + c.c * h);
-    x = nx; y = ny; Z = nZ;
-  }
-}
-
-// Exit threshold of side o for the knot in `d` (NAIVE: the side line; GM: the
-// line shifted inwards by c_GM sqrt(a_nn) sqrt(h), a_nn = N^T A N evaluated on
-// the side at the knot's along-line coordinate; for every analytic family a_nn
-// of a vertical side depends on x only and of a horizontal side on y only).
-// Returned as the strict threshold of the test that flags side o.
-template <int KIND, typename R>
-__device__ R exit_threshold(const AsmParams& P, const KnotDesc& d, int o) {
-  const double line = d.line[o];
-  if (P.exit_rule == PDD_EXIT_NAIVE) return (R)line;
-  const bool vert = (o == 0 || o == 2);
-  Coef<R> c;
-  const R px = vert ? (R)line : (R)d.sx;
-  const R py = vert ? (R)d.sy : (R)line;
-  coef_at<KIND>(P.coef, px, py, c);
-  R thr;
-  {
-#pragma clang fp contract(off)
-    const R ann = vert ? (c.sxx * c.sxx + c.sxy * c.sxy) : (c.sxy * c.sxy + c.syy * c.syy);
-    const R delta = (R)kGM * sqrt(ann) * (R)P.sqrt_h;
-    thr = (o < 2) ? (R)line - delta : (R)line + delta;
-  }
-  // x >= thr  <=>  x > nextafter(thr, -inf);  x <= thr  <=>  x < nextafter(thr, +inf)
-  return (o < 2) ? nextafter(thr, (R)-INFINITY) : nextafter(thr, (R)INFINITY);
-}
-
 // Per-buffer uniform values used at refill (kept in scalar registers).
 template <typename R>
 struct BufU {
@@ -159,15 +103,27 @@ struct BufU {
   uint32_t knot, inst;
 };
 
-template <int KIND, bool F64>
+template <int KIND, bool F64, int CV>
 __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
   using R = typename std::conditional<F64, double, float>::type;
+  constexpr bool CVON = CV != PDD_CV_NONE;
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int waves_per_block = blockDim.x >> 6;
   const int RL = P.row_len, SL = P.slot_len;
-  unsigned char* wbase = reinterpret_cast<unsigned char*>(smem) + (size_t)wid * wave_lds_bytes<R>(RL);
+  unsigned char* lds0 = reinterpret_cast<unsigned char*>(smem);
+  NetLds* NL = reinterpret_cast<NetLds*>(lds0);            // network, CV == NETWORK (float32)
+  float* TH = reinterpret_cast<float*>(lds0);              // network, CV == NETWORK (float64 mode)
+  if constexpr (CV == PDD_CV_NETWORK) {
+    if constexpr (F64) {
+      for (int i = threadIdx.x; i < MLP_PARAMS; i += blockDim.x) TH[i] = P.cv_params[i];
+    } else {
+      net_stage(NL, P.cv_params);
+    }
+    __syncthreads();
+  }
+  unsigned char* wbase = lds0 + net_lds_bytes<F64, CV>() + (size_t)wid * wave_lds_bytes<R>(RL);
   WaveBuf* B = reinterpret_cast<WaveBuf*>(wbase);
   ExitRec<R>* Q = reinterpret_cast<ExitRec<R>*>(wbase + 2 * sizeof(WaveBuf));
   uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>));
@@ -217,14 +173,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         bool fE = r.x > (R)W.ebox[0], fN = r.y > (R)W.ebox[1];
         bool fW = r.x < (R)W.ebox[2], fS = r.y < (R)W.ebox[3];
         if (forced) fE = fN = fW = fS = true;
-        // side: the tripped side whose line is closest (ties: E, N, W, S)
-        const R lE = (R)d.line[0], lN = (R)d.line[1], lW = (R)d.line[2], lS = (R)d.line[3];
-        o = -1;
-        R best = 0;
-        if (fE) { o = 0; best = fabs(r.x - lE); }
-        if (fN) { const R v = fabs(r.y - lN); if (o < 0 || v < best) { o = 1; best = v; } }
-        if (fW) { const R v = fabs(r.x - lW); if (o < 0 || v < best) { o = 2; best = v; } }
-        if (fS) { const R v = fabs(r.y - lS); if (o < 0 || v < best) { o = 3; best = v; } }
+        o = choose_side<R>(r.x, r.y, fE, fN, fW, fS, d.line);
         const bool vert = (o == 0 || o == 2);
         const R along = vert ? r.y : r.x;
         const R lpos = (R)d.line[o];
@@ -240,15 +189,11 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
           }
         } else {
           // interface side: hat weights on the line lattice, clamped to the stencil range
-          const R a0 = vert ? (R)P.y0 : (R)P.x0;
           const int clo = d.clo[o], chi = d.chi[o];
-          R t;
-          if constexpr (F64) t = (along - a0) / (vert ? P.dy : P.dx);
-          else t = (along - a0) * (vert ? P.inv_dy : P.inv_dx);
-          t = fmin(fmax(t, (R)clo), (R)chi);
-          const R i0 = fmin(floor(t), (R)(chi - 1));
-          const R w = t - i0;
-          const int q0 = (int)i0;
+          int q0;
+          R w;
+          hat_weights<R, F64>(along, vert ? (R)P.y0 : (R)P.x0, vert ? P.dy : P.dx, vert ? P.inv_dy : P.inv_dx,
+                              clo, chi, q0, w);
           double* row = rows + (size_t)rb * RL + o * SL;
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
@@ -392,18 +337,52 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
     bool ex = false;
     bool forced = false;
     uint32_t K = 0;
-    if (active) {
+    if constexpr (CV == PDD_CV_NETWORK && !F64) {
+      // the network gradient is a wave-wide MFMA product: evaluate it with
+      // every lane active, at each lane's left point, before each half step
+      U4 r{};
+      float gx, gy;
+      net_grad_mfma(NL, x, y, gx, gy);
+      if (active) {
+        r = philox10(j, p, kn, inst, P.key0, P.key1);
+        R z0, z1;
+        box_muller(uniform32(r.a), uniform32(r.b), z0, z1);
+        em_step<KIND, R, true>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+        K = 2 * j + 1;
+        ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
+      }
+      net_grad_mfma(NL, x, y, gx, gy);
+      if (active) {
+        if (!ex) {
+          R z0, z1;
+          box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
+          em_step<KIND, R, true>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+          K = 2 * j + 2;
+          ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
+        }
+        ++j;
+        if (!ex && 2 * j >= MAX_STEPS) { ex = true; forced = true; }
+      }
+    } else if (active) {
+      // grad v at the current (left) point for the per-lane control variates
+      auto cv_grad = [&](R& gx, R& gy) __attribute__((always_inline)) {
+        if constexpr (CV == PDD_CV_GRAD_LUT) grad_lut(P, x, y, gx, gy);
+        else if constexpr (CV == PDD_CV_NETWORK) net_grad_f64(TH, x, y, gx, gy);
+        else { gx = 0; gy = 0; }
+      };
       const U4 r = philox10(j, p, kn, inst, P.key0, P.key1);
-      R z0, z1;
+      R z0, z1, gx, gy;
       if constexpr (F64) box_muller(uniform64(r.a), uniform64(r.b), z0, z1);
       else box_muller(uniform32(r.a), uniform32(r.b), z0, z1);
-      em_step<KIND, R>(P, z0, z1, x, y, Y, Z);
+      cv_grad(gx, gy);
+      em_step<KIND, R, CVON>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
       K = 2 * j + 1;
       ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
       if (!ex) {
         if constexpr (F64) box_muller(uniform64(r.c), uniform64(r.d), z0, z1);
         else box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
-        em_step<KIND, R>(P, z0, z1, x, y, Y, Z);
+        cv_grad(gx, gy);
+        em_step<KIND, R, CVON>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
         K = 2 * j + 2;
         ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
       }
@@ -493,45 +472,62 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
   }
 }
 
-template <int KIND, bool F64>
+template <int KIND, bool F64, int CV>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_assemble<KIND, F64>);
+  return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV>);
+}
+
+template <bool F64, int CV>
+const void* pick_kind(int kind) {
+  switch (kind) {
+    case PDD_COEF_POISSON: return kernel_ptr<PDD_COEF_POISSON, F64, CV>();
+    case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64, CV>();
+    case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64, CV>();
+    case PDD_COEF_LUT: return kernel_ptr<PDD_COEF_LUT, F64, CV>();
+    default: break;
+  }
+  if constexpr (CV == PDD_CV_NONE) {
+    if (kind == PDD_COEF_CONSTSOL) return kernel_ptr<PDD_COEF_CONSTSOL, F64, CV>();
+    if (kind == PDD_COEF_EXITTIME) return kernel_ptr<PDD_COEF_EXITTIME, F64, CV>();
+  }
+  return nullptr;
 }
 
 template <bool F64>
-const void* pick(int kind) {
-  switch (kind) {
-    case PDD_COEF_POISSON: return kernel_ptr<PDD_COEF_POISSON, F64>();
-    case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64>();
-    case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64>();
-    case PDD_COEF_LUT: return kernel_ptr<PDD_COEF_LUT, F64>();
-    case PDD_COEF_CONSTSOL: return kernel_ptr<PDD_COEF_CONSTSOL, F64>();
-    case PDD_COEF_EXITTIME: return kernel_ptr<PDD_COEF_EXITTIME, F64>();
+const void* pick(int kind, int cv) {
+  switch (cv) {
+    case PDD_CV_NONE: return pick_kind<F64, PDD_CV_NONE>(kind);
+    case PDD_CV_NETWORK: return pick_kind<F64, PDD_CV_NETWORK>(kind);
+    case PDD_CV_GRAD_LUT: return pick_kind<F64, PDD_CV_GRAD_LUT>(kind);
     default: return nullptr;
   }
 }
 
-const void* assemble_kernel(int precision, int kind) {
-  return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind) : pick<false>(kind);
+const void* assemble_kernel(int precision, int kind, int cv) {
+  return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind, cv) : pick<false>(kind, cv);
 }
 
 }  // namespace
 
-size_t assemble_lds_bytes(int precision, int row_len, int block) {
+size_t assemble_lds_bytes(int precision, int row_len, int block, int cv_mode) {
   const size_t waves = (size_t)block / 64;
-  return waves * (precision == PDD_FP64_SAME_STREAM ? wave_lds_bytes<double>(row_len)
-                                                    : wave_lds_bytes<float>(row_len));
+  if (precision == PDD_FP64_SAME_STREAM) {
+    const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<true, PDD_CV_NETWORK>() : 0;
+    return net + waves * wave_lds_bytes<double>(row_len);
+  }
+  const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<false, PDD_CV_NETWORK>() : 0;
+  return net + waves * wave_lds_bytes<float>(row_len);
 }
 
-hipError_t assemble_occupancy(int precision, int kind, int block, size_t lds_bytes, int* blocks_per_cu) {
-  const void* f = assemble_kernel(precision, kind);
+hipError_t assemble_occupancy(int precision, int kind, int cv_mode, int block, size_t lds_bytes, int* blocks_per_cu) {
+  const void* f = assemble_kernel(precision, kind, cv_mode);
   if (!f) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block, size_t lds_bytes,
                            hipStream_t stream) {
-  const void* f = assemble_kernel(precision, p.coef.kind);
+  const void* f = assemble_kernel(precision, p.coef.kind, p.cv_mode);
   if (!f) return hipErrorInvalidValue;
   AsmParams arg = p;
   void* args[] = {&arg};

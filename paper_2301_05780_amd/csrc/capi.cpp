@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -11,6 +12,7 @@
 #include "context.h"
 #include "geometry.h"
 #include "kernels.h"
+#include "mlp.h"
 
 using namespace pdd;
 
@@ -219,6 +221,75 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
     return fail(ctx, PDD_EINVAL, "pdd_solve: need n >= 1 and non-null arrays");
   if (!(tol > 0.0) || max_iter < 1) return fail(ctx, PDD_EINVAL, "pdd_solve: need tol > 0 and max_iter >= 1");
   return run_solve(ctx, n, row_ptr, col_idx, val, b, u, tol, max_iter, iters, relres);
+}
+
+pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_eval: null context");
+  if (!params || !xy || n < 0 || (!v && !grad)) return fail(ctx, PDD_EINVAL, "pdd_mlp_eval: bad arguments");
+  if (n == 0) return PDD_OK;
+  return run_mlp_eval(ctx, params, n, xy, v, grad);
+}
+
+pdd_status pdd_mlp_grad(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, const float* target,
+                        float* grad, float* loss) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_grad: null context");
+  if (!params || !xy || !target || !grad || n < 1 || n > INT32_MAX)
+    return fail(ctx, PDD_EINVAL, "pdd_mlp_grad: bad arguments");
+  // identity order over the n points, one batch of n
+  hipError_t e = ctx->mlp_scratch.reserve((size_t)n * sizeof(int32_t));
+  if (e != hipSuccess) return check_hip(ctx, e, "hipMalloc(mlp scratch)");
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  e = hipMemcpy(ctx->mlp_scratch.ptr, order.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return check_hip(ctx, e, "upload order");
+  return run_mlp_train(ctx, const_cast<float*>(params), nullptr, nullptr, n, xy, target, ctx->mlp_scratch.as<int32_t>(),
+                       n, (int32_t)n, 1, 0, 0.0f, loss, grad);
+}
+
+pdd_status pdd_mlp_train(pdd_ctx* ctx, float* params, float* adam_m, float* adam_s, int64_t n_points,
+                         const float* xy, const float* target, const int32_t* order, int64_t n_order, int32_t batch,
+                         int32_t steps, int32_t step0, float lr, float* losses) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_train: null context");
+  if (!params || !adam_m || !adam_s || !xy || !target || !order || n_points < 1 || n_order < 1 || batch < 1 ||
+      steps < 0 || step0 < 0 || !(lr > 0.0f))
+    return fail(ctx, PDD_EINVAL, "pdd_mlp_train: bad arguments");
+  if (steps == 0) return PDD_OK;
+  return run_mlp_train(ctx, params, adam_m, adam_s, n_points, xy, target, order, n_order, batch, steps, step0, lr,
+                       losses, nullptr);
+}
+
+pdd_status pdd_mlp_bake_grad_lut(pdd_ctx* ctx, const float* params, const pdd_partition* part, int32_t lut_n,
+                                 float* grad_lut) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_bake_grad_lut: null context");
+  if (!params || !part || !grad_lut || lut_n < 2 || lut_n > 65536 || !(part->x1 > part->x0) || !(part->y1 > part->y0))
+    return fail(ctx, PDD_EINVAL, "pdd_mlp_bake_grad_lut: bad arguments");
+  return run_mlp_bake(ctx, params, *part, lut_n, grad_lut);
+}
+
+pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                                const pdd_knots* knots, const pdd_run* run, const double* u0, int32_t paths_per_knot,
+                                int32_t points_per_path, float* xy, float* target) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_collect_training: null context");
+  if (!coeffs || !part || !knots || !run || !u0 || !xy || !target || paths_per_knot < 1 || points_per_path < 1)
+    return fail(ctx, PDD_EINVAL, "pdd_collect_training: bad arguments");
+  if (run->cv && run->cv->mode != PDD_CV_NONE)
+    return fail(ctx, PDD_EINVAL, "pdd_collect_training: collect from plain paths (run.cv must be NULL)");
+  pdd_status st = validate_run(ctx, *coeffs, *run);
+  if (st != PDD_OK) return st;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  GeoCache* gc = nullptr;
+  if ((st = get_geometry(ctx, *part, *knots, &gc)) != PDD_OK) return st;
+  if ((st = get_lattice(ctx, gc)) != PDD_OK) return st;
+  const int64_t slots = gc->g.n * (int64_t)paths_per_knot * points_per_path;
+  if (slots > ((int64_t)1 << 31)) return fail(ctx, PDD_EINVAL, "pdd_collect_training: too many record slots");
+  if ((e = ctx->collect_scratch.reserve((size_t)slots * 2 * sizeof(float))) != hipSuccess)
+    return check_hip(ctx, e, "hipMalloc(collect scratch)");
+  AsmParams P;
+  fill_asm_params(*gc, *coeffs, *run, P);
+  e = launch_collect(P, gc->g.n, paths_per_knot, points_per_path, run->instance, u0, xy,
+                     ctx->collect_scratch.as<float>(), target, ctx->stream);
+  return check_hip(ctx, e, "launch collect");
 }
 
 pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket,

@@ -68,6 +68,7 @@ struct pdd_ctx {
   std::unique_ptr<pdd::TicketCache> tickets;
   pdd::DeviceBuffer partial;
   pdd::DeviceBuffer solve_scratch, solve_flag;
+  pdd::DeviceBuffer collect_scratch, mlp_scratch;
   // launch overrides (0 = automatic), set by the tuner
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
   int schedule = PDD_SCHEDULE_STATIC;
@@ -90,6 +91,7 @@ pdd_status check_hip(pdd_ctx* ctx, hipError_t e, const char* what);
 pdd_status get_geometry(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn, GeoCache** out);
 pdd_status get_lattice(pdd_ctx* ctx, GeoCache* gc);
 pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r);
+void fill_asm_params(const GeoCache& gc, const pdd_coeffs& co, const pdd_run& run, AsmParams& P);
 pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);
 pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                      const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres);

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace pdd {
@@ -247,6 +249,128 @@ __device__ __forceinline__ float g_at(float x, float y) {
   else if constexpr (KIND == PDD_COEF_CONSTSOL) return 1.0f;
   else if constexpr (KIND == PDD_COEF_EXITTIME) return 0.0f;
   else return sin_rev(0.5f * x) * sin_rev(0.5f * y) + x * x * y;
+}
+
+// ---- path step and exit rules (shared by the assembly, collection and
+// point-evaluation kernels) ------------------------------------------------
+
+// One Euler-Maruyama step of eq. (9) with coefficients frozen at the left
+// point.  With the control variate (CVON), Xi gains -Y (sigma^T grad v) . dW
+// (eq. 37), grad v = (gx, gy) taken at the same left point.
+template <int KIND, typename R, bool CVON = false>
+__device__ __forceinline__ void em_step(const AsmParams& P, R z0, R z1, R& x, R& y, R& Y, R& Z, R gx = 0, R gy = 0,
+                                        R* Xi = nullptr) {
+  using T = Traits<KIND>;
+  Coef<R> c;
+  coef_at<KIND>(P.coef, x, y, c);
+  if constexpr (std::is_same<R, double>::value) {
+#pragma clang fp contract(off)
+    const double sq = P.sqrt_h, h = P.h;
+    const double dWx = sq * z0, dWy = sq * z1;
+    if constexpr (CVON) {
+      double Fx, Fy;
+      if constexpr (T::offdiag) {
+        Fx = c.sxx * gx + c.sxy * gy;
+        Fy = c.sxy * gx + c.syy * gy;
+      } else {
+        Fx = c.sxx * gx;
+        Fy = c.syy * gy;
+      }
+      *Xi = *Xi - Y * (Fx * dWx + Fy * dWy);
+    }
+    double nx = x, ny = y;
+    if constexpr (T::drift) { nx = nx + c.dx * h; ny = ny + c.dy * h; }
+    if constexpr (T::offdiag) {
+      nx = nx + (c.sxx * dWx + c.sxy * dWy);
+      ny = ny + (c.sxy * dWx + c.syy * dWy);
+    } else {
+      nx = nx + c.sxx * dWx;
+      ny = ny + c.syy * dWy;
+    }
+    const double nZ = Z - c.f * Y * h;
+    if constexpr (T::reaction) Y = Y * (1.0 + c.c * h);
+    x = nx; y = ny; Z = nZ;
+  } else {
+    const float sq = (float)P.sqrt_h, h = (float)P.h;
+    const float dWx = sq * z0, dWy = sq * z1;
+    if constexpr (CVON) {
+      float Fx, Fy;
+      if constexpr (T::offdiag) {
+        Fx = c.sxx * gx + c.sxy * gy;
+        Fy = c.sxy * gx + c.syy * gy;
+      } else {
+        Fx = c.sxx * gx;
+        Fy = c.syy * gy;
+      }
+      *Xi = *Xi - Y * (Fx * dWx + Fy * dWy);
+    }
+    float nx = x, ny = y;
+    if constexpr (T::drift) { nx = nx + c.dx * h; ny = ny + c.dy * h; }
+    if constexpr (T::offdiag) {
+      nx = nx + (c.sxx * dWx + c.sxy * dWy);
+      ny = ny + (c.sxy * dWx + c.syy * dWy);
+    } else {
+      nx = nx + c.sxx * dWx;
+      ny = ny + c.syy * dWy;
+    }
+    const float nZ = Z - c.f * Y * h;
+    if constexpr (T::reaction) Y = Y * (1.0f + c.c * h);
+    x = nx; y = ny; Z = nZ;
+  }
+}
+
+// Exit threshold of side o for the knot in `d` (NAIVE: the side line; GM: the
+// line shifted inwards by c_GM sqrt(a_nn) sqrt(h), a_nn = N^T A N evaluated on
+// the side at the knot's along-line coordinate; for every analytic family a_nn
+// of a vertical side depends on x only and of a horizontal side on y only).
+// Returned as the strict threshold of the test that flags side o.
+template <int KIND, typename R>
+__device__ __forceinline__ R exit_threshold(const AsmParams& P, const KnotDesc& d, int o) {
+  const double line = d.line[o];
+  if (P.exit_rule == PDD_EXIT_NAIVE) return (R)line;
+  const bool vert = (o == 0 || o == 2);
+  Coef<R> c;
+  const R px = vert ? (R)line : (R)d.sx;
+  const R py = vert ? (R)d.sy : (R)line;
+  coef_at<KIND>(P.coef, px, py, c);
+  R thr;
+  {
+#pragma clang fp contract(off)
+    const R ann = vert ? (c.sxx * c.sxx + c.sxy * c.sxy) : (c.sxy * c.sxy + c.syy * c.syy);
+    const R delta = (R)kGM * sqrt(ann) * (R)P.sqrt_h;
+    thr = (o < 2) ? (R)line - delta : (R)line + delta;
+  }
+  // x >= thr  <=>  x > nextafter(thr, -inf);  x <= thr  <=>  x < nextafter(thr, +inf)
+  return (o < 2) ? nextafter(thr, (R)-INFINITY) : nextafter(thr, (R)INFINITY);
+}
+
+
+// Side chosen at an exit: among the tripped sides, the one whose grid line is
+// closest to the exit iterate; ties go to the first of E, N, W, S.  `line`
+// holds the physical coordinate of each side's line.
+template <typename R>
+__device__ __forceinline__ int choose_side(R x, R y, bool fE, bool fN, bool fW, bool fS, const double* line) {
+  int o = -1;
+  R best = 0;
+  if (fE) { o = 0; best = fabs(x - (R)line[0]); }
+  if (fN) { const R v = fabs(y - (R)line[1]); if (o < 0 || v < best) { o = 1; best = v; } }
+  if (fW) { const R v = fabs(x - (R)line[2]); if (o < 0 || v < best) { o = 2; best = v; } }
+  if (fS) { const R v = fabs(y - (R)line[3]); if (o < 0 || v < best) { o = 3; best = v; } }
+  return o;
+}
+
+// Hat-function interpolation on an interface line: lattice coordinate t of the
+// exit point clamped to [clo, chi], i0 = min(floor t, chi - 1), w = t - i0;
+// lattice points i0 and i0 + 1 carry 1 - w and w.
+template <typename R, bool F64>
+__device__ __forceinline__ void hat_weights(R along, R a0, double d, float inv_d, int clo, int chi, int& q0, R& w) {
+  R t;
+  if constexpr (F64) t = (along - a0) / (R)d;
+  else t = (along - a0) * (R)inv_d;
+  t = fmin(fmax(t, (R)clo), (R)chi);
+  const R i0 = fmin(floor(t), (R)(chi - 1));
+  w = t - i0;
+  q0 = (int)i0;
 }
 
 }  // namespace pdd

@@ -35,11 +35,52 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
     return bad(ctx, PDD_EINVAL, "run.n_paths: need 1 <= n_paths <= 2^31 - 1");
   if (r.dump_paths < 0 || (r.dump_paths > 0 && !r.dump))
     return bad(ctx, PDD_EINVAL, "run.dump_paths: need dump_paths >= 0 and a dump buffer when > 0");
-  if (r.cv && r.cv->mode != PDD_CV_NONE)
-    return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variate not available in this entry point");
+  if (r.cv) {
+    const pdd_cv& cv = *r.cv;
+    if (cv.mode < PDD_CV_NONE || cv.mode > PDD_CV_GRAD_LUT) return bad(ctx, PDD_EINVAL, "run.cv.mode: unknown mode");
+    if (cv.mode == PDD_CV_NETWORK && !cv.params) return bad(ctx, PDD_EINVAL, "run.cv: network mode needs params");
+    if (cv.mode == PDD_CV_GRAD_LUT && (!cv.grad_lut || cv.lut_n < 2 || cv.lut_n > 65536))
+      return bad(ctx, PDD_EINVAL, "run.cv: grad-table mode needs a table and 2 <= lut_n <= 65536");
+    if (cv.mode != PDD_CV_NONE && (c.kind == PDD_COEF_CONSTSOL || c.kind == PDD_COEF_EXITTIME))
+      return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variates are built for the poisson, varcoef, amplitude and LUT families");
+  }
   if (c.kind == PDD_COEF_LUT && r.exit_rule == PDD_EXIT_GM)
     return bad(ctx, PDD_EUNSUPPORTED, "LUT coefficients with the Gobet-Menozzi rule are not implemented");
   return PDD_OK;
+}
+
+void fill_asm_params(const GeoCache& gcr, const pdd_coeffs& co, const pdd_run& run, AsmParams& P) {
+  const Geometry& g = gcr.g;
+  std::memset(&P, 0, sizeof(P));
+  P.desc = gcr.desc.as<KnotDesc>();
+  P.L = g.L;
+  P.key0 = (uint32_t)(run.seed & 0xFFFFFFFFu);
+  P.key1 = (uint32_t)(run.seed >> 32);
+  P.exit_rule = run.exit_rule;
+  P.h = run.h;
+  P.sqrt_h = std::sqrt(run.h);
+  P.x0 = g.x0; P.x1 = g.x1; P.y0 = g.y0; P.y1 = g.y1; P.dx = g.dx; P.dy = g.dy;
+  P.inv_dx = (float)(1.0 / g.dx);
+  P.inv_dy = (float)(1.0 / g.dy);
+  P.coef.kind = co.kind;
+  P.coef.lut_n = co.lut_n;
+  P.coef.a = co.param[0];
+  P.coef.lut = co.lut;
+  P.coef.x0 = g.x0; P.coef.x1 = g.x1; P.coef.y0 = g.y0; P.coef.y1 = g.y1;
+  if (co.kind == PDD_COEF_LUT) {
+    P.coef.lut_sx = (float)((co.lut_n - 1) / (g.x1 - g.x0));
+    P.coef.lut_sy = (float)((co.lut_n - 1) / (g.y1 - g.y0));
+  }
+  P.u_ref = run.u_ref;
+  P.lattice = gcr.lattice.as<int32_t>();
+  P.cv_mode = run.cv ? run.cv->mode : PDD_CV_NONE;
+  if (P.cv_mode == PDD_CV_NETWORK) P.cv_params = run.cv->params;
+  if (P.cv_mode == PDD_CV_GRAD_LUT) {
+    P.cv_lut = run.cv->grad_lut;
+    P.cv_lut_n = run.cv->lut_n;
+    P.cv_lut_sx = (float)((run.cv->lut_n - 1) / (g.x1 - g.x0));
+    P.cv_lut_sy = (float)((run.cv->lut_n - 1) / (g.y1 - g.y0));
+  }
 }
 
 pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
@@ -68,15 +109,16 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   // launch shape
   const int slot_len = g.slot_len;
   const int row_len = 4 * slot_len + EX_COUNT;
+  const int cv_mode = run.cv ? run.cv->mode : PDD_CV_NONE;
   int block = ctx->force_block ? ctx->force_block : 256;
-  size_t lds = assemble_lds_bytes(run.precision, row_len, block);
+  size_t lds = assemble_lds_bytes(run.precision, row_len, block, cv_mode);
   while (lds > 65536 && block > 64) {
     block /= 2;
-    lds = assemble_lds_bytes(run.precision, row_len, block);
+    lds = assemble_lds_bytes(run.precision, row_len, block, cv_mode);
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;
-  e = assemble_occupancy(run.precision, job.coeffs.kind, block, lds, &per_cu);
+  e = assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, block, lds, &per_cu);
   if (e != hipSuccess) return check_hip(ctx, e, "occupancy query");
   per_cu = std::max(per_cu, 1);
   int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
@@ -149,33 +191,14 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     return check_hip(ctx, e, "copy col_idx");
 
   AsmParams P;
-  std::memset(&P, 0, sizeof(P));
-  P.desc = gc->desc.as<KnotDesc>();
+  fill_asm_params(*gc, job.coeffs, run, P);
   P.tickets = tc->tickets.as<Ticket>();
   P.order = tc->order.as<int32_t>();
   P.n_tickets = (int32_t)tc->n_tickets;
   P.row_len = row_len;
   P.slot_len = slot_len;
-  P.L = g.L;
   P.partial = ctx->partial.as<double>();
-  P.key0 = (uint32_t)(run.seed & 0xFFFFFFFFu);
-  P.key1 = (uint32_t)(run.seed >> 32);
-  P.exit_rule = run.exit_rule;
   P.dump_paths = run.dump_paths;
-  P.h = run.h;
-  P.sqrt_h = std::sqrt(run.h);
-  P.x0 = g.x0; P.x1 = g.x1; P.y0 = g.y0; P.y1 = g.y1; P.dx = g.dx; P.dy = g.dy;
-  P.coef.kind = job.coeffs.kind;
-  P.coef.lut_n = job.coeffs.lut_n;
-  P.coef.a = job.coeffs.param[0];
-  P.coef.lut = job.coeffs.lut;
-  P.coef.x0 = g.x0; P.coef.x1 = g.x1; P.coef.y0 = g.y0; P.coef.y1 = g.y1;
-  if (job.coeffs.kind == PDD_COEF_LUT) {
-    P.coef.lut_sx = (float)((job.coeffs.lut_n - 1) / (g.x1 - g.x0));
-    P.coef.lut_sy = (float)((job.coeffs.lut_n - 1) / (g.y1 - g.y0));
-  }
-  P.u_ref = run.u_ref;
-  P.lattice = gc->lattice.as<int32_t>();
   P.dump = run.dump_paths > 0 ? run.dump : nullptr;
   P.ticket_counter = nullptr;
   if (ctx->schedule == PDD_SCHEDULE_DYNAMIC) {
@@ -185,8 +208,6 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     }
     P.ticket_counter = ctx->ticket_counter.as<uint32_t>();
   }
-  P.inv_dx = (float)(1.0 / g.dx);
-  P.inv_dy = (float)(1.0 / g.dy);
 
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (ctx->timing && ctx->ev_used < 4096) {

@@ -57,6 +57,12 @@ struct AsmParams {
   const int32_t* lattice;     // (L+1)^2 lattice -> knot index (for u_ref)
   double* dump;               // nullable
   uint32_t* ticket_counter;   // dynamic schedule: zeroed work counter; nullptr: static stride
+  // control variate
+  int32_t cv_mode;            // PDD_CV_*
+  int32_t cv_lut_n;
+  const float* cv_params;     // network parameters (float32, PDD_MLP_PARAMS)
+  const float* cv_lut;        // grad v table [n][n][2]
+  float cv_lut_sx, cv_lut_sy; // (n-1)/(x1-x0), (n-1)/(y1-y0)
 };
 
 // Extras stored after the 4 slot_len G slots of a partial row.
@@ -82,9 +88,12 @@ struct FinalizeParams {
 hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block,
                            size_t lds_bytes, hipStream_t stream);
 hipError_t launch_finalize(const FinalizeParams& p, hipStream_t stream);
-// Dynamic LDS bytes per workgroup for a precision, row length and block size.
-size_t assemble_lds_bytes(int precision, int row_len, int block);
+// Training-pair collection (collect.hip).
+hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot, int32_t points_per_path,
+                          uint32_t inst, const double* u0, float* xy, float* yz, float* target, hipStream_t stream);
+// Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
+size_t assemble_lds_bytes(int precision, int row_len, int block, int cv_mode);
 // Kernel attribute query for occupancy-based grid sizing.
-hipError_t assemble_occupancy(int precision, int kind, int block, size_t lds_bytes, int* blocks_per_cu);
+hipError_t assemble_occupancy(int precision, int kind, int cv_mode, int block, size_t lds_bytes, int* blocks_per_cu);
 
 }  // namespace pdd

@@ -48,6 +48,19 @@ class CV(C.Structure):
                 ("grad_lut", C.c_void_p)]
 
 
+class CVSpec:
+    """Control variate for pdd_assemble: mode 'network' (params: float32 device
+    tensor of MLP_PARAMS) or 'grad_lut' (table: float32 device tensor
+    [n, n, 2] over the domain)."""
+
+    def __init__(self, mode, params=None, table=None):
+        self.mode, self.params, self.table = mode, params, table
+
+    def struct(self):
+        n = int(self.table.shape[0]) if self.table is not None else 0
+        return CV(CV_MODE[self.mode], n, _ptr(self.params), _ptr(self.table))
+
+
 class Run(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32), ("precision", C.c_int32),
                 ("exit_rule", C.c_int32), ("dump_paths", C.c_int32), ("n_paths", C.c_int64),
@@ -79,6 +92,12 @@ def lib():
                              C.POINTER(Run), vp, vp, vp, vp, vp],
             "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
+            "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
+            "pdd_mlp_grad": [vp, vp, i64, vp, vp, vp, vp],
+            "pdd_mlp_train": [vp, vp, vp, vp, i64, vp, vp, vp, i64, i32, i32, i32, C.c_float, vp],
+            "pdd_mlp_bake_grad_lut": [vp, vp, C.POINTER(Partition), i32, vp],
+            "pdd_collect_training": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots), C.POINTER(Run),
+                                     vp, i32, i32, vp, vp],
             "pdd_last_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)],
             "pdd_set_timing": [vp, i32],
             "pdd_kernel_ms": [vp, C.POINTER(f64), C.POINTER(i32)],
@@ -197,6 +216,47 @@ class Context:
         if check or st != ENOTCONV:
             self.check(st)
         return u, it.value, rr.value
+
+    # ---- control-variate network ---------------------------------------------
+    def mlp_eval(self, params, xy):
+        n = xy.shape[0]
+        v = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        g = self.torch.empty(n, 2, dtype=self.torch.float32, device=self.device)
+        self.check(lib().pdd_mlp_eval(self.h, _ptr(params), n, _ptr(xy), _ptr(v), _ptr(g)))
+        return v, g
+
+    def mlp_grad(self, params, xy, target):
+        grad = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.device)
+        loss = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
+        self.check(lib().pdd_mlp_grad(self.h, _ptr(params), xy.shape[0], _ptr(xy), _ptr(target), _ptr(grad), _ptr(loss)))
+        return grad, loss
+
+    def mlp_train(self, params, m, s, xy, target, order, batch, steps, step0, lr):
+        losses = self.torch.empty(max(steps, 1), dtype=self.torch.float32, device=self.device)
+        self.check(lib().pdd_mlp_train(self.h, _ptr(params), _ptr(m), _ptr(s), target.numel(), _ptr(xy), _ptr(target),
+                                       _ptr(order), order.numel(), int(batch), int(steps), int(step0), float(lr),
+                                       _ptr(losses)))
+        return losses[:steps]
+
+    def mlp_bake(self, params, w, lut_n):
+        table = self.torch.empty(lut_n, lut_n, 2, dtype=self.torch.float32, device=self.device)
+        part = partition_of(w)
+        self.check(lib().pdd_mlp_bake_grad_lut(self.h, _ptr(params), C.byref(part), int(lut_n), _ptr(table)))
+        return table
+
+    def collect(self, w, u0, paths_per_knot, points_per_path, seed=None, exit_rule=None):
+        """Training pairs (xy [slots, 2], target [slots]); NaN targets mark unused slots."""
+        n = pattern(w)[0]
+        slots = n * paths_per_knot * points_per_path
+        xy = self.torch.empty(slots, 2, dtype=self.torch.float32, device=self.device)
+        t = self.torch.empty(slots, dtype=self.torch.float32, device=self.device)
+        run = Run(int(w["seed"] if seed is None else seed), int(w.get("instance", 0)), PRECISION["fp32"],
+                  EXIT[exit_rule or w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), None, None, None)
+        co = self.coeffs_of(w)
+        part, kn = partition_of(w), knots_of(w)
+        self.check(lib().pdd_collect_training(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
+                                              _ptr(u0), int(paths_per_knot), int(points_per_path), _ptr(xy), _ptr(t)))
+        return xy, t
 
     # ---- assembly ----------------------------------------------------------
     def coeffs_of(self, w, lut=None):

@@ -66,3 +66,25 @@ def test_training_reduces_loss():
     order = workloads.minibatch_order(512, 40, seed=1)
     theta, losses = mlp.train(theta0, X, T, order, batch=64, lr=3e-3)
     assert losses[-20:].mean() < 0.05 * losses[:5].mean()
+
+
+def test_grad_table_reproduces_bilinear_fields():
+    """Bilinear interpolation is exact for fields a + b x + c y + d x y, so a
+    table sampled from such a field returns it exactly at any point."""
+    n = 17
+    dom = (-0.5, 1.5, 0.25, 2.25)
+    xs = dom[0] + np.arange(n) * (dom[1] - dom[0]) / (n - 1)
+    ys = dom[2] + np.arange(n) * (dom[3] - dom[2]) / (n - 1)
+    X, Y = np.meshgrid(xs, ys)
+    f0 = lambda x, y: 0.5 + 2.0 * x - 1.0 * y + 0.25 * x * y
+    f1 = lambda x, y: -1.0 + 0.5 * x * y
+    tab = np.stack([f0(X, Y), f1(X, Y)], axis=-1).astype(np.float32)
+    cv = mlp.GradLutCV(tab, dom)
+    rng = np.random.default_rng(3)
+    x, y = rng.uniform(dom[0], dom[1], 500), rng.uniform(dom[2], dom[3], 500)
+    gx, gy = cv.grad(x, y)
+    # the float32 table rounds the node values: compare at float32 resolution
+    assert np.allclose(gx, f0(x, y), atol=1e-6) and np.allclose(gy, f1(x, y), atol=1e-6)
+    # outside the domain the position is clamped to the boundary
+    gx2, _ = cv.grad(np.array([dom[1] + 1.0]), np.array([dom[2]]))
+    assert np.isclose(gx2[0], f0(dom[1], dom[2]), atol=1e-6)
