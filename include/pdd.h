@@ -187,6 +187,56 @@ pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partit
                         int32_t* row_ptr, int32_t* col_idx, double* val, double* b,
                         double* diag);
 
+/* ---- batched assembly -------------------------------------------------------- */
+
+/* One BVP instance of a batch: its problem, discretisation, run options and
+ * its own device outputs (as for pdd_assemble). */
+typedef struct pdd_instance {
+  pdd_coeffs coeffs;
+  pdd_partition part;
+  pdd_knots knots;
+  pdd_run run;
+  int32_t* row_ptr;
+  int32_t* col_idx;
+  double* val;
+  double* b;
+  double* diag;          /* nullable */
+} pdd_instance;
+
+/* Assemble n_inst independent instances in ONE persistent launch: the tickets
+ * of all instances form a single work list ordered longest-expected-first
+ * (paths x patch area / h), so instances of uneven size and uneven path
+ * lengths share the machine.  Every instance's result equals what
+ * pdd_assemble gives it alone, up to float64 summation order.  Restrictions:
+ * all instances share precision, exit rule, coefficient family (POISSON,
+ * VARCOEF or AMPLITUDE) and seed; no control variate, u_ref or dump.
+ * Instances are told apart in the random stream by run.instance. */
+pdd_status pdd_assemble_batch(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst);
+
+/* ---- graph capture ---------------------------------------------------------- */
+
+/* Capture the device work that the context enqueues between pdd_graph_begin
+ * and pdd_graph_end into a HIP graph, then replay it with pdd_graph_launch.
+ * Only cached work can be captured: run the same pdd_assemble /
+ * pdd_assemble_batch call once before capturing (a call that needs new
+ * tables during capture fails with PDD_EINVAL).  Captured work must not call
+ * pdd_solve.  *n_nodes receives the node count of the graph (nullable). */
+pdd_status pdd_graph_begin(pdd_ctx* ctx);
+pdd_status pdd_graph_end(pdd_ctx* ctx, int32_t* n_nodes);
+pdd_status pdd_graph_launch(pdd_ctx* ctx);
+
+/* ---- autotuning ----------------------------------------------------------- */
+
+/* Time the assembly of the given instance(s) (n_inst == 1: pdd_assemble;
+ * otherwise pdd_assemble_batch) over a grid of launch shapes -- threads per
+ * block, workgroups per compute unit, paths per ticket, static or dynamic
+ * schedule -- with `reps` timed repetitions each, and keep the fastest as the
+ * context's launch shape (pdd_set_launch).  *best_ms receives its mean
+ * kernel time; `report` (nullable, report_len bytes) a text table of every
+ * shape tried.  Results are cached per workload signature in the context. */
+pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, int32_t reps, double* best_ms,
+                        char* report, int32_t report_len);
+
 /* ---- solve (eq. 23) -------------------------------------------------------- */
 
 /* Solve G u = b for a CSR matrix (device arrays; row_ptr int32[n+1], col_idx

@@ -37,6 +37,7 @@ constexpr uint32_t MAX_STEPS = (1u << 24) - 2;
 
 struct WaveBuf {
   KnotDesc d;
+  InstDesc I;          // instance parameters (batched launches)
   double ebox[4];      // strict exit thresholds: x > e[0], y > e[1], x < e[2], y < e[3]
   int32_t ticket, p0, p1;
   uint32_t inst;
@@ -100,10 +101,20 @@ __device__ __forceinline__ uint32_t to_uniform_u(uint32_t v) {
 template <typename R>
 struct BufU {
   R sx, sy, e0, e1, e2, e3;
+  R h, sq, a;          // instance step and family parameter (batched launches)
   uint32_t knot, inst;
 };
 
-template <int KIND, bool F64, int CV>
+// Geometry used when resolving exits (the launch's, or a batched instance's).
+template <typename R>
+struct GeoView {
+  R x0, x1, y0, y1;
+  double dx, dy;
+  float inv_dx, inv_dy;
+  int L;
+};
+
+template <int KIND, bool F64, int CV, bool BATCH>
 __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
   using R = typename std::conditional<F64, double, float>::type;
   constexpr bool CVON = CV != PDD_CV_NONE;
@@ -155,6 +166,19 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
   uint32_t p = 0, kn = 0, inst = 0, j = 0;
   R x = 0, y = 0, Y = 0, Z = 0, Xi = 0;
   R ehx = 0, ehy = 0, elx = 0, ely = 0;
+  R lh = (R)P.h, lsq = (R)P.sqrt_h, la = (R)P.coef.a;   // per lane in batched launches
+
+  auto geo = [&](const WaveBuf& W) __attribute__((always_inline)) -> GeoView<R> {
+    GeoView<R> G;
+    if constexpr (BATCH) {
+      G.x0 = (R)W.I.x0; G.x1 = (R)W.I.x1; G.y0 = (R)W.I.y0; G.y1 = (R)W.I.y1;
+      G.dx = W.I.dx; G.dy = W.I.dy; G.inv_dx = W.I.inv_dx; G.inv_dy = W.I.inv_dy; G.L = W.I.L;
+    } else {
+      G.x0 = (R)P.x0; G.x1 = (R)P.x1; G.y0 = (R)P.y0; G.y1 = (R)P.y1;
+      G.dx = P.dx; G.dy = P.dy; G.inv_dx = P.inv_dx; G.inv_dy = P.inv_dy; G.L = P.L;
+    }
+    return G;
+  };
 
   // ---- exit processing over the queue (all lanes) ----------------------------
   auto process_queue = [&]() __attribute__((always_inline)) {
@@ -170,6 +194,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         const bool forced = (meta >> 25) & 1u;
         const WaveBuf& W = B[rb];
         const KnotDesc& d = W.d;
+        const GeoView<R> G = geo(W);
         bool fE = r.x > (R)W.ebox[0], fN = r.y > (R)W.ebox[1];
         bool fW = r.x < (R)W.ebox[2], fS = r.y < (R)W.ebox[3];
         if (forced) fE = fN = fW = fS = true;
@@ -180,7 +205,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         R bp = r.bp, uref = 0;
         if ((d.bmask >> o) & 1) {
           // boundary side: Y g(P), P the projection clamped to the domain
-          const R a0 = vert ? (R)P.y0 : (R)P.x0, a1 = vert ? (R)P.y1 : (R)P.x1;
+          const R a0 = vert ? G.y0 : G.x0, a1 = vert ? G.y1 : G.x1;
           const R pa = fmin(fmax(along, a0), a1);
           const R gv = vert ? g_at<KIND>(lpos, pa) : g_at<KIND>(pa, lpos);
           {
@@ -192,7 +217,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
           const int clo = d.clo[o], chi = d.chi[o];
           int q0;
           R w;
-          hat_weights<R, F64>(along, vert ? (R)P.y0 : (R)P.x0, vert ? P.dy : P.dx, vert ? P.inv_dy : P.inv_dx,
+          hat_weights<R, F64>(along, vert ? G.y0 : G.x0, vert ? G.dy : G.dx, vert ? G.inv_dy : G.inv_dx,
                               clo, chi, q0, w);
           double* row = rows + (size_t)rb * RL + o * SL;
 #pragma unroll
@@ -203,8 +228,8 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
 #pragma clang fp contract(off)
               c = r.Y * (e == 0 ? (R)1 - w : w);
             }
-            if (q == 0 || q == P.L) {
-              const R qc = vert ? (R)P.y0 + (R)q * (R)P.dy : (R)P.x0 + (R)q * (R)P.dx;
+            if (q == 0 || q == G.L) {
+              const R qc = vert ? G.y0 + (R)q * (R)G.dy : G.x0 + (R)q * (R)G.dx;
               const R gv = vert ? g_at<KIND>(lpos, qc) : g_at<KIND>(qc, lpos);
               {
 #pragma clang fp contract(off)
@@ -267,11 +292,24 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
     const double* src = reinterpret_cast<const double*>(P.desc + T.knot);
     if (lane < (int)(sizeof(KnotDesc) / sizeof(double)))
       reinterpret_cast<double*>(&W.d)[lane] = src[lane];
-    if (lane == 0) { W.ticket = (int32_t)t; W.p0 = T.p0; W.p1 = T.p1; W.inst = T.inst; }
+    if constexpr (BATCH) {
+      const double* isrc = reinterpret_cast<const double*>(P.insts + T.inst);
+      if (lane < (int)(sizeof(InstDesc) / sizeof(double)))
+        reinterpret_cast<double*>(&W.I)[lane] = isrc[lane];
+    }
+    if (lane == 0) {
+      W.ticket = (int32_t)t; W.p0 = T.p0; W.p1 = T.p1;
+      W.inst = BATCH ? P.insts[T.inst].inst_id : T.inst;
+    }
     double* row = rows + (size_t)b * RL;
     for (int i = lane; i < RL; i += 64) row[i] = 0.0;
     wave_sync();
-    if (lane < 4) W.ebox[lane] = (double)exit_threshold<KIND, R>(P, W.d, lane);
+    if (lane < 4) {
+      CoefParams cp = P.coef;
+      double sqh = P.sqrt_h;
+      if constexpr (BATCH) { cp.a = W.I.a; sqh = W.I.sqrt_h; }
+      W.ebox[lane] = (double)exit_threshold<KIND, R>(cp, P.exit_rule, sqh, W.d, lane);
+    }
     wave_sync();
     BufU<R> u;
     u.sx = to_uniform((R)W.d.sx);
@@ -280,8 +318,13 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
     u.e1 = to_uniform((R)W.ebox[1]);
     u.e2 = to_uniform((R)W.ebox[2]);
     u.e3 = to_uniform((R)W.ebox[3]);
-    u.knot = to_uniform_u((uint32_t)T.knot);
-    u.inst = to_uniform_u(T.inst);
+    u.knot = to_uniform_u((uint32_t)W.d.knot);
+    u.inst = to_uniform_u(W.inst);
+    if constexpr (BATCH) {
+      u.h = to_uniform((R)W.I.h);
+      u.sq = to_uniform((R)W.I.sqrt_h);
+      u.a = to_uniform((R)W.I.a);
+    }
     if (b) { tk1 = (int)t; nx1 = T.p0; en1 = T.p1; u1 = u; }
     else { tk0 = (int)t; nx0 = T.p0; en0 = T.p1; u0 = u; }
   };
@@ -326,6 +369,11 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         ehy = cur ? u1.e1 : u0.e1;
         elx = cur ? u1.e2 : u0.e2;
         ely = cur ? u1.e3 : u0.e3;
+        if constexpr (BATCH) {
+          lh = cur ? u1.h : u0.h;
+          lsq = cur ? u1.sq : u0.sq;
+          la = cur ? u1.a : u0.a;
+        }
         active = true;
         buf = cur;
       }
@@ -337,6 +385,8 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
     bool ex = false;
     bool forced = false;
     uint32_t K = 0;
+    CoefParams cpl = P.coef;
+    if constexpr (BATCH) cpl.a = (double)la;
     if constexpr (CV == PDD_CV_NETWORK && !F64) {
       // the network gradient is a wave-wide MFMA product: evaluate it with
       // every lane active, at each lane's left point, before each half step
@@ -347,7 +397,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         r = philox10(j, p, kn, inst, P.key0, P.key1);
         R z0, z1;
         box_muller(uniform32(r.a), uniform32(r.b), z0, z1);
-        em_step<KIND, R, true>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+        em_step<KIND, R, true>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
         K = 2 * j + 1;
         ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
       }
@@ -356,7 +406,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         if (!ex) {
           R z0, z1;
           box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
-          em_step<KIND, R, true>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+          em_step<KIND, R, true>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
           K = 2 * j + 2;
           ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
         }
@@ -375,14 +425,14 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
       if constexpr (F64) box_muller(uniform64(r.a), uniform64(r.b), z0, z1);
       else box_muller(uniform32(r.a), uniform32(r.b), z0, z1);
       cv_grad(gx, gy);
-      em_step<KIND, R, CVON>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+      em_step<KIND, R, CVON>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
       K = 2 * j + 1;
       ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
       if (!ex) {
         if constexpr (F64) box_muller(uniform64(r.c), uniform64(r.d), z0, z1);
         else box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
         cv_grad(gx, gy);
-        em_step<KIND, R, CVON>(P, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+        em_step<KIND, R, CVON>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
         K = 2 * j + 2;
         ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
       }
@@ -472,9 +522,19 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
   }
 }
 
-template <int KIND, bool F64, int CV>
+template <int KIND, bool F64, int CV, bool BATCH = false>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV>);
+  return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
+}
+
+template <bool F64>
+const void* pick_batch(int kind) {
+  switch (kind) {
+    case PDD_COEF_POISSON: return kernel_ptr<PDD_COEF_POISSON, F64, PDD_CV_NONE, true>();
+    case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64, PDD_CV_NONE, true>();
+    case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64, PDD_CV_NONE, true>();
+    default: return nullptr;
+  }
 }
 
 template <bool F64, int CV>
@@ -503,7 +563,11 @@ const void* pick(int kind, int cv) {
   }
 }
 
-const void* assemble_kernel(int precision, int kind, int cv) {
+const void* assemble_kernel(int precision, int kind, int cv, bool batch) {
+  if (batch) {
+    if (cv != PDD_CV_NONE) return nullptr;
+    return precision == PDD_FP64_SAME_STREAM ? pick_batch<true>(kind) : pick_batch<false>(kind);
+  }
   return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind, cv) : pick<false>(kind, cv);
 }
 
@@ -519,15 +583,16 @@ size_t assemble_lds_bytes(int precision, int row_len, int block, int cv_mode) {
   return net + waves * wave_lds_bytes<float>(row_len);
 }
 
-hipError_t assemble_occupancy(int precision, int kind, int cv_mode, int block, size_t lds_bytes, int* blocks_per_cu) {
-  const void* f = assemble_kernel(precision, kind, cv_mode);
+hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
+                              int* blocks_per_cu) {
+  const void* f = assemble_kernel(precision, kind, cv_mode, batch);
   if (!f) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block, size_t lds_bytes,
                            hipStream_t stream) {
-  const void* f = assemble_kernel(precision, p.coef.kind, p.cv_mode);
+  const void* f = assemble_kernel(precision, p.coef.kind, p.cv_mode, p.insts != nullptr);
   if (!f) return hipErrorInvalidValue;
   AsmParams arg = p;
   void* args[] = {&arg};

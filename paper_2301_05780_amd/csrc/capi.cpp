@@ -54,14 +54,9 @@ pdd_status check_hip(pdd_ctx* ctx, hipError_t e, const char* what) {
   return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PDD_ENOMEM : PDD_EDEVICE;
 }
 
-// Geometry of (part, knots), built on the host once and uploaded.
-pdd_status get_geometry(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn, GeoCache** out) {
-  for (auto& gc : ctx->geo) {
-    if (same_part(gc->part, part) && gc->kn.m == kn.m && gc->kn.ext == kn.ext) {
-      *out = gc.get();
-      return PDD_OK;
-    }
-  }
+// Geometry of (part, knots), built on the host and uploaded.
+pdd_status build_geo_cache(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn,
+                           std::unique_ptr<GeoCache>& out) {
   auto gc = std::make_unique<GeoCache>();
   gc->part = part;
   gc->kn = kn;
@@ -103,7 +98,31 @@ pdd_status get_geometry(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots
   if ((e = hipMemcpy(gc->knot_ij.ptr, ij.data(), ij.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload knot_ij");
   if ((e = hipMemcpy(gc->row_ptr.ptr, g.row_ptr.data(), g.row_ptr.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload row_ptr");
   if (!g.col_idx.empty() && (e = hipMemcpy(gc->col_idx.ptr, g.col_idx.data(), g.col_idx.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload col_idx");
-  if (ctx->geo.size() >= 8) ctx->geo.erase(ctx->geo.begin());
+  out = std::move(gc);
+  return PDD_OK;
+}
+
+bool same_geometry(const GeoCache& gc, const pdd_partition& part, const pdd_knots& kn) {
+  return same_part(gc.part, part) && gc.kn.m == kn.m && gc.kn.ext == kn.ext;
+}
+
+// Cached geometry of (part, knots) for single-instance calls (up to 8 kept).
+pdd_status get_geometry(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn, GeoCache** out) {
+  for (auto& gc : ctx->geo) {
+    if (same_geometry(*gc, part, kn)) {
+      *out = gc.get();
+      return PDD_OK;
+    }
+  }
+  std::unique_ptr<GeoCache> gc;
+  pdd_status st = build_geo_cache(ctx, part, kn, gc);
+  if (st != PDD_OK) return st;
+  if (ctx->geo.size() >= 8) {
+    // the stream may still read the evicted arrays
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    ctx->geo.erase(ctx->geo.begin());
+  }
   ctx->geo.push_back(std::move(gc));
   *out = ctx->geo.back().get();
   return PDD_OK;

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(BLK) void k_collect(CollectArgs C) {
   const uint32_t p = (uint32_t)(gid % C.paths_per_knot);
   const KnotDesc& d = P.desc[k];
   float eb[4];
-  for (int o = 0; o < 4; ++o) eb[o] = exit_threshold<KIND, float>(P, d, o);
+  for (int o = 0; o < 4; ++o) eb[o] = exit_threshold<KIND, float>(P.coef, P.exit_rule, P.sqrt_h, d, o);
   const int S = C.points_per_path;
   const int64_t slot0 = gid * S;
   float x = (float)d.sx, y = (float)d.sy, Y = 1.0f, Z = 0.0f;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(BLK) void k_collect(CollectArgs C) {
         C.yz[2 * (slot0 + recorded) + 1] = Z;
         ++recorded;
       }
-      em_step<KIND, float>(P, z0, z1, x, y, Y, Z);
+      em_step<KIND, float>(P.coef, (float)P.h, (float)P.sqrt_h, z0, z1, x, y, Y, Z);
       ex = (x > eb[0]) | (y > eb[1]) | (x < eb[2]) | (y < eb[3]);
     }
     ++j;

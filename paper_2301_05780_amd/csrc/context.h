@@ -44,6 +44,29 @@ struct TicketCache {
   DeviceBuffer tickets, ticket_begin, n_paths, order;
 };
 
+// Device-side tables of one batch of instances (rebuilt when the batch changes).
+struct BatchCache {
+  std::vector<pdd_partition> parts;
+  std::vector<pdd_knots> knots;
+  std::vector<std::vector<int32_t>> npk;
+  std::vector<double> h, a;
+  std::vector<uint32_t> inst_ids;
+  int32_t per_ticket = 0;
+  std::vector<std::unique_ptr<GeoCache>> geos;
+  std::vector<int64_t> knot_off, ticket_off, n_tickets;
+  int64_t total_tickets = 0;
+  int slot_len = 0;
+  DeviceBuffer desc, insts, tickets, order;
+  std::vector<std::unique_ptr<DeviceBuffer>> ticket_begin, n_paths;
+};
+
+struct TuneEntry {
+  std::string sig;
+  int block, grid, per_ticket, schedule;
+  double ms;
+  std::string report;
+};
+
 struct AssembleJob {
   pdd_coeffs coeffs;
   pdd_partition part;
@@ -66,6 +89,11 @@ struct pdd_ctx {
   std::string err;
   std::vector<std::unique_ptr<pdd::GeoCache>> geo;
   std::unique_ptr<pdd::TicketCache> tickets;
+  std::unique_ptr<pdd::BatchCache> batch;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool capturing = false;
+  std::vector<pdd::TuneEntry> tune_cache;
   pdd::DeviceBuffer partial;
   pdd::DeviceBuffer solve_scratch, solve_flag;
   pdd::DeviceBuffer collect_scratch, mlp_scratch;
@@ -82,6 +110,8 @@ struct pdd_ctx {
   int ev_used = 0;                   // pairs recorded since pdd_set_timing
   ~pdd_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
   }
 };
 
@@ -90,6 +120,10 @@ namespace pdd {
 pdd_status check_hip(pdd_ctx* ctx, hipError_t e, const char* what);
 pdd_status get_geometry(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn, GeoCache** out);
 pdd_status get_lattice(pdd_ctx* ctx, GeoCache* gc);
+pdd_status build_geo_cache(pdd_ctx* ctx, const pdd_partition& part, const pdd_knots& kn,
+                           std::unique_ptr<GeoCache>& out);
+bool same_geometry(const GeoCache& gc, const pdd_partition& part, const pdd_knots& kn);
+pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst);
 pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r);
 void fill_asm_params(const GeoCache& gc, const pdd_coeffs& co, const pdd_run& run, AsmParams& P);
 pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);

@@ -258,14 +258,13 @@ __device__ __forceinline__ float g_at(float x, float y) {
 // point.  With the control variate (CVON), Xi gains -Y (sigma^T grad v) . dW
 // (eq. 37), grad v = (gx, gy) taken at the same left point.
 template <int KIND, typename R, bool CVON = false>
-__device__ __forceinline__ void em_step(const AsmParams& P, R z0, R z1, R& x, R& y, R& Y, R& Z, R gx = 0, R gy = 0,
-                                        R* Xi = nullptr) {
+__device__ __forceinline__ void em_step(const CoefParams& cp, R h, R sq, R z0, R z1, R& x, R& y, R& Y, R& Z,
+                                        R gx = 0, R gy = 0, R* Xi = nullptr) {
   using T = Traits<KIND>;
   Coef<R> c;
-  coef_at<KIND>(P.coef, x, y, c);
+  coef_at<KIND>(cp, x, y, c);
   if constexpr (std::is_same<R, double>::value) {
 #pragma clang fp contract(off)
-    const double sq = P.sqrt_h, h = P.h;
     const double dWx = sq * z0, dWy = sq * z1;
     if constexpr (CVON) {
       double Fx, Fy;
@@ -291,7 +290,6 @@ __device__ __forceinline__ void em_step(const AsmParams& P, R z0, R z1, R& x, R&
     if constexpr (T::reaction) Y = Y * (1.0 + c.c * h);
     x = nx; y = ny; Z = nZ;
   } else {
-    const float sq = (float)P.sqrt_h, h = (float)P.h;
     const float dWx = sq * z0, dWy = sq * z1;
     if constexpr (CVON) {
       float Fx, Fy;
@@ -325,19 +323,20 @@ __device__ __forceinline__ void em_step(const AsmParams& P, R z0, R z1, R& x, R&
 // of a vertical side depends on x only and of a horizontal side on y only).
 // Returned as the strict threshold of the test that flags side o.
 template <int KIND, typename R>
-__device__ __forceinline__ R exit_threshold(const AsmParams& P, const KnotDesc& d, int o) {
+__device__ __forceinline__ R exit_threshold(const CoefParams& cp, int exit_rule, double sqrt_h, const KnotDesc& d,
+                                            int o) {
   const double line = d.line[o];
-  if (P.exit_rule == PDD_EXIT_NAIVE) return (R)line;
+  if (exit_rule == PDD_EXIT_NAIVE) return (R)line;
   const bool vert = (o == 0 || o == 2);
   Coef<R> c;
   const R px = vert ? (R)line : (R)d.sx;
   const R py = vert ? (R)d.sy : (R)line;
-  coef_at<KIND>(P.coef, px, py, c);
+  coef_at<KIND>(cp, px, py, c);
   R thr;
   {
 #pragma clang fp contract(off)
     const R ann = vert ? (c.sxx * c.sxx + c.sxy * c.sxy) : (c.sxy * c.sxy + c.syy * c.syy);
-    const R delta = (R)kGM * sqrt(ann) * (R)P.sqrt_h;
+    const R delta = (R)kGM * sqrt(ann) * (R)sqrt_h;
     thr = (o < 2) ? (R)line - delta : (R)line + delta;
   }
   // x >= thr  <=>  x > nextafter(thr, -inf);  x <= thr  <=>  x < nextafter(thr, +inf)

@@ -91,6 +91,8 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   if (st != PDD_OK) return st;
   const Geometry& g = gc->g;
   const pdd_run& run = job.run;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  const bool capturing = hipStreamIsCapturing(ctx->stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusActive;
 
   // paths per knot
   std::vector<int32_t> npk(g.n);
@@ -102,6 +104,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     total += v;
   }
   if (run.u_ref) {
+    if (!gc->lattice.ptr && capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: lattice table not cached before capture");
     st = get_lattice(ctx, gc);
     if (st != PDD_OK) return st;
   }
@@ -118,7 +121,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;
-  e = assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, block, lds, &per_cu);
+  e = assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, false, block, lds, &per_cu);
   if (e != hipSuccess) return check_hip(ctx, e, "occupancy query");
   per_cu = std::max(per_cu, 1);
   int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
@@ -131,6 +134,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   // tickets (cached while geometry, path counts and ticket size repeat)
   TicketCache* tc = ctx->tickets.get();
   if (!tc || tc->geo != gc || tc->per_ticket != per_ticket || tc->npk != npk || tc->inst != run.instance) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: tables not cached; run the same call once before capturing");
     auto fresh = std::make_unique<TicketCache>();
     fresh->geo = gc;
     fresh->npk = npk;
@@ -180,6 +184,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
 
   const size_t partial_bytes = (size_t)tc->n_tickets * row_len * sizeof(double);
   if (partial_bytes > ctx->partial.bytes) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: scratch not sized; run the same call once before capturing");
     if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
     if ((e = ctx->partial.reserve(partial_bytes)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(partial)");
   }
@@ -203,6 +208,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.ticket_counter = nullptr;
   if (ctx->schedule == PDD_SCHEDULE_DYNAMIC) {
     if (!ctx->ticket_counter.ptr) {
+      if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: counter not allocated; run once before capturing");
       if ((e = ctx->ticket_counter.reserve(sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(counter)");
       if ((e = hipMemset(ctx->ticket_counter.ptr, 0, sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMemset(counter)");
     }
@@ -210,7 +216,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   }
 
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  if (ctx->timing && ctx->ev_used < 4096) {
+  if (ctx->timing && !capturing && ctx->ev_used < 4096) {
     while ((int)ctx->ev_pool.size() < 2 * (ctx->ev_used + 1)) {
       hipEvent_t ev;
       if ((e = hipEventCreate(&ev)) != hipSuccess) return check_hip(ctx, e, "hipEventCreate");

@@ -21,6 +21,18 @@ struct KnotDesc {
 };
 static_assert(sizeof(KnotDesc) == 128, "KnotDesc must stay 128 bytes");
 
+// Per-instance parameters of a batched launch (one BVP instance each).
+struct InstDesc {
+  double x0, x1, y0, y1, dx, dy;   // domain and lattice spacing
+  double h, sqrt_h;                // time step
+  double a;                        // AMPLITUDE family parameter
+  float inv_dx, inv_dy;
+  int32_t L;                       // lattice intervals per direction
+  uint32_t inst_id;                // fourth Philox counter word
+  int32_t pad[2];
+};
+static_assert(sizeof(InstDesc) == 96, "InstDesc must stay 96 bytes");
+
 // A unit of work: paths [p0, p1) of one knot of one instance.
 struct Ticket {
   int32_t knot;
@@ -39,7 +51,8 @@ struct CoefParams {
 
 struct AsmParams {
   const KnotDesc* desc;
-  const Ticket* tickets;
+  const Ticket* tickets;      // batched: Ticket.inst indexes `insts`, Ticket.knot the concatenated descs
+  const InstDesc* insts;      // batched launches only (nullptr otherwise)
   const int32_t* order;       // schedule: ticket ids, longest expected work first
   int32_t n_tickets;
   int32_t row_len;            // doubles per partial row: 4 slot_len + 8
@@ -94,6 +107,7 @@ hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot,
 // Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
 size_t assemble_lds_bytes(int precision, int row_len, int block, int cv_mode);
 // Kernel attribute query for occupancy-based grid sizing.
-hipError_t assemble_occupancy(int precision, int kind, int cv_mode, int block, size_t lds_bytes, int* blocks_per_cu);
+hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
+                              int* blocks_per_cu);
 
 }  // namespace pdd

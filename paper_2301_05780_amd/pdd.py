@@ -68,6 +68,12 @@ class Run(C.Structure):
                 ("u_ref", C.c_void_p), ("dump", C.c_void_p)]
 
 
+class Instance(C.Structure):
+    _fields_ = [("coeffs", Coeffs), ("part", Partition), ("knots", Knots), ("run", Run),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p), ("b", C.c_void_p),
+                ("diag", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -93,6 +99,11 @@ def lib():
             "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
+            "pdd_assemble_batch": [vp, i32, vp],
+            "pdd_graph_begin": [vp],
+            "pdd_graph_end": [vp, C.POINTER(i32)],
+            "pdd_graph_launch": [vp],
+            "pdd_autotune": [vp, i32, vp, i32, C.POINTER(f64), C.c_char_p, i32],
             "pdd_mlp_grad": [vp, vp, i64, vp, vp, vp, vp],
             "pdd_mlp_train": [vp, vp, vp, vp, i64, vp, vp, vp, i64, i32, i32, i32, C.c_float, vp],
             "pdd_mlp_bake_grad_lut": [vp, vp, C.POINTER(Partition), i32, vp],
@@ -216,6 +227,56 @@ class Context:
         if check or st != ENOTCONV:
             self.check(st)
         return u, it.value, rr.value
+
+    # ---- batches, graphs, tuning -------------------------------------------------
+    def _outputs(self, w):
+        n, nnz, _, _ = pattern(w)
+        dev, torch = self.device, self.torch
+        return dict(n=n, nnz=nnz,
+                    row_ptr=torch.empty(n + 1, dtype=torch.int32, device=dev),
+                    col_idx=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                    val=torch.empty(max(nnz, 1), dtype=torch.float64, device=dev),
+                    b=torch.empty(n, dtype=torch.float64, device=dev),
+                    diag=torch.empty(n * DIAG_WIDTH, dtype=torch.float64, device=dev))
+
+    def _instance(self, w, out, precision=None):
+        par = (C.c_double * 4)(*(list(w.get("param", ())) + [0.0] * 4)[:4])
+        run = Run(int(w["seed"]) & (2 ** 64 - 1), int(w.get("instance", 0)), PRECISION[precision or w["precision"]],
+                  EXIT[w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), None, None, None)
+        return Instance(Coeffs(KIND[w["kind"]], 0, par, None), partition_of(w), knots_of(w), run,
+                        _ptr(out["row_ptr"]), _ptr(out["col_idx"]), _ptr(out["val"]), _ptr(out["b"]),
+                        _ptr(out["diag"]))
+
+    def batch_arrays(self, ws, outs=None, precision=None):
+        outs = outs or [self._outputs(w) for w in ws]
+        arr = (Instance * len(ws))(*[self._instance(w, o, precision) for w, o in zip(ws, outs)])
+        return arr, outs
+
+    def assemble_batch(self, ws, outs=None, precision=None, arr=None):
+        """Assemble every workload of ws in one launch; returns the list of outputs."""
+        if arr is None:
+            arr, outs = self.batch_arrays(ws, outs, precision)
+        self.check(lib().pdd_assemble_batch(self.h, len(arr), arr))
+        self._keep_batch = arr
+        return outs
+
+    def graph_begin(self):
+        self.check(lib().pdd_graph_begin(self.h))
+
+    def graph_end(self):
+        n = C.c_int32()
+        self.check(lib().pdd_graph_end(self.h, C.byref(n)))
+        return n.value
+
+    def graph_launch(self):
+        self.check(lib().pdd_graph_launch(self.h))
+
+    def autotune(self, arr, reps=3):
+        """Tune the launch shape for an Instance array (see batch_arrays)."""
+        ms = C.c_double()
+        rep = C.create_string_buffer(16384)
+        self.check(lib().pdd_autotune(self.h, len(arr), arr, int(reps), C.byref(ms), rep, 16384))
+        return ms.value, rep.value.decode()
 
     # ---- control-variate network ---------------------------------------------
     def mlp_eval(self, params, xy):
