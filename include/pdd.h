@@ -59,7 +59,10 @@ typedef struct pdd_ctx pdd_ctx;
  *              nodes spanning the partition's domain, node (i, j) at
  *              (x0 + i (x1-x0)/(lut_n-1), y0 + j (y1-y0)/(lut_n-1)); layout
  *              lut[(j * lut_n + i) * PDD_LUT_STRIDE + field], device pointer;
- *              g = u* of POISSON
+ *              g = u* of POISSON.  The table must give a positive definite
+ *              A = sigma sigma^T.  Under PDD_EXIT_GM each assembly first
+ *              reads the whole table once (max |sxx|, |sxy|, |syy|) to bound
+ *              the shift; the exact shift uses a_nn at the projection.
  *   CONSTSOL   sigma, d, c of VARCOEF, f = c, g = 1 (u = 1 is the solution)
  *   EXITTIME   sigma = sqrt(2) I, d = 0, c = 0, f = -1, g = 0 (u = mean exit
  *              time, eq. 26) */

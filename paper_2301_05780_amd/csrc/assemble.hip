@@ -180,6 +180,26 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
     return G;
   };
 
+  // ---- exit test at the new iterate --------------------------------------------
+  // The negation of "strictly inside the thresholds", so a NaN iterate exits
+  // (and is tallied as NaN) instead of running to the step cap.  For the LUT
+  // family under GM the thresholds are candidate ones: a candidate hit is
+  // decided exactly at the projection, and the flagged sides travel with the
+  // exit record.
+  auto exit_test = [&](uint32_t& fl) __attribute__((always_inline)) -> bool {
+    const bool inside = (x <= ehx) & (y <= ehy) & (x >= elx) & (y >= ely);
+    if constexpr (KIND == PDD_COEF_LUT) {
+      if (!inside && P.exit_rule == PDD_EXIT_GM) {
+        const uint32_t cand = (uint32_t)(x > ehx) | ((uint32_t)(y > ehy) << 1) | ((uint32_t)(x < elx) << 2) |
+                              ((uint32_t)(y < ely) << 3);
+        if (cand == 0) { fl = 0; return true; }
+        fl = lut_gm_refine<R>(P.coef, lsq, B[buf].d.line, x, y, cand);
+        return fl != 0;
+      }
+    }
+    return !inside;
+  };
+
   // ---- exit processing over the queue (all lanes) ----------------------------
   auto process_queue = [&]() __attribute__((always_inline)) {
     for (int base = 0; base < qn; base += 64) {
@@ -188,16 +208,25 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
       int rb = 0, o = 0;
       double vb = 0.0, vs = 0.0, vk = 0.0;
       if (valid) {
-        const ExitRec<R> r = Q[i];
+        ExitRec<R> r = Q[i];
         const uint32_t meta = Qm[i];
+        // an iterate that went NaN (NaN coefficients) poisons its row instead
+        // of landing on a clamped side point
+        if (isnan(r.x) || isnan(r.y)) { r.Y = (R)NAN; r.bp = (R)NAN; }
         rb = (int)((meta >> 24) & 1u);
         const bool forced = (meta >> 25) & 1u;
         const WaveBuf& W = B[rb];
         const KnotDesc& d = W.d;
         const GeoView<R> G = geo(W);
-        bool fE = r.x > (R)W.ebox[0], fN = r.y > (R)W.ebox[1];
-        bool fW = r.x < (R)W.ebox[2], fS = r.y < (R)W.ebox[3];
-        if (forced) fE = fN = fW = fS = true;
+        bool fE, fN, fW, fS;
+        if (KIND == PDD_COEF_LUT && P.exit_rule == PDD_EXIT_GM) {
+          fE = (meta >> 26) & 1u; fN = (meta >> 27) & 1u; fW = (meta >> 28) & 1u; fS = (meta >> 29) & 1u;
+        } else {
+          fE = r.x > (R)W.ebox[0]; fN = r.y > (R)W.ebox[1];
+          fW = r.x < (R)W.ebox[2]; fS = r.y < (R)W.ebox[3];
+        }
+        // the step cap, or a NaN iterate (no side flagged): every side is a candidate
+        if (forced || !(fE | fN | fW | fS)) fE = fN = fW = fS = true;
         o = choose_side<R>(r.x, r.y, fE, fN, fW, fS, d.line);
         const bool vert = (o == 0 || o == 2);
         const R along = vert ? r.y : r.x;
@@ -384,7 +413,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
     // ---- one Philox draw, up to two Euler steps -------------------------------
     bool ex = false;
     bool forced = false;
-    uint32_t K = 0;
+    uint32_t K = 0, fl = 0;
     CoefParams cpl = P.coef;
     if constexpr (BATCH) cpl.a = (double)la;
     if constexpr (CV == PDD_CV_NETWORK && !F64) {
@@ -399,7 +428,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         box_muller(uniform32(r.a), uniform32(r.b), z0, z1);
         em_step<KIND, R, true>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
         K = 2 * j + 1;
-        ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
+        ex = exit_test(fl);
       }
       net_grad_mfma(NL, x, y, gx, gy);
       if (active) {
@@ -408,7 +437,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
           box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
           em_step<KIND, R, true>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
           K = 2 * j + 2;
-          ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
+          ex = exit_test(fl);
         }
         ++j;
         if (!ex && 2 * j >= MAX_STEPS) { ex = true; forced = true; }
@@ -427,14 +456,14 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
       cv_grad(gx, gy);
       em_step<KIND, R, CVON>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
       K = 2 * j + 1;
-      ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
+      ex = exit_test(fl);
       if (!ex) {
         if constexpr (F64) box_muller(uniform64(r.c), uniform64(r.d), z0, z1);
         else box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
         cv_grad(gx, gy);
         em_step<KIND, R, CVON>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
         K = 2 * j + 2;
-        ex = (x > ehx) | (y > ehy) | (x < elx) | (y < ely);
+        ex = exit_test(fl);
       }
       ++j;
       if (!ex && 2 * j >= MAX_STEPS) { ex = true; forced = true; }
@@ -452,7 +481,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
           rec.bp = Z + Xi;
         }
         Q[i] = rec;
-        Qm[i] = K | ((uint32_t)buf << 24) | ((uint32_t)forced << 25);
+        Qm[i] = K | ((uint32_t)buf << 24) | ((uint32_t)forced << 25) | (fl << 26);
         if (P.dump && (int)p < P.dump_paths) {
           double* d = P.dump + ((size_t)kn * P.dump_paths + p) * PDD_DUMP_WIDTH;
           d[0] = (double)K; d[1] = (double)x; d[2] = (double)y; d[3] = (double)Y;

@@ -306,6 +306,7 @@ pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pd
     return check_hip(ctx, e, "hipMalloc(collect scratch)");
   AsmParams P;
   fill_asm_params(*gc, *coeffs, *run, P);
+  if ((st = prepare_lut_bound(ctx, *coeffs, *run, P, false)) != PDD_OK) return st;
   e = launch_collect(P, gc->g.n, paths_per_knot, points_per_path, run->instance, u0, xy,
                      ctx->collect_scratch.as<float>(), target, ctx->stream);
   return check_hip(ctx, e, "launch collect");

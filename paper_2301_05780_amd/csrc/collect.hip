@@ -50,6 +50,7 @@ __global__ __launch_bounds__(BLK) void k_collect(CollectArgs C) {
   uint32_t j = 0;
   int recorded = 0;
   bool ex = false;
+  uint32_t fl = 0;
   while (!ex) {
     const U4 r = philox10(j, p, (uint32_t)k, C.inst, P.key0, P.key1);
     float z0, z1;
@@ -64,13 +65,14 @@ __global__ __launch_bounds__(BLK) void k_collect(CollectArgs C) {
         ++recorded;
       }
       em_step<KIND, float>(P.coef, (float)P.h, (float)P.sqrt_h, z0, z1, x, y, Y, Z);
-      ex = (x > eb[0]) | (y > eb[1]) | (x < eb[2]) | (y < eb[3]);
+      fl = exit_sides<KIND, float>(P.coef, P.exit_rule, (float)P.sqrt_h, d.line, eb, x, y);
+      ex = fl != 0;
     }
     ++j;
     if (!ex && 2 * j >= (1u << 24) - 2) break;   // safety cap (forced exit below)
   }
-  bool fE = x > eb[0], fN = y > eb[1], fW = x < eb[2], fS = y < eb[3];
-  if (!ex) fE = fN = fW = fS = true;
+  if (!ex) fl = 15u;
+  const bool fE = fl & 1u, fN = (fl >> 1) & 1u, fW = (fl >> 2) & 1u, fS = (fl >> 3) & 1u;
   const int o = choose_side<float>(x, y, fE, fN, fW, fS, d.line);
   const bool vert = (o == 0 || o == 2);
   const float along = vert ? y : x;
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(BLK) void k_collect(CollectArgs C) {
       uex += wq * val;
     }
   }
-  const float vout = Z + Y * uex;
+  const float vout = (isnan(x) || isnan(y)) ? NAN : Z + Y * uex;
   for (int n = 0; n < S; ++n) {
     const int64_t sl = slot0 + n;
     if (n < recorded) {

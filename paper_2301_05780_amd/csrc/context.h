@@ -101,6 +101,7 @@ struct pdd_ctx {
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
   int schedule = PDD_SCHEDULE_STATIC;
   pdd::DeviceBuffer ticket_counter;
+  pdd::DeviceBuffer lut_max;         // LUT + GM: table-wide |sigma| maxima
   // shape of the last assembly launch (reported by pdd_last_launch)
   int last_grid = 0, last_block = 0;
   int64_t last_tickets = 0;
@@ -127,6 +128,9 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* 
 pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r);
 void fill_asm_params(const GeoCache& gc, const pdd_coeffs& co, const pdd_run& run, AsmParams& P);
 pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);
+// LUT family under the GM rule: enqueue the table-bound kernels and point
+// P.coef.lut_max at their result (no-op otherwise).
+pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
 pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                      const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres);
 

@@ -322,27 +322,143 @@ __device__ __forceinline__ void em_step(const CoefParams& cp, R h, R sq, R z0, R
 // the side at the knot's along-line coordinate; for every analytic family a_nn
 // of a vertical side depends on x only and of a horizontal side on y only).
 // Returned as the strict threshold of the test that flags side o.
+//
+// The LUT family's a_nn varies along a side, so under GM its threshold is a
+// candidate one: the shift uses a bound on a_nn over the whole table (a
+// bilinear value never exceeds its largest node in magnitude, so
+// sxx(P)^2 + sxy(P)^2 <= max|sxx|^2 + max|sxy|^2), widened by 1e-5 to absorb
+// rounding.  Every point the exact test flags passes the candidate test; the
+// exact decision, with a_nn at the projection, is lut_gm_refine's.
 template <int KIND, typename R>
 __device__ __forceinline__ R exit_threshold(const CoefParams& cp, int exit_rule, double sqrt_h, const KnotDesc& d,
                                             int o) {
   const double line = d.line[o];
   if (exit_rule == PDD_EXIT_NAIVE) return (R)line;
   const bool vert = (o == 0 || o == 2);
-  Coef<R> c;
-  const R px = vert ? (R)line : (R)d.sx;
-  const R py = vert ? (R)d.sy : (R)line;
-  coef_at<KIND>(cp, px, py, c);
   R thr;
-  {
-#pragma clang fp contract(off)
-    const R ann = vert ? (c.sxx * c.sxx + c.sxy * c.sxy) : (c.sxy * c.sxy + c.syy * c.syy);
-    const R delta = (R)kGM * sqrt(ann) * (R)sqrt_h;
+  if constexpr (KIND == PDD_COEF_LUT) {
+    const double mxx = (double)__uint_as_float(cp.lut_max[0]);
+    const double mxy = (double)__uint_as_float(cp.lut_max[1]);
+    const double myy = (double)__uint_as_float(cp.lut_max[2]);
+    const double bound = (vert ? mxx * mxx + mxy * mxy : mxy * mxy + myy * myy) * (1.0 + 1e-5);
+    // no finite bound (a NaN in the table): every iterate becomes a candidate
+    const R delta = isfinite(bound) ? (R)(kGM * sqrt(bound) * sqrt_h * (1.0 + 1e-5)) : (R)INFINITY;
     thr = (o < 2) ? (R)line - delta : (R)line + delta;
+  } else {
+    Coef<R> c;
+    const R px = vert ? (R)line : (R)d.sx;
+    const R py = vert ? (R)d.sy : (R)line;
+    coef_at<KIND>(cp, px, py, c);
+    {
+#pragma clang fp contract(off)
+      const R ann = vert ? (c.sxx * c.sxx + c.sxy * c.sxy) : (c.sxy * c.sxy + c.syy * c.syy);
+      const R delta = (R)kGM * sqrt(ann) * (R)sqrt_h;
+      thr = (o < 2) ? (R)line - delta : (R)line + delta;
+    }
   }
   // x >= thr  <=>  x > nextafter(thr, -inf);  x <= thr  <=>  x < nextafter(thr, +inf)
   return (o < 2) ? nextafter(thr, (R)-INFINITY) : nextafter(thr, (R)INFINITY);
 }
 
+// sigma entries (sxx, sxy, syy) of the LUT at (x, y): the first three fields
+// of lut_fetch, computed the same way.
+__device__ __forceinline__ void lut_sigma(const CoefParams& cp, double x, double y, double& sxx, double& sxy,
+                                          double& syy) {
+#pragma clang fp contract(off)
+  const int n = cp.lut_n;
+  double fx = (x - cp.x0) / (cp.x1 - cp.x0) * (double)(n - 1);
+  double fy = (y - cp.y0) / (cp.y1 - cp.y0) * (double)(n - 1);
+  fx = fmin(fmax(fx, 0.0), (double)(n - 1));
+  fy = fmin(fmax(fy, 0.0), (double)(n - 1));
+  const int i = (int)fmin(floor(fx), (double)(n - 2));
+  const int j = (int)fmin(floor(fy), (double)(n - 2));
+  const double tx = fx - (double)i, ty = fy - (double)j;
+  const float* p00 = cp.lut + ((size_t)j * n + i) * PDD_LUT_STRIDE;
+  const float* p01 = p00 + (size_t)n * PDD_LUT_STRIDE;
+  double v[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double v00 = p00[q], v10 = p00[PDD_LUT_STRIDE + q];
+    const double v01 = p01[q], v11 = p01[PDD_LUT_STRIDE + q];
+    v[q] = (1.0 - ty) * ((1.0 - tx) * v00 + tx * v10) + ty * ((1.0 - tx) * v01 + tx * v11);
+  }
+  sxx = v[0]; sxy = v[1]; syy = v[2];
+}
+
+__device__ __forceinline__ void lut_sigma(const CoefParams& cp, float x, float y, float& sxx, float& sxy,
+                                          float& syy) {
+  const int n = cp.lut_n;
+  float fx = (x - (float)cp.x0) * cp.lut_sx;
+  float fy = (y - (float)cp.y0) * cp.lut_sy;
+  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
+  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  const int i = min((int)fx, n - 2);
+  const int j = min((int)fy, n - 2);
+  const float tx = fx - (float)i, ty = fy - (float)j;
+  const float4* p00 = reinterpret_cast<const float4*>(cp.lut + ((size_t)j * n + i) * PDD_LUT_STRIDE);
+  const float4* p01 = p00 + (size_t)n * (PDD_LUT_STRIDE / 4);
+  const float4 a0 = p00[0], b0 = p00[2], c0 = p01[0], d0 = p01[2];
+  auto bl = [&](float v00, float v10, float v01, float v11) {
+    const float lo = v00 + tx * (v10 - v00);
+    const float hi = v01 + tx * (v11 - v01);
+    return lo + ty * (hi - lo);
+  };
+  sxx = bl(a0.x, b0.x, c0.x, d0.x);
+  sxy = bl(a0.y, b0.y, c0.y, d0.y);
+  syy = bl(a0.z, b0.z, c0.z, d0.z);
+}
+
+// Exact Gobet-Menozzi decision for the LUT family on the candidate sides
+// `cand` (bit o: side o passed the candidate test): side o is flagged iff the
+// point lies on or beyond the line shifted inwards by c_GM sqrt(a_nn(P_o))
+// sqrt(h), P_o the projection onto side o with its along-side coordinate
+// clamped to the side.  `line` holds the lines of E, N, W, S.  Returns the
+// flagged sides as a bit mask.
+template <typename R>
+__device__ __forceinline__ uint32_t lut_gm_refine(const CoefParams& cp, R sqrt_h, const double* line, R x, R y,
+                                                  uint32_t cand) {
+  const R xE = (R)line[0], yN = (R)line[1], xW = (R)line[2], yS = (R)line[3];
+  uint32_t fl = 0;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    if (!((cand >> o) & 1u)) continue;
+    const bool vert = (o == 0 || o == 2);
+    const R lpos = (o == 0) ? xE : (o == 1) ? yN : (o == 2) ? xW : yS;
+    const R px = vert ? lpos : fmin(fmax(x, xW), xE);
+    const R py = vert ? fmin(fmax(y, yS), yN) : lpos;
+    R sxx, sxy, syy;
+    lut_sigma(cp, px, py, sxx, sxy, syy);
+    bool hit;
+    {
+#pragma clang fp contract(off)
+      const R ann = vert ? (sxx * sxx + sxy * sxy) : (sxy * sxy + syy * syy);
+      const R delta = (R)kGM * sqrt(ann) * sqrt_h;
+      const R c = vert ? x : y;
+      hit = (o < 2) ? (c >= lpos - delta) : (c <= lpos + delta);
+    }
+    if (hit) fl |= 1u << o;
+  }
+  return fl;
+}
+
+// Sides flagged at (x, y) against the strict thresholds e[] of
+// exit_threshold (x > e[0], y > e[1], x < e[2], y < e[3]) as a bit mask; 0
+// while the point is strictly inside.  A NaN iterate flags every side, so it
+// exits instead of running to the step cap.  For the LUT family under GM a
+// candidate hit is decided exactly by lut_gm_refine.
+template <int KIND, typename R>
+__device__ __forceinline__ uint32_t exit_sides(const CoefParams& cp, int exit_rule, R sqrt_h, const double* line,
+                                               const R* e, R x, R y) {
+  const bool inside = (x <= e[0]) & (y <= e[1]) & (x >= e[2]) & (y >= e[3]);
+  if (inside) return 0u;
+  const uint32_t cand = (uint32_t)(x > e[0]) | ((uint32_t)(y > e[1]) << 1) | ((uint32_t)(x < e[2]) << 2) |
+                        ((uint32_t)(y < e[3]) << 3);
+  if (cand == 0) return 15u;
+  if constexpr (KIND == PDD_COEF_LUT) {
+    if (exit_rule == PDD_EXIT_GM) return lut_gm_refine<R>(cp, sqrt_h, line, x, y, cand);
+  }
+  return cand;
+}
 
 // Side chosen at an exit: among the tripped sides, the one whose grid line is
 // closest to the exit iterate; ties go to the first of E, N, W, S.  `line`

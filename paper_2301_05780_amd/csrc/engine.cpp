@@ -44,8 +44,19 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
     if (cv.mode != PDD_CV_NONE && (c.kind == PDD_COEF_CONSTSOL || c.kind == PDD_COEF_EXITTIME))
       return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variates are built for the poisson, varcoef, amplitude and LUT families");
   }
-  if (c.kind == PDD_COEF_LUT && r.exit_rule == PDD_EXIT_GM)
-    return bad(ctx, PDD_EUNSUPPORTED, "LUT coefficients with the Gobet-Menozzi rule are not implemented");
+  return PDD_OK;
+}
+
+pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing) {
+  if (co.kind != PDD_COEF_LUT || run.exit_rule != PDD_EXIT_GM) return PDD_OK;
+  hipError_t e;
+  if (!ctx->lut_max.ptr) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "LUT bound scratch not allocated; run the same call once before capturing");
+    if ((e = ctx->lut_max.reserve(4 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(lut bound)");
+  }
+  if ((e = launch_lut_bound(co.lut, co.lut_n, ctx->lut_max.as<uint32_t>(), ctx->stream)) != hipSuccess)
+    return check_hip(ctx, e, "launch LUT bound");
+  P.coef.lut_max = ctx->lut_max.as<uint32_t>();
   return PDD_OK;
 }
 
@@ -206,6 +217,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.dump_paths = run.dump_paths;
   P.dump = run.dump_paths > 0 ? run.dump : nullptr;
   P.ticket_counter = nullptr;
+  if ((st = prepare_lut_bound(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
   if (ctx->schedule == PDD_SCHEDULE_DYNAMIC) {
     if (!ctx->ticket_counter.ptr) {
       if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: counter not allocated; run once before capturing");

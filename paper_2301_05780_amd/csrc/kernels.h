@@ -47,6 +47,9 @@ struct CoefParams {
   const float* lut;           // LUT kind
   double x0, x1, y0, y1;      // domain (LUT node grid spans it)
   float lut_sx, lut_sy;       // (n-1)/(x1-x0), (n-1)/(y1-y0)
+  // LUT kind under the Gobet-Menozzi rule: max |sxx|, |sxy|, |syy| over the
+  // table's nodes as float bit patterns (device, written by launch_lut_bound)
+  const uint32_t* lut_max;
 };
 
 struct AsmParams {
@@ -104,6 +107,9 @@ hipError_t launch_finalize(const FinalizeParams& p, hipStream_t stream);
 // Training-pair collection (collect.hip).
 hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot, int32_t points_per_path,
                           uint32_t inst, const double* u0, float* xy, float* yz, float* target, hipStream_t stream);
+// Table-wide maxima of |sxx|, |sxy|, |syy| of a LUT (lut.hip): out[0..2]
+// as float bit patterns, out[3] unused.  Two kernels, no memset.
+hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipStream_t stream);
 // Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
 size_t assemble_lds_bytes(int precision, int row_len, int block, int cv_mode);
 // Kernel attribute query for occupancy-based grid sizing.

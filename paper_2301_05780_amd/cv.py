@@ -15,7 +15,7 @@ import numpy as np
 from . import pdd, workloads
 
 
-def fit(ctx, w, u0, paths_per_knot=256, points_per_path=32, epochs=8, batch=256, lr=3e-3, seed=0):
+def fit(ctx, w, u0, paths_per_knot=256, points_per_path=32, epochs=8, batch=256, lr=3e-3, seed=0, lut=None):
     """Train the control-variate network on pathwise estimates of workload w.
 
     Returns (params tensor, info dict with the number of pairs, the loss
@@ -23,7 +23,7 @@ def fit(ctx, w, u0, paths_per_knot=256, points_per_path=32, epochs=8, batch=256,
     torch = ctx.torch
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     ev[0].record(ctx.stream)
-    xy, t = ctx.collect(w, u0, paths_per_knot, points_per_path)
+    xy, t = ctx.collect(w, u0, paths_per_knot, points_per_path, lut=lut)
     ev[1].record(ctx.stream)
     valid = torch.nonzero(~torch.isnan(t)).flatten()
     n_pairs = int(valid.numel())

@@ -305,7 +305,7 @@ class Context:
         self.check(lib().pdd_mlp_bake_grad_lut(self.h, _ptr(params), C.byref(part), int(lut_n), _ptr(table)))
         return table
 
-    def collect(self, w, u0, paths_per_knot, points_per_path, seed=None, exit_rule=None):
+    def collect(self, w, u0, paths_per_knot, points_per_path, seed=None, exit_rule=None, lut=None):
         """Training pairs (xy [slots, 2], target [slots]); NaN targets mark unused slots."""
         n = pattern(w)[0]
         slots = n * paths_per_knot * points_per_path
@@ -313,7 +313,7 @@ class Context:
         t = self.torch.empty(slots, dtype=self.torch.float32, device=self.device)
         run = Run(int(w["seed"] if seed is None else seed), int(w.get("instance", 0)), PRECISION["fp32"],
                   EXIT[exit_rule or w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), None, None, None)
-        co = self.coeffs_of(w)
+        co = self.coeffs_of(w, lut)
         part, kn = partition_of(w), knots_of(w)
         self.check(lib().pdd_collect_training(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
                                               _ptr(u0), int(paths_per_knot), int(points_per_path), _ptr(xy), _ptr(t)))

@@ -79,11 +79,38 @@ def poisson_lut(n=4096, domain=(0.0, 1.0, 0.0, 1.0)):
     x0, x1, y0, y1 = domain
     xs = x0 + np.arange(n) * ((x1 - x0) / (n - 1))
     ys = y0 + np.arange(n) * ((y1 - y0) / (n - 1))
-    X, Y = np.meshgrid(xs, ys)                      # [j, i]
     tab = np.zeros((n, n, LUT_STRIDE), dtype=np.float32)
     tab[..., 0] = np.sqrt(2.0)
     tab[..., 2] = np.sqrt(2.0)
-    tab[..., 6] = (-2.0 * np.pi ** 2 * np.sin(np.pi * X) * np.sin(np.pi * Y) + 2.0 * Y)
+    # f[j, i] = -2 pi^2 sin(pi x_i) sin(pi y_j) + 2 y_j, formed as an outer product
+    a = -2.0 * np.pi ** 2 * np.sin(np.pi * xs)
+    tab[..., 6] = a[None, :] * np.sin(np.pi * ys)[:, None] + 2.0 * ys[:, None]
+    return tab
+
+
+def varied_lut(n=65, domain=(0.0, 1.0, 0.0, 1.0)):
+    """A tabulated problem whose every field varies, sigma with an off-diagonal
+    entry (same layout as ``poisson_lut``):
+
+      sxx = 1.3 + 0.25 sin(2 pi x) cos(pi y)     sxy = 0.2 sin(pi (x + 2 y))
+      syy = 1.2 + 0.3 cos(2 pi y) sin(pi x)      d = (0.5 sin 2 pi y, -0.4 cos 2 pi x)
+      c = -(0.5 + x y)                           f = cos 3x + y
+
+    det sigma >= 1.05 * 0.9 - 0.04 > 0, so A = sigma sigma^T is uniformly
+    elliptic.  No manufactured solution: it serves the parity checks.
+    """
+    x0, x1, y0, y1 = domain
+    xs = x0 + np.arange(n) * ((x1 - x0) / (n - 1))
+    ys = y0 + np.arange(n) * ((y1 - y0) / (n - 1))
+    X, Y = np.meshgrid(xs, ys)
+    tab = np.zeros((n, n, LUT_STRIDE), dtype=np.float32)
+    tab[..., 0] = 1.3 + 0.25 * np.sin(2 * np.pi * X) * np.cos(np.pi * Y)
+    tab[..., 1] = 0.2 * np.sin(np.pi * (X + 2 * Y))
+    tab[..., 2] = 1.2 + 0.3 * np.cos(2 * np.pi * Y) * np.sin(np.pi * X)
+    tab[..., 3] = 0.5 * np.sin(2 * np.pi * Y)
+    tab[..., 4] = -0.4 * np.cos(2 * np.pi * X)
+    tab[..., 5] = -(0.5 + X * Y)
+    tab[..., 6] = np.cos(3 * X) + Y
     return tab
 
 

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("w", [workloads.poisson_small(), workloads.varcoef(),
+@pytest.mark.parametrize("w", [workloads.poisson_small(), workloads.varcoef(), workloads.large_lut(),
                                dict(domain=(-1.0, 2.0, 0.0, 1.5), H=5, m=6, ext=3),
                                dict(domain=(0.0, 1.0, 0.0, 1.0), H=3, m=1, ext=0)])
 def test_pattern_bit_exact_against_oracle(w):

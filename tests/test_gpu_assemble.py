@@ -19,6 +19,7 @@ from paper_2301_05780_amd import pdd, workloads
 from oracle.geometry import Geometry
 from oracle.coeffs import Coefficients
 from oracle.assemble import assemble as oracle_assemble, to_csr
+from parity import fetch, assert_same_stream, assert_within_se
 
 pytestmark = pytest.mark.gpu
 
@@ -57,36 +58,6 @@ def _oracle_cached(key):
 def oracle(w):
     key = tuple(sorted((k, tuple(v) if isinstance(v, (list, tuple)) else v) for k, v in w.items()))
     return _oracle_cached(key)
-
-
-def fetch(out, g):
-    return dict(row_ptr=out["row_ptr"].cpu().numpy(), col_idx=out["col_idx"].cpu().numpy()[:g.nnz],
-                val=out["val"].cpu().numpy()[:g.nnz], b=out["b"].cpu().numpy(),
-                diag=out["diag"].cpu().numpy().reshape(g.n, pdd.DIAG_WIDTH))
-
-
-def assert_same_stream(got, g, ref, rel=1e-12):
-    assert np.array_equal(got["row_ptr"], g.row_ptr)
-    assert np.array_equal(got["col_idx"], g.col_idx)
-    row_of = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
-    tol = rel * ref["mass"]
-    dv = np.abs(got["val"] - ref["val"])
-    db = np.abs(got["b"] - ref["b"])
-    assert np.all(dv <= tol[row_of]), f"max G error {np.max(dv / tol[row_of]):.3g} x tol"
-    assert np.all(db <= tol), f"max b error {np.max(db / tol):.3g} x tol"
-    d, r = got["diag"], ref["diag"]
-    assert np.array_equal(d[:, :6], r[:, :6]), "step counts / exit-side counts differ"
-    assert np.allclose(d[:, 6:], r[:, 6:], rtol=1e-11, atol=1e-12 * np.max(np.abs(r[:, 6:])))
-
-
-def assert_within_se(got, g, ref, nse=3.0, floor=1e-6):
-    assert np.array_equal(got["row_ptr"], g.row_ptr)
-    assert np.array_equal(got["col_idx"], g.col_idx)
-    dv = np.abs(got["val"] - ref["val"])
-    db = np.abs(got["b"] - ref["b"])
-    assert np.all(dv <= nse * ref["se_val"] + floor), f"worst G {np.max(dv - nse * ref['se_val']):.3g}"
-    assert np.all(db <= nse * ref["se_b"] + floor * np.maximum(1, np.abs(ref["b"]))), \
-        f"worst b {np.max(db - nse * ref['se_b']):.3g}"
 
 
 # ---------------------------------------------------------------------------
