@@ -255,6 +255,29 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
                      const double* val, const double* b, double* u, double tol, int32_t max_iter,
                      int32_t* iters, double* relres);
 
+/* ---- values inside the subdomains (Sec. 3.3; eq. 8 on each square) ------- */
+
+/* u at n_pts points from the knot values: each subdomain square is a
+ * Dirichlet problem whose sides carry the knot values interpolated along the
+ * grid lines (hat functions, the along-side coordinate clamped to the side)
+ * on interfaces and g on the domain boundary; u(x) is the Feynman-Kac mean of
+ * Z + Y u(exit) over run.n_paths paths from x absorbed at the square's
+ * boundary, with the assembly's step, exit rule and side choice.  The square
+ * of (x, y) has lower-left corner index min(floor((x - x0) / s), H - 1) per
+ * direction, s the subdomain side; a point exactly on a grid line of its
+ * square gets the line value itself (se = 0).  Points outside the closed
+ * domain give NaN.
+ * Inputs (device): u_knots[n] (canonical knot order, e.g. from pdd_solve),
+ * xy[2 n_pts] float64 interleaved.  Outputs (device): u[n_pts], se[n_pts]
+ * (nullable) the Monte Carlo standard error of each value.
+ * run: seed, instance (< 2^31), precision, exit_rule, n_paths (paths per
+ * point), h; cv, n_paths_per_knot and dump must be unset.  Path p of point i
+ * draws from the Philox counter (draw, p, i, instance + 2^31), disjoint from
+ * the knot streams of assemblies with instance < 2^31. */
+pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                              const pdd_knots* knots, const double* u_knots, int64_t n_pts, const double* xy,
+                              const pdd_run* run, double* u, double* se);
+
 /* ---- control-variate network (eqs. 11, 37-38) ---------------------------- */
 
 /* v and/or grad v of the 2-64-64-1 tanh network at n points (float32, device

@@ -42,9 +42,10 @@ SIDE_CODE = {"E": 0, "N": 1, "W": 2, "S": 3}
 DIAG_WIDTH = 8                      # sum K, N, exits E/N/W/S, sum s, sum s^2
 
 
-def _gm_shifts(coef, geom, k, x, y, h):
-    """Per-path inward shifts (dE, dN, dW, dS) of the Gobet-Menozzi rule."""
-    xlo, xhi, ylo, yhi = geom.box[k]
+def _gm_shifts(coef, box, x, y, h):
+    """Per-path inward shifts (dE, dN, dW, dS) of the Gobet-Menozzi rule for the
+    rectangle box = (xlo, xhi, ylo, yhi)."""
+    xlo, xhi, ylo, yhi = box
     yc = np.minimum(np.maximum(y, ylo), yhi)
     xc = np.minimum(np.maximum(x, xlo), xhi)
     sh = np.sqrt(h)
@@ -55,17 +56,25 @@ def _gm_shifts(coef, geom, k, x, y, h):
     return dE, dN, dW, dS
 
 
-def exit_flags(coef, geom, k, x, y, h, exit_rule):
-    """Boolean flags (E, N, W, S) of the sides the exit test trips on."""
-    xlo, xhi, ylo, yhi = geom.box[k]
+def exit_flags_box(coef, box, x, y, h, exit_rule):
+    """Boolean flags (E, N, W, S) of the sides of box = (xlo, xhi, ylo, yhi)
+    that the exit test trips on."""
+    xlo, xhi, ylo, yhi = box
     if exit_rule == "naive":
         return x > xhi, y > yhi, x < xlo, y < ylo
-    dE, dN, dW, dS = _gm_shifts(coef, geom, k, x, y, h)
+    dE, dN, dW, dS = _gm_shifts(coef, box, x, y, h)
     return x >= xhi - dE, y >= yhi - dN, x <= xlo + dW, y <= ylo + dS
 
 
-def integrate_knot(geom, coef, k, n_paths, h, seed, instance, exit_rule, cv=None):
-    """Run n_paths paths from knot k to their first exit.
+def exit_flags(coef, geom, k, x, y, h, exit_rule):
+    """Boolean flags (E, N, W, S) of the sides of knot k's patch the exit test trips on."""
+    return exit_flags_box(coef, geom.box[k], x, y, h, exit_rule)
+
+
+def integrate_paths(coef, box, start, word2, instance, n_paths, h, seed, exit_rule, cv=None):
+    """Run n_paths paths from ``start`` to their first exit from the rectangle
+    box = (xlo, xhi, ylo, yhi).  Path p draws from the stream with counter
+    (draw, p, word2, instance).
 
     Returns a dict of per-path arrays: K (steps, exit step included), x, y
     (the exit iterate X_K before projection), Y, Z, Xi, and flags (N x 4 bool,
@@ -74,8 +83,8 @@ def integrate_knot(geom, coef, k, n_paths, h, seed, instance, exit_rule, cv=None
     N = int(n_paths)
     sq = np.sqrt(h)
     path = np.arange(N, dtype=np.uint64)
-    x = np.full(N, geom.x[k])
-    y = np.full(N, geom.y[k])
+    x = np.full(N, float(start[0]))
+    y = np.full(N, float(start[1]))
     Y = np.ones(N)
     Z = np.zeros(N)
     Xi = np.zeros(N)
@@ -84,7 +93,7 @@ def integrate_knot(geom, coef, k, n_paths, h, seed, instance, exit_rule, cv=None
     alive = np.arange(N)
     j = 0
     while alive.size:
-        first, second = normals_for_draw(j, path[alive], k, instance, seed)
+        first, second = normals_for_draw(j, path[alive], word2, instance, seed)
         idx = alive
         for half, (nx, ny) in enumerate((first, second)):
             if half == 1:
@@ -105,7 +114,7 @@ def integrate_knot(geom, coef, k, n_paths, h, seed, instance, exit_rule, cv=None
             Y[idx] = Ya * (1.0 + cr * h)
             Z[idx] = Z[idx] - fs * Ya * h
             K[idx] += 1
-            fE, fN, fW, fS = exit_flags(coef, geom, k, x[idx], y[idx], h, exit_rule)
+            fE, fN, fW, fS = exit_flags_box(coef, box, x[idx], y[idx], h, exit_rule)
             out = fE | fN | fW | fS
             flags[idx[out]] = np.stack([fE[out], fN[out], fW[out], fS[out]], axis=1)
             keep = ~out
@@ -115,6 +124,13 @@ def integrate_knot(geom, coef, k, n_paths, h, seed, instance, exit_rule, cv=None
         alive = idx
         j += 1
     return dict(K=K, x=x, y=y, Y=Y, Z=Z, Xi=Xi, flags=flags)
+
+
+def integrate_knot(geom, coef, k, n_paths, h, seed, instance, exit_rule, cv=None):
+    """Run n_paths paths from knot k to their first exit from its patch
+    (stream counter (draw, path, k, instance))."""
+    return integrate_paths(coef, geom.box[k], (geom.x[k], geom.y[k]), k, instance, n_paths, h, seed,
+                           exit_rule, cv)
 
 
 def exit_points(geom, coef, k, rec):

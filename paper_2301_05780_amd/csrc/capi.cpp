@@ -242,6 +242,25 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
   return run_solve(ctx, n, row_ptr, col_idx, val, b, u, tol, max_iter, iters, relres);
 }
 
+pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                              const pdd_knots* knots, const double* u_knots, int64_t n_pts, const double* xy,
+                              const pdd_run* run, double* u, double* se) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_eval_subdomain: null context");
+  if (!coeffs || !part || !knots || !run || !u_knots || n_pts < 0 || (n_pts > 0 && (!xy || !u)))
+    return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: bad arguments");
+  if (run->cv && run->cv->mode != PDD_CV_NONE)
+    return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: run.cv must be NULL");
+  if (run->n_paths_per_knot || run->dump_paths != 0)
+    return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: run.n_paths_per_knot must be NULL and run.dump_paths 0");
+  if (run->instance >= 0x80000000u)
+    return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: run.instance must be below 2^31");
+  if (n_pts > INT32_MAX) return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: at most 2^31 - 1 points");
+  pdd_status st = validate_run(ctx, *coeffs, *run);
+  if (st != PDD_OK) return st;
+  if (n_pts == 0) return PDD_OK;
+  return run_eval_subdomain(ctx, *coeffs, *part, *knots, u_knots, n_pts, xy, *run, u, se);
+}
+
 pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad) {
   if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_eval: null context");
   if (!params || !xy || n < 0 || (!v && !grad)) return fail(ctx, PDD_EINVAL, "pdd_mlp_eval: bad arguments");

@@ -131,6 +131,9 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);
 // LUT family under the GM rule: enqueue the table-bound kernels and point
 // P.coef.lut_max at their result (no-op otherwise).
 pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
+pdd_status run_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_partition& part, const pdd_knots& kn,
+                              const double* u_knots, int64_t n_pts, const double* xy, const pdd_run& run, double* u,
+                              double* se);
 pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                      const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres);
 

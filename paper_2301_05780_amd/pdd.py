@@ -109,6 +109,8 @@ def lib():
             "pdd_mlp_bake_grad_lut": [vp, vp, C.POINTER(Partition), i32, vp],
             "pdd_collect_training": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots), C.POINTER(Run),
                                      vp, i32, i32, vp, vp],
+            "pdd_eval_subdomain": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots), vp, i64, vp,
+                                   C.POINTER(Run), vp, vp],
             "pdd_last_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)],
             "pdd_set_timing": [vp, i32],
             "pdd_kernel_ms": [vp, C.POINTER(f64), C.POINTER(i32)],
@@ -318,6 +320,23 @@ class Context:
         self.check(lib().pdd_collect_training(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
                                               _ptr(u0), int(paths_per_knot), int(points_per_path), _ptr(xy), _ptr(t)))
         return xy, t
+
+    def eval_subdomain(self, w, u_knots, xy, n_paths, h=None, seed=None, instance=None, precision=None,
+                       exit_rule=None, lut=None):
+        """u and its standard error at the points xy (device float64 [P, 2])
+        inside the subdomains, from the knot values u_knots (device float64 [n])."""
+        P = xy.shape[0]
+        u = self.torch.empty(P, dtype=self.torch.float64, device=self.device)
+        se = self.torch.empty(P, dtype=self.torch.float64, device=self.device)
+        run = Run(int(w["seed"] if seed is None else seed) & (2 ** 64 - 1),
+                  int(w.get("instance", 0) if instance is None else instance),
+                  PRECISION[precision or w["precision"]], EXIT[exit_rule or w["exit_rule"]], 0, int(n_paths),
+                  None, float(w["h"] if h is None else h), None, None, None)
+        co = self.coeffs_of(w, lut)
+        part, kn = partition_of(w), knots_of(w)
+        self.check(lib().pdd_eval_subdomain(self.h, C.byref(co), C.byref(part), C.byref(kn), _ptr(u_knots), int(P),
+                                            _ptr(xy), C.byref(run), _ptr(u), _ptr(se)))
+        return u, se
 
     # ---- assembly ----------------------------------------------------------
     def coeffs_of(self, w, lut=None):
