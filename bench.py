@@ -1,39 +1,90 @@
 """Benchmark: Euler-Maruyama path-steps per second of the Monte Carlo assembly
-of G and b on one MI355X.
+of G and b on one MI355X, and the RMSE x time comparison of the plain and the
+control-variate estimators.
 
-Workload (default): the variable-coefficient problem on [0,1]^2 with 8 x 8
+Default workload: the variable-coefficient problem on [0,1]^2 with 8 x 8
 subdomains, knot spacing 1/128 (1729 knots, 229,405 structural nonzeros),
 N = 1e4 paths per knot, h = 1e-4, Gobet-Menozzi exits, float32 paths with
 float64 accumulation of G and b.  One step = one full assembly (all paths of
 all knots, CSR values and b written).  Inputs are formula-defined and resident
-on the device before timing.
+on the device before timing.  Other workloads (--workload): poisson_small
+(29 knots), large_lut (4096^2 coefficient table, 62465 knots, h = 1e-5) and
+batched (64 instances in one launch, replayed from a HIP graph).
 
-Prints one JSON line.  ``roofline`` reports the assembly kernel against the
-VALU issue peak (the path is bound by plain ALU work: integer multiplies of
-the counter-based generator, transcendentals, float32 arithmetic; HBM traffic
-is a few MB per launch).  ``cpu_baseline`` is the float64 CPU oracle timed on
-a bounded sample of the same workload.
+Prints one JSON line.
+  roofline      the assembly kernel against the VALU issue peak (the path is
+                bound by plain ALU work: the counter-based generator's integer
+                multiplies, transcendentals, float32 arithmetic); `achieved` is
+                the algorithmic lane-operations per path-step (ALG_OPS) times
+                the path-steps of one launch over the launch's mean duration
+                from HIP events on the library's stream; `traffic` is the HBM
+                byte count of the committed counter summary for this kernel
+                source and workload, or null when the source has changed.
+  cpu_baseline  the float64 CPU oracle on a bounded sample of the workload.
+  cv_comparison (default workload only) interface RMSE and GPU time of the
+                plain estimator and of the trained control variate on the
+                29-knot poisson problem, each the mean over 16 seeds.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+CSRC = os.path.join(ROOT, "paper_2301_05780_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
 
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one
-# full-rate 32-bit lane operation per lane per clock).
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# full-rate 32-bit lane operation per lane per clock (a wave64 instruction
+# occupies its SIMD for 4 clocks).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic VALU work of one float32 path-step of each coefficient family,
-# in full-rate lane-operation equivalents (quarter-rate transcendentals and
-# 32x32->64-bit integer multiplies count 4).  Derivation in the design doc.
-ALG_OPS_PER_STEP = {"varcoef": 149, "poisson": 108, "amplitude": 125, "lut": 132}
-FP32_FLOP_PER_STEP = {"varcoef": 60, "poisson": 25, "amplitude": 40, "lut": 70}
+# Algorithmic VALU work of one float32 path-step, in lane-operation issue
+# slots: full-rate ops count 1; transcendentals (v_sin, v_cos, v_log, v_exp,
+# v_sqrt) and 32x32->64-bit integer multiplies count the issue slots they were
+# measured to take on gfx950 (2 and 1).  Per step: half a Philox4x32-10 draw
+# (10 rounds x (2 wide multiplies + 2 three-input XORs) / 2 = 20), two
+# uniforms (6), one Box-Muller pair (log, sqrt, sin, cos + 3 multiplies = 11),
+# the coefficients at X_n, the Euler update of X, Y, Z and the exit test (7).
+ALG_OPS = {
+    "poisson": 20 + 6 + 11 + 9 + 6 + 7,        # f: 2 sin + 5 ops
+    "varcoef": 20 + 6 + 11 + 31 + 12 + 7,      # 6 trans, 2 sqrt, f: exp + polynomial
+    "amplitude": 20 + 6 + 11 + 24 + 6 + 7,     # 4 trans, 2 sqrt
+    "lut": 20 + 6 + 11 + 56 + 14 + 7,          # index math 14, 7 fields x 3 lerps x 2 ops
+}
+FP32_FLOP = {"poisson": 25, "varcoef": 60, "amplitude": 40, "lut": 70}
 FP32_PEAK_TFLOPS = 157.3
+
+
+def kernel_source_hash():
+    """sha256 of the assembly kernel's sources (ties counter summaries to a version)."""
+    h = hashlib.sha256()
+    for f in ("assemble.hip", "device_common.h", "kernels.h", "net_grad.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload):
+    """HBM bytes per launch from profiles/assemble_<workload>_hbm.txt when its
+    source hash matches the current kernel source, else None."""
+    path = os.path.join(PROFILES, f"assemble_{workload}_hbm.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_sha256:\s*(\w+)", txt)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+# ---- CPU oracle baseline ---------------------------------------------------
+_ORACLE_INPUTS = {}
 
 
 def _oracle_sample(args):
@@ -42,9 +93,17 @@ def _oracle_sample(args):
     from oracle.geometry import Geometry
     from oracle.coeffs import Coefficients
     from oracle.assemble import integrate_knot, exit_points, knot_row
-    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
-    c = Coefficients(w["kind"], w.get("param", ()))
-    rec = integrate_knot(g, c, k, w["n_paths"], w["h"], w["seed"], 0, w["exit_rule"])
+    key = w["name"]
+    if key not in _ORACLE_INPUTS:            # geometry and coefficients, once per worker
+        g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+        if w["kind"] == "lut":
+            from paper_2301_05780_amd import workloads
+            c = Coefficients("lut", lut=workloads.poisson_lut(w["lut_n"]), lut_n=w["lut_n"])
+        else:
+            c = Coefficients(w["kind"], w.get("param", ()))
+        _ORACLE_INPUTS[key] = (g, c)
+    g, c = _ORACLE_INPUTS[key]
+    rec = integrate_knot(g, c, k, w["n_paths"], w["h"], w["seed"], w.get("instance", 0), w["exit_rule"])
     ex = exit_points(g, c, k, rec)
     knot_row(g, c, k, rec, ex)
     return int(rec["K"].sum())
@@ -56,6 +115,9 @@ def cpu_baseline(w, n_knots, workers):
     from paper_2301_05780_amd import pdd
     n = pdd.pattern(w)[0]
     knots = np.linspace(0, n - 1, n_knots).round().astype(int).tolist()
+    if workers == 1:
+        _oracle_sample((w, knots[0]))          # set-up (geometry, tables) outside the timed sample
+        knots = knots[1:]
     t0 = time.perf_counter()
     if workers > 1:
         with mp.get_context("spawn").Pool(workers) as pool:
@@ -68,87 +130,249 @@ def cpu_baseline(w, n_knots, workers):
                        f"{sum(steps)} path-steps in {dt:.1f} s")
 
 
+# ---- control-variate comparison (RMSE x time) ------------------------------
+def cv_comparison(ctx, w, n_plain, sweep_n, seeds=16, epochs=4):
+    """Plain estimator at n_plain paths per knot against the trained network
+    control variate (and its baked gradient table) at the path counts
+    `sweep_n`, float32.  RMSE: interface RMSE against u*, mean over `seeds`
+    Philox keys.  Time: the assembly kernel's GPU time (HIP events on the
+    library's stream), median over the seeds; the solve that follows is the
+    same for both estimators and is left out."""
+    import numpy as np
+    import torch
+    from paper_2301_05780_amd import pdd, cv as cvmod
+    from oracle.coeffs import Coefficients     # the manufactured solution only
+    w = dict(w, precision="fp32")
+    xy = pdd.knot_xy(w)
+    ue = Coefficients(w["kind"], w.get("param", ())).exact(xy[:, 0], xy[:, 1])
+
+    def run(n_paths, spec=None):
+        ww = dict(w, n_paths=n_paths)
+        out = ctx.assemble(ww, seed=100, cv=spec)     # warm caches
+        ctx.sync()
+        rm, ms = [], []
+        for s in range(seeds):
+            ctx.set_timing(True)
+            ctx.assemble(ww, out=out, seed=s, cv=spec)
+            ctx.sync()
+            ms.append(ctx.kernel_ms()[0])
+            ctx.set_timing(False)
+            u, _, _ = ctx.solve(out["row_ptr"], out["col_idx"], out["val"][:out["nnz"]], out["b"])
+            rm.append(float(np.sqrt(np.mean((u.cpu().numpy() - ue) ** 2))))
+        return float(np.mean(rm)), float(np.median(ms))
+
+    rmse_plain, t_plain = run(n_plain)
+    # training data: the method's own paths scored with a plain solution
+    out = ctx.assemble(dict(w, n_paths=n_plain), seed=1000)
+    u0, _, _ = ctx.solve(out["row_ptr"], out["col_idx"], out["val"][:out["nnz"]], out["b"])
+    params, info = cvmod.fit(ctx, w, u0, epochs=epochs, paths_per_knot=min(256, max(16, 2 ** 16 // xy.shape[0])))
+    t_train = info["collect_ms"] + info["train_ms"]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    table = ctx.mlp_bake(params, w, 257)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    t_bake = e0.elapsed_time(e1)
+    res = {"workload": w["name"], "plain": {"n_paths": n_plain, "rmse": rmse_plain, "gpu_ms": t_plain}}
+    for mode, spec, extra in [("network", pdd.CVSpec("network", params=params), 0.0),
+                              ("grad_lut", pdd.CVSpec("grad_lut", table=table), t_bake)]:
+        sweep = []
+        for N in sweep_n:
+            r, t = run(N, spec)
+            sweep.append({"n_paths": N, "rmse": r, "gpu_ms": t})
+        ok = [p for p in sweep if p["rmse"] <= rmse_plain]
+        best = min(ok, key=lambda p: p["n_paths"]) if ok else None
+        eq = min(sweep, key=lambda p: abs(p["gpu_ms"] - t_plain))   # closest to equal GPU time
+        entry = {"sweep": sweep, "rmse_at_equal_time": eq}
+        if best:
+            entry.update({"smallest_n_reaching_plain_rmse": best["n_paths"],
+                          "time_ratio_vs_plain": best["gpu_ms"] / t_plain,
+                          "time_ratio_vs_plain_with_training": (best["gpu_ms"] + t_train + extra) / t_plain,
+                          "time_ratio_vs_plain_with_training_amortised":
+                              (best["gpu_ms"] + (t_train + extra) / seeds) / t_plain,
+                          "rmse_time_ratio": best["rmse"] * best["gpu_ms"] / (rmse_plain * t_plain)})
+        res[mode] = entry
+    res["training"] = {"pairs": info["pairs"], "adam_steps": info["steps"], "gpu_ms": t_train,
+                       "bake_ms": t_bake}
+    return res
+
+
+# ---- runs ---------------------------------------------------------------------
+def time_single(ctx, w, steps, warmup, lut=None):
+    import torch
+    out = ctx.assemble(w, lut=lut)                 # allocates outputs, builds caches
+    ctx.sync()
+    for _ in range(warmup):
+        ctx.assemble(w, out=out, lut=lut)
+    ctx.sync()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.assemble(w, out=out, lut=lut)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, launches = ctx.kernel_ms()
+    ctx.set_timing(False)
+    diag = out["diag"].view(-1, 8)
+    return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3,
+                path_steps=float(diag[:, 0].sum().item()), paths=float(diag[:, 1].sum().item()),
+                n=int(out["n"]), nnz=int(out["nnz"]))
+
+
+def time_batched(steps, warmup):
+    """64 instances in one launch: eager launches for the kernel time, then a
+    captured graph replayed `steps` times for the throughput."""
+    import torch
+    from paper_2301_05780_amd import pdd, workloads
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = pdd.Context(0, stream=stream)
+        ws = workloads.batched()
+        arr, outs = ctx.batch_arrays(ws)
+        ctx.assemble_batch(ws, arr=arr)
+        ctx.sync()
+        for _ in range(warmup):
+            ctx.assemble_batch(ws, arr=arr)
+        ctx.set_timing(True)
+        for _ in range(3):
+            ctx.assemble_batch(ws, arr=arr)
+        ctx.sync()
+        kern_ms, launches = ctx.kernel_ms()
+        ctx.set_timing(False)
+        ctx.graph_begin()
+        ctx.assemble_batch(ws, arr=arr)
+        nodes = ctx.graph_end()
+        ctx.graph_launch()
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.graph_launch()
+        ctx.sync()
+        elapsed = time.perf_counter() - t0
+        ps = sum(float(o["diag"].view(-1, 8)[:, 0].sum().item()) for o in outs)
+        paths = sum(float(o["diag"].view(-1, 8)[:, 1].sum().item()) for o in outs)
+        grid, block, tickets = ctx.last_launch()
+        ctx.close()
+    return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3, path_steps=ps, paths=paths,
+                n=sum(int(o["n"]) for o in outs), nnz=sum(int(o["nnz"]) for o in outs),
+                launch={"grid": grid, "block": block, "tickets": tickets, "graph_nodes": nodes})
+
+
+def copy_calibration():
+    """A plain device copy of known size (256 MiB, three times) for scaling the
+    FETCH_SIZE and WRITE_SIZE counters."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="varcoef", choices=["varcoef", "poisson_small"])
+    ap.add_argument("--workload", default="varcoef", choices=["varcoef", "poisson_small", "large_lut", "batched"])
     ap.add_argument("--exit-rule", default="gm", choices=["gm", "naive"])
     ap.add_argument("--cpu-knots", type=int, default=32)
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cv-compare", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the assembly shards by knot rows and "
-              "this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU only: the assembly shards by knot rows, and this build "
+              "runs and measures the one-GPU share (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     from paper_2301_05780_amd import pdd, workloads
 
-    w = workloads.varcoef(args.exit_rule) if args.workload == "varcoef" else workloads.poisson_small(args.exit_rule)
-    if args.workload == "poisson_small":
-        w["precision"] = "fp32"
-    ctx = pdd.Context(0)
-    out = ctx.assemble(w)                     # allocates outputs, builds caches
-    ctx.sync()
-    for _ in range(args.warmup):
-        ctx.assemble(w, out=out)
-    ctx.sync()
+    lut = None
+    if args.workload == "batched":
+        r = time_batched(args.steps, args.warmup)
+        w = dict(workloads.batched()[0], name="batched", kind="amplitude")
+        desc = ("batched: 64 amplitude-family instances (a ~ U(0, 0.8), H in {4,6,8,12,16}, knot spacing "
+                "1/64..1/256, N ~ U[2e3, 2e4], h = 1e-4) in one persistent launch, replayed from a HIP graph")
+        launch = r["launch"]
+    else:
+        if args.workload == "varcoef":
+            w = workloads.varcoef(args.exit_rule)
+        elif args.workload == "large_lut":
+            w = workloads.large_lut(args.exit_rule)
+            lut = torch.from_numpy(workloads.poisson_lut(w["lut_n"])).cuda()
+        else:
+            w = workloads.poisson_small(args.exit_rule)
+            w["precision"] = "fp32"
+        ctx = pdd.Context(0)
+        r = time_single(ctx, w, args.steps, args.warmup, lut=lut)
+        grid, block, tickets = ctx.last_launch()
+        launch = {"grid": grid, "block": block, "tickets": tickets}
+        desc = (f"{w['name']}: {w['kind']} coefficients, {w['H']}x{w['H']} subdomains, knot spacing "
+                f"1/{w['H'] * w['m']}, N={w['n_paths']}, h={w['h']}, {w['exit_rule']} exits")
+        if w["kind"] == "lut":
+            desc += f", {w['lut_n']}^2 float32 coefficient table"
 
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.assemble(w, out=out)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kern_ms, launches = ctx.kernel_ms()
-    ctx.set_timing(False)
-
-    diag = out["diag"].view(-1, pdd.DIAG_WIDTH)
-    steps_per_launch = float(diag[:, 0].sum().item())
-    paths = float(diag[:, 1].sum().item())
-    value = steps_per_launch * args.steps / elapsed
-    kavg = kern_ms / max(launches, 1) / 1e3
-    ops = ALG_OPS_PER_STEP[w["kind"]]
+    steps_per_launch = r["path_steps"]
+    value = steps_per_launch * args.steps / r["elapsed"]
+    kavg = r["kavg_s"]
+    ops = ALG_OPS[w["kind"]]
     achieved = ops * steps_per_launch / kavg / 1e12
-    grid, block, tickets = ctx.last_launch()
-
     rec = {
-        "metric": "Euler-Maruyama path-steps/s building G,b",
+        "metric": "Euler-Maruyama path-steps/s building G,b; RMSE·time plain vs neural CV",
         "value": value,
         "unit": "path-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": r["elapsed"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 paths / f64 accumulation",
-        "data": "synthetic (formula-defined manufactured BVP)",
-        "config": {"workload": f"{w['name']}: {w['kind']} coefficients, {w['H']}x{w['H']} subdomains, "
-                               f"knot spacing 1/{w['H'] * w['m']}, N={w['n_paths']}, h={w['h']}, "
-                               f"{w['exit_rule']} exits",
-                   "knots": int(out["n"]), "nnz": int(out["nnz"]), "paths": int(paths),
+        "dtype": "f32",
+        "data": "synthetic (formula-defined manufactured BVP; inputs resident in HBM)",
+        "config": {"workload": desc, "knots": r["n"], "nnz": r["nnz"], "paths": int(r["paths"]),
                    "path_steps_per_step": int(steps_per_launch),
-                   "mean_steps_per_path": steps_per_launch / paths,
-                   "launch": {"grid": grid, "block": block, "tickets": tickets}},
+                   "mean_steps_per_path": steps_per_launch / r["paths"], "launch": launch,
+                   "accumulation": "f64"},
         "kernel_ms_avg": kavg * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "ops_per_path_step": ops,
-                     "fp32_flop_frac": FP32_FLOP_PER_STEP[w["kind"]] * steps_per_launch / kavg / 1e12
-                     / FP32_PEAK_TFLOPS},
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": committed_traffic(args.workload),
+                     "ops_per_path_step": ops, "kernel_source": kernel_source_hash(),
+                     "fp32_flop_frac": FP32_FLOP[w["kind"]] * steps_per_launch / kavg / 1e12 / FP32_PEAK_TFLOPS},
     }
-    ctx.close()
+    if args.workload != "batched":
+        if args.workload == "varcoef" and not args.no_cv_compare:
+            rec["cv_comparison"] = {
+                "note": ("RMSE: mean over 16 seeds of the interface RMSE vs u*; gpu_ms: median assembly-kernel "
+                         "time per seed; with_training adds the whole training (pair collection + Adam) to one "
+                         "run, _amortised divides it by the 16 seeds one trained network serves"),
+                "poisson_small": cv_comparison(ctx, workloads.poisson_small("gm"), 1000,
+                                               (1000, 500, 250, 125, 63, 32)),
+                "varcoef": cv_comparison(ctx, workloads.varcoef("gm"), 10000,
+                                         (10000, 5000, 2500, 1250, 625, 313)),
+            }
+        ctx.close()
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_knots, workers)
+        if w["kind"] == "lut":
+            workers = 1                       # the float64 table is 1 GiB per process
+        cw = dict(w)
+        if args.workload == "batched":
+            cw = workloads.batched()[0]
+        rec["cpu_baseline"] = cpu_baseline(cw, args.cpu_knots if w["kind"] != "lut" else 8, workers)
     print(json.dumps(rec), flush=True)
 
 

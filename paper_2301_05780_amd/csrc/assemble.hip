@@ -140,18 +140,29 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
   uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>));
   double* rows = reinterpret_cast<double*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>) +
                                            QCAP * sizeof(uint32_t));
-  const uint32_t nw = gridDim.x * waves_per_block;
-  // next ticket this wave takes: fixed stride (static schedule, reproducible
-  // sums) or claimed from a device counter (dynamic schedule, balanced)
+  // next ticket this wave takes: fixed stride over the whole order (static
+  // schedule, reproducible sums), fixed stride over its XCD's share of the
+  // order (static, spatially ordered tickets: the workgroups of one XCD, which
+  // share an L2, work on neighbouring knots), or claimed from a device counter
+  // (dynamic schedule, balanced)
+  uint32_t t_stride = gridDim.x * waves_per_block, t_end = (uint32_t)P.n_tickets;
+  uint32_t next_ticket = blockIdx.x * waves_per_block + wid;
+  if (P.xcd_begin) {
+    const uint32_t x = blockIdx.x & 7u;
+    const uint32_t blocks_x = (gridDim.x - x + 7u) >> 3;
+    t_stride = blocks_x * waves_per_block;
+    next_ticket = (uint32_t)P.xcd_begin[x] + (blockIdx.x >> 3) * waves_per_block + wid;
+    t_end = (uint32_t)P.xcd_begin[x + 1];
+  }
   auto claim = [&](uint32_t prev) __attribute__((always_inline)) -> uint32_t {
     if (P.ticket_counter) {
       uint32_t v = 0;
       if (lane == 0) v = atomicAdd(P.ticket_counter, 1u);
       return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
     }
-    return prev + nw;
+    return prev + t_stride;
   };
-  uint32_t next_ticket = P.ticket_counter ? claim(0) : blockIdx.x * waves_per_block + wid;
+  if (P.ticket_counter) next_ticket = claim(0);
 
   // wave-uniform ticket state of the two rows
   int tk0 = -1, tk1 = -1;
@@ -379,7 +390,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
         int tgt = -1;
         if ((old ? tk1 : tk0) < 0) tgt = old;
         else if ((cur ? tk1 : tk0) < 0) tgt = cur;
-        if (tgt < 0 || next_ticket >= (uint32_t)P.n_tickets) break;
+        if (tgt < 0 || next_ticket >= t_end) break;
         acquire(tgt);
         cur = tgt;
         continue;

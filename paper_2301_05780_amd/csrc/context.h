@@ -40,8 +40,14 @@ struct TicketCache {
   std::vector<int32_t> npk;       // paths per knot
   int32_t per_ticket = 0;
   uint32_t inst = 0;
+  bool spatial = false;           // spatial order (tabulated coefficients) instead of longest-first
   int64_t n_tickets = 0;
   DeviceBuffer tickets, ticket_begin, n_paths, order;
+  // spatial order: cumulative expected cost along the order, and the XCD
+  // split of the order for the grid it was last computed for
+  std::vector<double> cum_cost;
+  int32_t xcd_grid = -1;
+  DeviceBuffer xcd_begin;
 };
 
 // Device-side tables of one batch of instances (rebuilt when the batch changes).

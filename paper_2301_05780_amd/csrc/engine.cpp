@@ -138,13 +138,23 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
   const int64_t waves = grid * (block / 64);
 
-  // about seven tickets per wave (static stride stays balanced), at least 256 paths each
+  // Tabulated coefficients make the path memory-bound on table gathers: order
+  // the tickets spatially (subdomains in Morton order) and give each XCD a
+  // contiguous share, so the workgroups that share an L2 gather from one
+  // neighbourhood; cut knots into more tickets so that the share in flight on
+  // one XCD covers few knots.  Otherwise: about seven tickets per wave, longest
+  // expected first (the static stride stays balanced); at least 256 paths each.
+  const bool spatial = job.coeffs.kind == PDD_COEF_LUT;
   int64_t per_ticket = ctx->force_per_ticket;
-  if (per_ticket <= 0) per_ticket = std::max<int64_t>(256, (total + 7 * waves - 1) / (7 * waves));
+  if (per_ticket <= 0) {
+    const int64_t per_wave = spatial ? 256 : 7;
+    per_ticket = std::max<int64_t>(256, (total + per_wave * waves - 1) / (per_wave * waves));
+  }
 
-  // tickets (cached while geometry, path counts and ticket size repeat)
+  // tickets (cached while geometry, path counts, ticket size and order repeat)
   TicketCache* tc = ctx->tickets.get();
-  if (!tc || tc->geo != gc || tc->per_ticket != per_ticket || tc->npk != npk || tc->inst != run.instance) {
+  if (!tc || tc->geo != gc || tc->per_ticket != per_ticket || tc->npk != npk || tc->inst != run.instance ||
+      tc->spatial != spatial) {
     if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: tables not cached; run the same call once before capturing");
     auto fresh = std::make_unique<TicketCache>();
     fresh->geo = gc;
@@ -171,10 +181,33 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
       if ((int64_t)tk.size() > INT32_MAX) return bad(ctx, PDD_EUNSUPPORTED, "too many tickets");
       tb[k + 1] = (int32_t)tk.size();
     }
-    // longest-expected-first order (stable: ties keep knot order)
     std::vector<int32_t> order(tk.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    if (spatial) {
+      // subdomain of each knot in Morton (Z) order, knots and path ranges in order within it
+      auto spread = [](uint32_t v) {
+        v &= 0xFFFFu;
+        v = (v | (v << 8)) & 0x00FF00FFu;
+        v = (v | (v << 4)) & 0x0F0F0F0Fu;
+        v = (v | (v << 2)) & 0x33333333u;
+        v = (v | (v << 1)) & 0x55555555u;
+        return v;
+      };
+      std::vector<uint32_t> key(tk.size());
+      for (size_t i = 0; i < tk.size(); ++i) {
+        const int32_t k = tk[i].knot;
+        const uint32_t sx = (uint32_t)(g.ix[k] / job.knots.m), sy = (uint32_t)(g.iy[k] / job.knots.m);
+        key[i] = spread(sx) | (spread(sy) << 1);
+      }
+      std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+      fresh->cum_cost.resize(order.size() + 1);
+      fresh->cum_cost[0] = 0.0;
+      for (size_t i = 0; i < order.size(); ++i) fresh->cum_cost[i + 1] = fresh->cum_cost[i] + cost[order[i]];
+    } else {
+      // longest-expected-first order (stable: ties keep knot order)
+      std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    }
+    fresh->spatial = spatial;
     fresh->n_tickets = (int64_t)tk.size();
     if ((e = fresh->tickets.reserve(tk.size() * sizeof(Ticket))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(tickets)");
     if ((e = fresh->order.reserve(order.size() * 4)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(order)");
@@ -192,6 +225,30 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   const int64_t need_waves = tc->n_tickets;
   grid = std::min<int64_t>(grid, (need_waves + block / 64 - 1) / (block / 64));
   grid = std::max<int64_t>(grid, 1);
+
+  // XCD split of the spatial order (static schedule, at least one workgroup
+  // per XCD): XCD x, holding ceil((grid - x) / 8) of the workgroups, gets a
+  // contiguous share of the order with the same fraction of the expected cost
+  const bool xcd_split = tc->spatial && ctx->schedule == PDD_SCHEDULE_STATIC && grid >= 8;
+  if (xcd_split && tc->xcd_grid != (int32_t)grid) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: XCD split not cached for this grid; run once before capturing");
+    int32_t xb[9];
+    xb[0] = 0;
+    const double total_cost = tc->cum_cost.back();
+    int64_t blocks_before = 0;
+    for (int x = 0; x < 8; ++x) {
+      blocks_before += (grid - x + 7) / 8;
+      const double target = total_cost * (double)blocks_before / (double)grid;
+      const auto it = std::lower_bound(tc->cum_cost.begin(), tc->cum_cost.end(), target);
+      xb[x + 1] = (x == 7) ? (int32_t)tc->n_tickets
+                           : std::max(xb[x], (int32_t)std::min<int64_t>(it - tc->cum_cost.begin(), tc->n_tickets));
+    }
+    if ((e = tc->xcd_begin.reserve(sizeof(xb))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(xcd split)");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(tc->xcd_begin.ptr, xb, sizeof(xb), hipMemcpyHostToDevice)) != hipSuccess)
+      return check_hip(ctx, e, "upload xcd split");
+    tc->xcd_grid = (int32_t)grid;
+  }
 
   const size_t partial_bytes = (size_t)tc->n_tickets * row_len * sizeof(double);
   if (partial_bytes > ctx->partial.bytes) {
@@ -211,6 +268,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.tickets = tc->tickets.as<Ticket>();
   P.order = tc->order.as<int32_t>();
   P.n_tickets = (int32_t)tc->n_tickets;
+  P.xcd_begin = xcd_split ? tc->xcd_begin.as<int32_t>() : nullptr;
   P.row_len = row_len;
   P.slot_len = slot_len;
   P.partial = ctx->partial.as<double>();

@@ -56,8 +56,12 @@ struct AsmParams {
   const KnotDesc* desc;
   const Ticket* tickets;      // batched: Ticket.inst indexes `insts`, Ticket.knot the concatenated descs
   const InstDesc* insts;      // batched launches only (nullptr otherwise)
-  const int32_t* order;       // schedule: ticket ids, longest expected work first
+  const int32_t* order;       // schedule: ticket ids in the order they are handed out
   int32_t n_tickets;
+  // static schedule split by XCD (nullable): the waves of the workgroups with
+  // blockIdx % 8 == x take order[xcd_begin[x] .. xcd_begin[x+1]) among
+  // themselves, in a fixed stride
+  const int32_t* xcd_begin;
   int32_t row_len;            // doubles per partial row: 4 slot_len + 8
   int32_t slot_len;           // G slots per side
   int32_t L;                  // lattice intervals per direction
