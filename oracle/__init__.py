@@ -18,4 +18,5 @@ Modules
   assemble  Euler-Maruyama / Gobet-Menozzi paths and the rows of G, b (eqs. 9, 20-25)
   solve     linear solve of G u = b and interface errors
   mlp       2-64-64-1 tanh network v(x) for the martingale control variate (eqs. 11, 37-38)
+  evaluate  point values inside the subdomains from the knot values (eq. 8 on each square, Sec. 3.3)
 """
