@@ -198,10 +198,15 @@ def cv_comparison(ctx, w, n_plain, sweep_n, seeds=16, epochs=4):
 
 
 # ---- runs ---------------------------------------------------------------------
-def time_single(ctx, w, steps, warmup, lut=None):
+def time_single(ctx, w, steps, warmup, lut=None, tune=False):
     import torch
     out = ctx.assemble(w, lut=lut)                 # allocates outputs, builds caches
     ctx.sync()
+    tuned = None
+    if tune:
+        arr, _ = ctx.batch_arrays([w], outs=[out], lut=lut)
+        ms, report = ctx.autotune(arr, reps=2)
+        tuned = {"best_kernel_ms": ms, "shape": ctx.last_launch()}
     for _ in range(warmup):
         ctx.assemble(w, out=out, lut=lut)
     ctx.sync()
@@ -217,7 +222,7 @@ def time_single(ctx, w, steps, warmup, lut=None):
     diag = out["diag"].view(-1, 8)
     return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3,
                 path_steps=float(diag[:, 0].sum().item()), paths=float(diag[:, 1].sum().item()),
-                n=int(out["n"]), nnz=int(out["nnz"]))
+                n=int(out["n"]), nnz=int(out["nnz"]), tuned=tuned)
 
 
 def time_batched(steps, warmup):
@@ -232,6 +237,7 @@ def time_batched(steps, warmup):
         arr, outs = ctx.batch_arrays(ws)
         ctx.assemble_batch(ws, arr=arr)
         ctx.sync()
+        tuned_ms, _ = ctx.autotune(arr, reps=1)        # block size, grid, ticket size, schedule
         for _ in range(warmup):
             ctx.assemble_batch(ws, arr=arr)
         ctx.set_timing(True)
@@ -257,7 +263,8 @@ def time_batched(steps, warmup):
         ctx.close()
     return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3, path_steps=ps, paths=paths,
                 n=sum(int(o["n"]) for o in outs), nnz=sum(int(o["nnz"]) for o in outs),
-                launch={"grid": grid, "block": block, "tickets": tickets, "graph_nodes": nodes})
+                launch={"grid": grid, "block": block, "tickets": tickets, "graph_nodes": nodes,
+                "autotuned_kernel_ms": tuned_ms})
 
 
 def copy_calibration():
@@ -286,6 +293,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv-compare", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the launch-shape autotuner before timing (on by default)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -317,9 +326,10 @@ def main():
             w = workloads.poisson_small(args.exit_rule)
             w["precision"] = "fp32"
         ctx = pdd.Context(0)
-        r = time_single(ctx, w, args.steps, args.warmup, lut=lut)
+        r = time_single(ctx, w, args.steps, args.warmup, lut=lut, tune=args.autotune)
         grid, block, tickets = ctx.last_launch()
-        launch = {"grid": grid, "block": block, "tickets": tickets}
+        launch = {"grid": grid, "block": block, "tickets": tickets, "autotuned": args.autotune}
+        ctx.set_launch(0, 0, 0)                   # later runs (control-variate comparison) size themselves
         desc = (f"{w['name']}: {w['kind']} coefficients, {w['H']}x{w['H']} subdomains, knot spacing "
                 f"1/{w['H'] * w['m']}, N={w['n_paths']}, h={w['h']}, {w['exit_rule']} exits")
         if w["kind"] == "lut":

@@ -115,7 +115,7 @@ struct GeoView {
 };
 
 template <int KIND, bool F64, int CV, bool BATCH>
-__global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
+__device__ __forceinline__ void assemble_body(const AsmParams& P) {
   using R = typename std::conditional<F64, double, float>::type;
   constexpr bool CVON = CV != PDD_CV_NONE;
   extern __shared__ double smem[];
@@ -511,6 +511,20 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
   }
 }
 
+template <int KIND, bool F64, int CV, bool BATCH>
+__global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
+  assemble_body<KIND, F64, CV, BATCH>(P);
+}
+
+// float32 closed-form families without a control variate: capped at 80
+// VGPRs, i.e. 6 waves per SIMD (measured 4-12 % faster than the uncapped 5
+// waves; with the gradient-table control variate the extra spills cost more
+// than the occupancy gains)
+template <int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_assemble_w6(AsmParams P) {
+  assemble_body<KIND, false, PDD_CV_NONE, false>(P);
+}
+
 // Sum a knot's partial rows (ticket order, then side order) into its CSR row,
 // b entry and diagnostics.  One wave per knot.
 __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
@@ -564,7 +578,10 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
 
 template <int KIND, bool F64, int CV, bool BATCH = false>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
+  if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND != PDD_COEF_LUT)
+    return reinterpret_cast<const void*>(&k_assemble_w6<KIND>);
+  else
+    return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
 }
 
 template <bool F64>

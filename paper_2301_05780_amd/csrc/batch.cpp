@@ -353,8 +353,9 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   char buf[256];
   for (int32_t i = 0; i < n_inst; ++i) {
     const pdd_instance& q = inst[i];
-    snprintf(buf, sizeof(buf), "%d:%d:%d:%d:%.17g:%lld:%d:%d:%.17g;", q.coeffs.kind, q.part.H, q.knots.m, q.knots.ext,
-             q.run.h, (long long)q.run.n_paths, q.run.precision, q.run.exit_rule, q.coeffs.param[0]);
+    snprintf(buf, sizeof(buf), "%d:%d:%d:%d:%d:%.17g:%lld:%d:%d:%.17g:%.17g:%.17g:%.17g:%.17g;", q.coeffs.kind,
+             q.coeffs.lut_n, q.part.H, q.knots.m, q.knots.ext, q.run.h, (long long)q.run.n_paths, q.run.precision,
+             q.run.exit_rule, q.coeffs.param[0], q.part.x0, q.part.x1, q.part.y0, q.part.y1);
     sig += buf;
   }
   for (const auto& c : ctx->tune_cache) {

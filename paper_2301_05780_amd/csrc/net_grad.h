@@ -139,29 +139,31 @@ __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, floa
 }
 
 // float64 grad v of one point from float32 parameters (staged in LDS).
-__device__ __forceinline__ void net_grad_f64(const float* __restrict__ th, double x, double y, double& gx,
-                                             double& gy) {
-  double h1[MLP_W], g1[MLP_W];
+// grad v = sum_j g2_j c_j with g2_j = (1 - h2_j^2) w3_j and
+// c_j = sum_k W2[j][k] (1 - h1_k^2) W1[k]: the same sum as
+// W1^T [(1 - h1^2) * (W2^T g2)] taken in another order, which keeps only h1
+// live across the loop over j (64 doubles instead of 128).
+__device__ __forceinline__ void net_grad_f64(const float* th, double x, double y, double& gx, double& gy) {
+  double h1[MLP_W];
 #pragma unroll
-  for (int k = 0; k < MLP_W; ++k) {
+  for (int k = 0; k < MLP_W; ++k)
     h1[k] = tanh((double)th[OW1 + 2 * k] * x + (double)th[OW1 + 2 * k + 1] * y + (double)th[OB1 + k]);
-    g1[k] = 0.0;
-  }
+  double ax = 0.0, ay = 0.0;
+#pragma unroll 1
   for (int j = 0; j < MLP_W; ++j) {
-    double z = (double)th[OB2 + j];
+    double z = (double)th[OB2 + j], cx = 0.0, cy = 0.0;
 #pragma unroll
-    for (int k = 0; k < MLP_W; ++k) z += (double)th[OW2 + j * MLP_W + k] * h1[k];
+    for (int k = 0; k < MLP_W; ++k) {
+      const double w = (double)th[OW2 + j * MLP_W + k];
+      z += w * h1[k];
+      const double s = w * (1.0 - h1[k] * h1[k]);
+      cx += s * (double)th[OW1 + 2 * k];
+      cy += s * (double)th[OW1 + 2 * k + 1];
+    }
     const double h2 = tanh(z);
     const double g2 = (1.0 - h2 * h2) * (double)th[OW3 + j];
-#pragma unroll
-    for (int k = 0; k < MLP_W; ++k) g1[k] += g2 * (double)th[OW2 + j * MLP_W + k];
-  }
-  double ax = 0.0, ay = 0.0;
-#pragma unroll
-  for (int k = 0; k < MLP_W; ++k) {
-    const double d = (1.0 - h1[k] * h1[k]) * g1[k];
-    ax += d * (double)th[OW1 + 2 * k];
-    ay += d * (double)th[OW1 + 2 * k + 1];
+    ax += g2 * cx;
+    ay += g2 * cy;
   }
   gx = ax;
   gy = ay;

@@ -241,17 +241,18 @@ class Context:
                     b=torch.empty(n, dtype=torch.float64, device=dev),
                     diag=torch.empty(n * DIAG_WIDTH, dtype=torch.float64, device=dev))
 
-    def _instance(self, w, out, precision=None):
-        par = (C.c_double * 4)(*(list(w.get("param", ())) + [0.0] * 4)[:4])
+    def _instance(self, w, out, precision=None, lut=None):
         run = Run(int(w["seed"]) & (2 ** 64 - 1), int(w.get("instance", 0)), PRECISION[precision or w["precision"]],
                   EXIT[w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), None, None, None)
-        return Instance(Coeffs(KIND[w["kind"]], 0, par, None), partition_of(w), knots_of(w), run,
+        return Instance(self.coeffs_of(w, lut), partition_of(w), knots_of(w), run,
                         _ptr(out["row_ptr"]), _ptr(out["col_idx"]), _ptr(out["val"]), _ptr(out["b"]),
                         _ptr(out["diag"]))
 
-    def batch_arrays(self, ws, outs=None, precision=None):
+    def batch_arrays(self, ws, outs=None, precision=None, lut=None):
+        """Instance array (and outputs) for pdd_assemble_batch / pdd_autotune;
+        ``lut`` is the table of tabulated-coefficient workloads (single instance)."""
         outs = outs or [self._outputs(w) for w in ws]
-        arr = (Instance * len(ws))(*[self._instance(w, o, precision) for w, o in zip(ws, outs)])
+        arr = (Instance * len(ws))(*[self._instance(w, o, precision, lut) for w, o in zip(ws, outs)])
         return arr, outs
 
     def assemble_batch(self, ws, outs=None, precision=None, arr=None):
