@@ -57,11 +57,21 @@ constexpr size_t net_lds_bytes() {
   else return ((sizeof(NetLds) + 15) / 16) * 16;
 }
 
-// per-wave LDS bytes: two row headers, the exit queue (records + meta words), two tally rows
-template <typename R>
+// Per-wave LDS of the cooperative table read (float32 LUT kernels): each
+// lane's cell and weights, and the 8 interpolated fields of each lane.
+struct CoopLds {
+  uint32_t cell[64];
+  float tx[64], ty[64];
+  float res[64 * 8];
+};
+static_assert(sizeof(CoopLds) % 16 == 0, "CoopLds alignment");
+
+// per-wave LDS bytes: two row headers, the exit queue (records + meta words),
+// two tally rows, and the cooperative-read block when COOP
+template <typename R, bool COOP>
 constexpr size_t wave_lds_bytes(int row_len) {
   return 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>) + QCAP * sizeof(uint32_t) +
-         2 * (size_t)row_len * sizeof(double);
+         2 * (size_t)row_len * sizeof(double) + (COOP ? sizeof(CoopLds) : 0);
 }
 
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
@@ -97,6 +107,46 @@ __device__ __forceinline__ uint32_t to_uniform_u(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Bilinear coefficients of the whole wave's points from the cell-major table.
+// A lookup needs 112 bytes of one 128-byte cell; with one lane per path, a
+// wave's eight 16-byte loads would each touch 64 scattered lines.  Instead,
+// round r has the 8 lanes of group g load the 8 float4 of the cell of path
+// 8 r + g (one line per group, eight lines per instruction) and interpolate
+// one field each; the fields go back to their path's lane through LDS.  The
+// interpolation is the per-lane read's (same cell, weights and formula).
+__device__ __forceinline__ void lut_fetch_coop(const CoefParams& cp, float x, float y, CoopLds* C, int lane,
+                                               Coef<float>& o) {
+  const int n = cp.lut_n;
+  float fx = (x - (float)cp.x0) * cp.lut_sx;
+  float fy = (y - (float)cp.y0) * cp.lut_sy;
+  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));     // NaN maps to 0: every address stays in the table
+  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  const int i = min((int)fx, n - 2);
+  const int j = min((int)fy, n - 2);
+  wave_sync();
+  C->cell[lane] = (uint32_t)j * (uint32_t)(n - 1) + (uint32_t)i;
+  C->tx[lane] = fx - (float)i;
+  C->ty[lane] = fy - (float)j;
+  wave_sync();
+  const int q = lane & 7, g = lane >> 3;
+  float4 v[8];                                // all eight loads in flight
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = cp.cells[(size_t)C->cell[8 * r + g] * 8 + q];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int pth = 8 * r + g;
+    const float tx = C->tx[pth], ty = C->ty[pth];
+    const float lo = v[r].x + tx * (v[r].y - v[r].x);
+    const float hi = v[r].z + tx * (v[r].w - v[r].z);
+    C->res[pth * 8 + q] = lo + ty * (hi - lo);
+  }
+  wave_sync();
+  const float4 a = reinterpret_cast<const float4*>(C->res)[2 * lane];
+  const float4 b = reinterpret_cast<const float4*>(C->res)[2 * lane + 1];
+  o.sxx = a.x; o.sxy = a.y; o.syy = a.z; o.dx = a.w;
+  o.dy = b.x; o.c = b.y; o.f = b.z;
+}
+
 // Per-buffer uniform values used at refill (kept in scalar registers).
 template <typename R>
 struct BufU {
@@ -118,6 +168,12 @@ template <int KIND, bool F64, int CV, bool BATCH>
 __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   using R = typename std::conditional<F64, double, float>::type;
   constexpr bool CVON = CV != PDD_CV_NONE;
+  // float32 table reads go through the cooperative read (except beside the
+  // network, whose registers leave no room for it); it and the network
+  // gradient are wave-wide operations, evaluated with every lane before each
+  // half step
+  constexpr bool COOP = KIND == PDD_COEF_LUT && !F64 && CV != PDD_CV_NETWORK;
+  constexpr bool WAVEWIDE = !F64 && (CV == PDD_CV_NETWORK || COOP);
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -134,31 +190,35 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     }
     __syncthreads();
   }
-  unsigned char* wbase = lds0 + net_lds_bytes<F64, CV>() + (size_t)wid * wave_lds_bytes<R>(RL);
+  unsigned char* wbase = lds0 + net_lds_bytes<F64, CV>() + (size_t)wid * wave_lds_bytes<R, COOP>(RL);
   WaveBuf* B = reinterpret_cast<WaveBuf*>(wbase);
   ExitRec<R>* Q = reinterpret_cast<ExitRec<R>*>(wbase + 2 * sizeof(WaveBuf));
   uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>));
   double* rows = reinterpret_cast<double*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>) +
                                            QCAP * sizeof(uint32_t));
+  CoopLds* CW = reinterpret_cast<CoopLds*>(wbase + wave_lds_bytes<R, false>(RL));   // COOP only
   // next ticket this wave takes: fixed stride over the whole order (static
   // schedule, reproducible sums), fixed stride over its XCD's share of the
   // order (static, spatially ordered tickets: the workgroups of one XCD, which
   // share an L2, work on neighbouring knots), or claimed from a device counter
   // (dynamic schedule, balanced)
-  uint32_t t_stride = gridDim.x * waves_per_block, t_end = (uint32_t)P.n_tickets;
+  uint32_t t_stride = gridDim.x * waves_per_block, t_end = (uint32_t)P.n_tickets, t_base = 0;
   uint32_t next_ticket = blockIdx.x * waves_per_block + wid;
+  uint32_t* counter = P.ticket_counter;
   if (P.xcd_begin) {
     const uint32_t x = blockIdx.x & 7u;
     const uint32_t blocks_x = (gridDim.x - x + 7u) >> 3;
     t_stride = blocks_x * waves_per_block;
-    next_ticket = (uint32_t)P.xcd_begin[x] + (blockIdx.x >> 3) * waves_per_block + wid;
+    t_base = (uint32_t)P.xcd_begin[x];
+    next_ticket = t_base + (blockIdx.x >> 3) * waves_per_block + wid;
     t_end = (uint32_t)P.xcd_begin[x + 1];
+    if (counter) counter += x;        // dynamic: one counter per XCD share
   }
   auto claim = [&](uint32_t prev) __attribute__((always_inline)) -> uint32_t {
-    if (P.ticket_counter) {
+    if (counter) {
       uint32_t v = 0;
-      if (lane == 0) v = atomicAdd(P.ticket_counter, 1u);
-      return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+      if (lane == 0) v = atomicAdd(counter, 1u);
+      return t_base + (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
     }
     return prev + t_stride;
   };
@@ -427,26 +487,37 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     uint32_t K = 0, fl = 0;
     CoefParams cpl = P.coef;
     if constexpr (BATCH) cpl.a = (double)la;
-    if constexpr (CV == PDD_CV_NETWORK && !F64) {
-      // the network gradient is a wave-wide MFMA product: evaluate it with
-      // every lane active, at each lane's left point, before each half step
+    if constexpr (WAVEWIDE) {
+      // the network gradient (a wave-wide MFMA product) and the cooperative
+      // table read run with every lane, at each lane's left point, before
+      // each half step; the step itself is per lane
       U4 r{};
-      float gx, gy;
-      net_grad_mfma(NL, x, y, gx, gy);
+      R gx = 0, gy = 0;
+      Coef<R> cc;
+      auto prep = [&]() __attribute__((always_inline)) {
+        if constexpr (CV == PDD_CV_NETWORK) net_grad_mfma(NL, x, y, gx, gy);
+        if constexpr (COOP) lut_fetch_coop(cpl, x, y, CW, lane, cc);
+      };
+      auto step = [&](R z0, R z1) __attribute__((always_inline)) {
+        if constexpr (CV == PDD_CV_GRAD_LUT) grad_lut(P, x, y, gx, gy);
+        if constexpr (COOP) em_step_c<KIND, R, CVON>(cc, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+        else em_step<KIND, R, CVON>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+      };
+      prep();
       if (active) {
         r = philox10(j, p, kn, inst, P.key0, P.key1);
         R z0, z1;
         box_muller(uniform32(r.a), uniform32(r.b), z0, z1);
-        em_step<KIND, R, true>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+        step(z0, z1);
         K = 2 * j + 1;
         ex = exit_test(fl);
       }
-      net_grad_mfma(NL, x, y, gx, gy);
+      prep();
       if (active) {
         if (!ex) {
           R z0, z1;
           box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
-          em_step<KIND, R, true>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+          step(z0, z1);
           K = 2 * j + 2;
           ex = exit_test(fl);
         }
@@ -530,7 +601,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
   const int lane = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (F.ticket_counter && blockIdx.x == 0 && threadIdx.x == 0) *F.ticket_counter = 0u;
+  if (F.ticket_counter && blockIdx.x == 0 && threadIdx.x < 8) F.ticket_counter[threadIdx.x] = 0u;
   if (k >= F.n) return;
   const KnotDesc d = F.desc[k];
   const int tb = F.ticket_begin[k], te = F.ticket_begin[k + 1];
@@ -630,14 +701,15 @@ const void* assemble_kernel(int precision, int kind, int cv, bool batch) {
 
 }  // namespace
 
-size_t assemble_lds_bytes(int precision, int row_len, int block, int cv_mode) {
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode) {
   const size_t waves = (size_t)block / 64;
   if (precision == PDD_FP64_SAME_STREAM) {
     const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<true, PDD_CV_NETWORK>() : 0;
-    return net + waves * wave_lds_bytes<double>(row_len);
+    return net + waves * wave_lds_bytes<double, false>(row_len);
   }
   const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<false, PDD_CV_NETWORK>() : 0;
-  return net + waves * wave_lds_bytes<float>(row_len);
+  return net + waves * (kind == PDD_COEF_LUT && cv_mode != PDD_CV_NETWORK ? wave_lds_bytes<float, true>(row_len)
+                                                                          : wave_lds_bytes<float, false>(row_len));
 }
 
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,

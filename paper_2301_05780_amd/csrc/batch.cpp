@@ -88,10 +88,10 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   auto shape = [&](int slot_len, int& blk, size_t& lds, int64_t& grid) -> pdd_status {
     const int row_len = 4 * slot_len + EX_COUNT;
     blk = block;
-    lds = assemble_lds_bytes(precision, row_len, blk, PDD_CV_NONE);
+    lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE);
     while (lds > 65536 && blk > 64) {
       blk /= 2;
-      lds = assemble_lds_bytes(precision, row_len, blk, PDD_CV_NONE);
+      lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE);
     }
     if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
     int per_cu = 0;
@@ -225,8 +225,8 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   }
   if (ctx->schedule == PDD_SCHEDULE_DYNAMIC && !ctx->ticket_counter.ptr) {
     if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble_batch: counter not allocated; run once before capturing");
-    if ((e = ctx->ticket_counter.reserve(sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(counter)");
-    if ((e = hipMemset(ctx->ticket_counter.ptr, 0, sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMemset(counter)");
+    if ((e = ctx->ticket_counter.reserve(8 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(counter)");
+    if ((e = hipMemset(ctx->ticket_counter.ptr, 0, 8 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMemset(counter)");
   }
 
   // patterns into the caller's arrays

@@ -108,6 +108,7 @@ struct pdd_ctx {
   int schedule = PDD_SCHEDULE_STATIC;
   pdd::DeviceBuffer ticket_counter;
   pdd::DeviceBuffer lut_max;         // LUT + GM: table-wide |sigma| maxima
+  pdd::DeviceBuffer lut_cells;       // float32 LUT assembly: cell-major copy of the table
   // shape of the last assembly launch (reported by pdd_last_launch)
   int last_grid = 0, last_block = 0;
   int64_t last_tickets = 0;
@@ -137,6 +138,9 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);
 // LUT family under the GM rule: enqueue the table-bound kernels and point
 // P.coef.lut_max at their result (no-op otherwise).
 pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
+// LUT family in float32: enqueue the cell-major copy of the table and point
+// P.coef.cells at it (no-op otherwise).
+pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
 pdd_status run_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_partition& part, const pdd_knots& kn,
                               const double* u_knots, int64_t n_pts, const double* xy, const pdd_run& run, double* u,
                               double* se);

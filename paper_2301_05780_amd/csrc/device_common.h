@@ -257,12 +257,11 @@ __device__ __forceinline__ float g_at(float x, float y) {
 // One Euler-Maruyama step of eq. (9) with coefficients frozen at the left
 // point.  With the control variate (CVON), Xi gains -Y (sigma^T grad v) . dW
 // (eq. 37), grad v = (gx, gy) taken at the same left point.
+// The step with the coefficients at the left point already in `c`.
 template <int KIND, typename R, bool CVON = false>
-__device__ __forceinline__ void em_step(const CoefParams& cp, R h, R sq, R z0, R z1, R& x, R& y, R& Y, R& Z,
-                                        R gx = 0, R gy = 0, R* Xi = nullptr) {
+__device__ __forceinline__ void em_step_c(const Coef<R>& c, R h, R sq, R z0, R z1, R& x, R& y, R& Y, R& Z,
+                                          R gx = 0, R gy = 0, R* Xi = nullptr) {
   using T = Traits<KIND>;
-  Coef<R> c;
-  coef_at<KIND>(cp, x, y, c);
   if constexpr (std::is_same<R, double>::value) {
 #pragma clang fp contract(off)
     const double dWx = sq * z0, dWy = sq * z1;
@@ -315,6 +314,14 @@ __device__ __forceinline__ void em_step(const CoefParams& cp, R h, R sq, R z0, R
     if constexpr (T::reaction) Y = Y * (1.0f + c.c * h);
     x = nx; y = ny; Z = nZ;
   }
+}
+
+template <int KIND, typename R, bool CVON = false>
+__device__ __forceinline__ void em_step(const CoefParams& cp, R h, R sq, R z0, R z1, R& x, R& y, R& Y, R& Z,
+                                        R gx = 0, R gy = 0, R* Xi = nullptr) {
+  Coef<R> c;
+  coef_at<KIND>(cp, x, y, c);
+  em_step_c<KIND, R, CVON>(c, h, sq, z0, z1, x, y, Y, Z, gx, gy, Xi);
 }
 
 // Exit threshold of side o for the knot in `d` (NAIVE: the side line; GM: the

@@ -60,6 +60,24 @@ pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& 
   return PDD_OK;
 }
 
+pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing) {
+  if (co.kind != PDD_COEF_LUT || run.precision != PDD_FP32_PRODUCTION) return PDD_OK;
+  if (run.cv && run.cv->mode == PDD_CV_NETWORK) return PDD_OK;     // that kernel reads the node table per lane
+  const size_t bytes = (size_t)(co.lut_n - 1) * (size_t)(co.lut_n - 1) * 128;
+  if (bytes > ((size_t)64 << 30))
+    return bad(ctx, PDD_EUNSUPPORTED, "LUT too large for the float32 cell-major copy (at most 64 GiB, lut_n <= 23171)");
+  hipError_t e;
+  if (ctx->lut_cells.bytes < bytes) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "LUT cell table not allocated; run the same call once before capturing");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    if ((e = ctx->lut_cells.reserve(bytes)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(lut cells)");
+  }
+  if ((e = launch_lut_cells(co.lut, co.lut_n, ctx->lut_cells.as<float4>(), ctx->stream)) != hipSuccess)
+    return check_hip(ctx, e, "launch LUT cells");
+  P.coef.cells = ctx->lut_cells.as<float4>();
+  return PDD_OK;
+}
+
 void fill_asm_params(const GeoCache& gcr, const pdd_coeffs& co, const pdd_run& run, AsmParams& P) {
   const Geometry& g = gcr.g;
   std::memset(&P, 0, sizeof(P));
@@ -125,10 +143,10 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   const int row_len = 4 * slot_len + EX_COUNT;
   const int cv_mode = run.cv ? run.cv->mode : PDD_CV_NONE;
   int block = ctx->force_block ? ctx->force_block : 256;
-  size_t lds = assemble_lds_bytes(run.precision, row_len, block, cv_mode);
+  size_t lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode);
   while (lds > 65536 && block > 64) {
     block /= 2;
-    lds = assemble_lds_bytes(run.precision, row_len, block, cv_mode);
+    lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode);
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;
@@ -226,10 +244,12 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   grid = std::min<int64_t>(grid, (need_waves + block / 64 - 1) / (block / 64));
   grid = std::max<int64_t>(grid, 1);
 
-  // XCD split of the spatial order (static schedule, at least one workgroup
-  // per XCD): XCD x, holding ceil((grid - x) / 8) of the workgroups, gets a
-  // contiguous share of the order with the same fraction of the expected cost
-  const bool xcd_split = tc->spatial && ctx->schedule == PDD_SCHEDULE_STATIC && grid >= 8;
+  // XCD split of the spatial order (at least one workgroup per XCD): XCD x,
+  // holding ceil((grid - x) / 8) of the workgroups, gets a contiguous share
+  // of the order with the same fraction of the expected cost; its waves take
+  // the share in a fixed stride (static) or from the XCD's own counter
+  // (dynamic)
+  const bool xcd_split = tc->spatial && grid >= 8;
   if (xcd_split && tc->xcd_grid != (int32_t)grid) {
     if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: XCD split not cached for this grid; run once before capturing");
     int32_t xb[9];
@@ -276,11 +296,12 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.dump = run.dump_paths > 0 ? run.dump : nullptr;
   P.ticket_counter = nullptr;
   if ((st = prepare_lut_bound(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
+  if ((st = prepare_lut_cells(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
   if (ctx->schedule == PDD_SCHEDULE_DYNAMIC) {
     if (!ctx->ticket_counter.ptr) {
       if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: counter not allocated; run once before capturing");
-      if ((e = ctx->ticket_counter.reserve(sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(counter)");
-      if ((e = hipMemset(ctx->ticket_counter.ptr, 0, sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMemset(counter)");
+      if ((e = ctx->ticket_counter.reserve(8 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(counter)");
+      if ((e = hipMemset(ctx->ticket_counter.ptr, 0, 8 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMemset(counter)");
     }
     P.ticket_counter = ctx->ticket_counter.as<uint32_t>();
   }

@@ -50,6 +50,10 @@ struct CoefParams {
   // LUT kind under the Gobet-Menozzi rule: max |sxx|, |sxy|, |syy| over the
   // table's nodes as float bit patterns (device, written by launch_lut_bound)
   const uint32_t* lut_max;
+  // float32 LUT kernels: the table re-laid cell by cell (launch_lut_cells):
+  // cell (i, j) holds 8 float4, float4 q = field q at the corners
+  // (i, j), (i+1, j), (i, j+1), (i+1, j+1); q = 7 is zero padding (128 B per cell)
+  const float4* cells;
 };
 
 struct AsmParams {
@@ -76,7 +80,8 @@ struct AsmParams {
   const double* u_ref;        // nullable
   const int32_t* lattice;     // (L+1)^2 lattice -> knot index (for u_ref)
   double* dump;               // nullable
-  uint32_t* ticket_counter;   // dynamic schedule: zeroed work counter; nullptr: static stride
+  uint32_t* ticket_counter;   // dynamic schedule: 8 zeroed work counters (one per XCD share when
+                              // xcd_begin is set, else the first); nullptr: static stride
   // control variate
   int32_t cv_mode;            // PDD_CV_*
   int32_t cv_lut_n;
@@ -101,7 +106,7 @@ struct FinalizeParams {
   double* val;
   double* b;
   double* diag;                  // nullable
-  uint32_t* ticket_counter;      // reset to zero for the next assembly (nullable)
+  uint32_t* ticket_counter;      // 8 counters reset to zero for the next assembly (nullable)
 };
 
 // Launchers (defined in assemble.hip).  Return hipSuccess or the launch error.
@@ -114,8 +119,10 @@ hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot,
 // Table-wide maxima of |sxx|, |sxy|, |syy| of a LUT (lut.hip): out[0..2]
 // as float bit patterns, out[3] unused.  Two kernels, no memset.
 hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipStream_t stream);
+// Cell-major copy of a LUT (lut.hip): cells[(j (n-1) + i) 8 + q], (n-1)^2 cells of 128 B.
+hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream);
 // Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
-size_t assemble_lds_bytes(int precision, int row_len, int block, int cv_mode);
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode);
 // Kernel attribute query for occupancy-based grid sizing.
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
                               int* blocks_per_cu);

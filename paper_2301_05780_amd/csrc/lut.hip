@@ -1,4 +1,9 @@
-// Table-wide bounds of a coefficient look-up table.
+// Table-wide bounds of a coefficient look-up table, and its cell-major copy.
+//
+// The float32 assembly reads the table cooperatively (eight lanes fetch one
+// path's cell as one 128-byte line), so it reads a copy laid out cell by
+// cell: the four corners of each field contiguous, the seven fields of a cell
+// in one line.
 //
 // The Gobet-Menozzi test of the LUT family (Sec. 2.3) shifts each side
 // inwards by c_GM sqrt(a_nn(P)) sqrt(h) with a_nn taken at the projection P,
@@ -46,7 +51,34 @@ __global__ __launch_bounds__(BLK) void k_lut_bound(const float4* lut, int64_t no
   }
 }
 
+// One thread per output float4: cell c = j (n-1) + i, field q.
+__global__ __launch_bounds__(BLK) void k_lut_cells(const float* __restrict__ lut, int32_t n, float4* __restrict__ cells) {
+  const int64_t m = n - 1;
+  const int64_t total = m * m * 8;
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x; t < total; t += stride) {
+    const int q = (int)(t & 7);
+    const int64_t c = t >> 3;
+    const int64_t j = c / m, i = c - j * m;
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (q < 7) {
+      const float* p00 = lut + (j * n + i) * PDD_LUT_STRIDE + q;
+      const float* p01 = p00 + (int64_t)n * PDD_LUT_STRIDE;
+      v = make_float4(p00[0], p00[PDD_LUT_STRIDE], p01[0], p01[PDD_LUT_STRIDE]);
+    }
+    cells[t] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream) {
+  const int64_t total = (int64_t)(lut_n - 1) * (lut_n - 1) * 8;
+  const int64_t want = (total + BLK - 1) / BLK;
+  const unsigned grid = (unsigned)(want < 16384 ? want : 16384);
+  hipLaunchKernelGGL(k_lut_cells, dim3(grid), dim3(BLK), 0, stream, lut, lut_n, cells);
+  return hipGetLastError();
+}
 
 hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipStream_t stream) {
   const int64_t nodes = (int64_t)lut_n * lut_n;
