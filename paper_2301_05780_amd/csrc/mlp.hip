@@ -1,6 +1,6 @@
 // The control-variate network v(x) = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3
 // (2 -> 64 -> 64 -> 1) on the GPU: pointwise evaluation with input gradient,
-// the single-workgroup Adam trainer, the grad-v table bake, and the kernel
+// the single-workgroup Adam trainer (float32 MFMA), the grad-v table bake, and the kernel
 // that collects (path point, tail score) training pairs from the method's own
 // paths.
 //
@@ -96,13 +96,24 @@ __global__ __launch_bounds__(BLK) void k_mlp_bake(const float* __restrict__ para
   }
 }
 
-// ---- single-workgroup trainer ---------------------------------------------
-// One workgroup runs every Adam step (the steps are sequential).  The batch is
-// processed in chunks of 32 points by 256 threads, 8 per point, each owning 8
-// hidden units; per-point vectors are staged in LDS and every thread then
-// accumulates the gradient entries it owns (parameter q = tid + 256 i) over
-// the chunk.  Parameters stay in LDS; Adam moments live in global memory and
-// are touched once per step.
+// ---- single-workgroup trainer (float32 MFMA) ---------------------------------
+// One workgroup of four waves runs every Adam step (the steps are
+// sequential).  A step's minibatch is processed in rounds of 128 points, 32
+// per wave.  Per wave and round, with points as the columns c = lane % 32 and
+// the two half-waves h = lane / 32 splitting the contraction index:
+//   h1 = tanh(W1 x + b1)                          VALU, 32 values per lane
+//   z2^T = W2 h1^T                                v_mfma_f32_32x32x2_f32, K = 64
+//   h2 = tanh(z2 + b2), v = w3 . h2 + b3, dv = (v - t) / B
+//   dz2^T = dv (1 - h2^2) w3                      in registers
+//   gW2 += dz2^T h1                               MFMA, K = the 32 points
+//   dh1^T = W2^T dz2^T, dz1 = dh1 (1 - h1^2)      MFMA, K = 64
+//   gW1, gb1, gb2, gw3, gb3                       VALU sums over the points
+// The contraction order of z2 and dh1 follows the accumulator's row order
+// (row = 8 (r / 4) + 4 h + r % 4 of register r), so h1 and dz2 serve as
+// operands straight from registers; the batch contractions read the wave's
+// LDS copies.  The four waves' gradients are summed in wave order (fixed,
+// reproducible), then every thread applies Adam to the parameters it owns.
+// Parameters stay in LDS; Adam moments live in global memory.
 struct TrainArgs {
   float* params;
   float* m;
@@ -121,132 +132,227 @@ struct TrainArgs {
   float* losses;          // per step, nullable
 };
 
-constexpr int OWN = (MLP_PARAMS + BLK - 1) / BLK;   // 18
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-__global__ __launch_bounds__(BLK) void k_mlp_train(TrainArgs A) {
-  __shared__ float th[MLP_PARAMS];
-  __shared__ float sh1[32][MLP_W + 1], sh2[32][MLP_W + 1], sdz2[32][MLP_W + 1], sdz1[32][MLP_W + 1];
-  __shared__ float sx[32][2], sdv[32];
-  __shared__ float sred[BLK / 64];
-  const int tid = threadIdx.x;
-  const int pt = tid >> 3, part = tid & 7;      // point within the chunk, hidden-unit slice
-  for (int i = tid; i < MLP_PARAMS; i += BLK) th[i] = A.params[i];
+constexpr int TW = 4;                 // waves per workgroup
+constexpr int H1S = 68;               // row stride of the h1 copy [point][unit] (16-byte aligned rows)
+constexpr int DZS = 36;               // row stride of the [unit][point] copies
+constexpr int PARAM_PAD = ((MLP_PARAMS + 3) / 4) * 4;
+
+struct TrainWaveLds {
+  float h1[32 * H1S];                 // h1[c][k]
+  float dz[64 * DZS];                 // dz2^T[j][c], later dz1^T[k][c]
+  float dh[64 * DZS];                 // dv_c h2[j][c]
+  float xy[32][2];
+};
+
+constexpr size_t train_lds_bytes() { return PARAM_PAD * sizeof(float) + TW * sizeof(TrainWaveLds); }
+
+// accumulator register r of a 32 x 32 tile holds row 8 (r / 4) + 4 h + r % 4
+__device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+__global__ __launch_bounds__(TW * 64) void k_mlp_train(TrainArgs A) {
+  extern __shared__ float tlds[];
+  float* th = tlds;
+  TrainWaveLds* WL = reinterpret_cast<TrainWaveLds*>(tlds + PARAM_PAD);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, c = lane & 31;
+  TrainWaveLds& L = WL[w];
+  for (int i = tid; i < MLP_PARAMS; i += TW * 64) th[i] = A.params[i];
   __syncthreads();
   const float inv_b = 1.0f / (float)A.batch;
+  const int rounds = (A.batch + 32 * TW - 1) / (32 * TW);
 
   for (int step = 0; step < A.steps; ++step) {
-    float g[OWN];
+    f32x16 gw2[2][2];
 #pragma unroll
-    for (int i = 0; i < OWN; ++i) g[i] = 0.0f;
-    float loss = 0.0f;
-    for (int c0 = 0; c0 < A.batch; c0 += 32) {
-      const int p = c0 + pt;
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) gw2[a][b] = f32x16{};
+    float g_b2 = 0.0f, g_w3 = 0.0f, g_w1x = 0.0f, g_w1y = 0.0f, g_b1 = 0.0f, g_b3 = 0.0f, loss = 0.0f;
+
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int p = rd * 32 * TW + 32 * w + c;
+      const bool inb = p < A.batch;
       const int64_t oi = ((int64_t)step * A.batch + p) % A.n_order;
-      const int32_t oidx = p < A.batch ? A.order[oi] : -1;
+      const int32_t oidx = inb ? A.order[oi] : -1;
       const bool valid = oidx >= 0 && (int64_t)oidx < A.n_points;
       const int32_t idx = valid ? oidx : 0;
       const float x = valid ? A.xy[2 * (int64_t)idx] : 0.0f;
       const float y = valid ? A.xy[2 * (int64_t)idx + 1] : 0.0f;
-      if (part == 0) { sx[pt][0] = x; sx[pt][1] = y; }
-      // layer 1 (8 units per thread)
-      for (int u = 0; u < 8; ++u) {
-        const int k = part * 8 + u;
-        sh1[pt][k] = tanhf(th[OW1 + 2 * k] * x + th[OW1 + 2 * k + 1] * y + th[OB1 + k]);
-      }
-      __syncthreads();
-      // layer 2 and output
-      float vpart = 0.0f;
-      float h2v[8];
-      for (int u = 0; u < 8; ++u) {
-        const int j = part * 8 + u;
-        float z = th[OB2 + j];
-        for (int k = 0; k < MLP_W; ++k) z += th[OW2 + j * MLP_W + k] * sh1[pt][k];
-        h2v[u] = tanhf(z);
-        sh2[pt][j] = h2v[u];
-        vpart += th[OW3 + j] * h2v[u];
-      }
-      // sum the 8 slices of a point (adjacent lanes)
-      vpart += __shfl_xor(vpart, 1, 64);
-      vpart += __shfl_xor(vpart, 2, 64);
-      vpart += __shfl_xor(vpart, 4, 64);
-      const float v = vpart + th[OB3];
-      const float t = valid ? A.target[idx] : v;
-      const float r = valid ? (v - t) : 0.0f;
-      const float dv = r * inv_b;
-      if (part == 0) { sdv[pt] = dv; loss += 0.5f * r * r * inv_b; }
-      for (int u = 0; u < 8; ++u) {
-        const int j = part * 8 + u;
-        sdz2[pt][j] = dv * th[OW3 + j] * (1.0f - h2v[u] * h2v[u]);
-      }
-      __syncthreads();
-      // back to layer 1
-      for (int u = 0; u < 8; ++u) {
-        const int k = part * 8 + u;
-        float d = 0.0f;
-        for (int j = 0; j < MLP_W; ++j) d += th[OW2 + j * MLP_W + k] * sdz2[pt][j];
-        const float h = sh1[pt][k];
-        sdz1[pt][k] = d * (1.0f - h * h);
-      }
-      __syncthreads();
-      // accumulate owned gradient entries over the chunk
+      const float t = valid ? A.target[idx] : 0.0f;
+      if (h == 0) { L.xy[c][0] = x; L.xy[c][1] = y; }
+      // layer 1: units k = 32 kb + acc_row(r, h) of point c
+      float h1r[2][16];
 #pragma unroll
-      for (int i = 0; i < OWN; ++i) {
-        const int q = tid + BLK * i;
-        if (q >= MLP_PARAMS) break;
-        float acc = 0.0f;
-        if (q < OB1) {
-          const int k = q >> 1, dd = q & 1;
-          for (int pp = 0; pp < 32; ++pp) acc += sdz1[pp][k] * sx[pp][dd];
-        } else if (q < OW2) {
-          const int k = q - OB1;
-          for (int pp = 0; pp < 32; ++pp) acc += sdz1[pp][k];
-        } else if (q < OB2) {
-          const int j = (q - OW2) / MLP_W, k = (q - OW2) % MLP_W;
-          for (int pp = 0; pp < 32; ++pp) acc += sdz2[pp][j] * sh1[pp][k];
-        } else if (q < OW3) {
-          const int j = q - OB2;
-          for (int pp = 0; pp < 32; ++pp) acc += sdz2[pp][j];
-        } else if (q < OB3) {
-          const int j = q - OW3;
-          for (int pp = 0; pp < 32; ++pp) acc += sdv[pp] * sh2[pp][j];
-        } else {
-          for (int pp = 0; pp < 32; ++pp) acc += sdv[pp];
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int k = 32 * kb + acc_row(r, h);
+          const float v = tanhf(th[OW1 + 2 * k] * x + th[OW1 + 2 * k + 1] * y + th[OB1 + k]);
+          h1r[kb][r] = v;
+          L.h1[c * H1S + k] = v;
         }
-        g[i] += acc;
+      // layer 2: z2^T[j][c], contraction k(s, h) = 32 (s / 16) + acc_row(s % 16, h)
+      f32x16 z[2];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        z[jb] = f32x16{};
+        const float* wrow = th + OW2 + (32 * jb + c) * MLP_W;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {          // four steps s = 4q .. 4q+3 read four consecutive k
+          const float4 a4 = *reinterpret_cast<const float4*>(wrow + 32 * (q >> 2) + 8 * (q & 3) + 4 * h);
+          const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int s2 = 4 * q + e;
+            z[jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], h1r[s2 >> 4][s2 & 15], z[jb], 0, 0, 0);
+          }
+        }
+      }
+      // output, residual and dz2 (registers: rows j = 32 jb + acc_row(r, h) of column c)
+      float vpart = 0.0f;
+      float dz2r[2][16];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int j = 32 * jb + acc_row(r, h);
+          const float h2 = tanhf(z[jb][r] + th[OB2 + j]);
+          vpart += th[OW3 + j] * h2;
+          z[jb][r] = h2;
+          dz2r[jb][r] = (1.0f - h2 * h2) * th[OW3 + j];
+        }
+      const float v = vpart + __shfl_xor(vpart, 32, 64) + th[OB3];
+      const float res = valid ? v - t : 0.0f;
+      const float dv = res * inv_b;
+      if (h == 0) { loss += 0.5f * res * res * inv_b; g_b3 += dv; }
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int j = 32 * jb + acc_row(r, h);
+          dz2r[jb][r] *= dv;
+          L.dz[j * DZS + c] = dz2r[jb][r];
+          L.dh[j * DZS + c] = dv * z[jb][r];
+        }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // gb2[j], gw3[j] for j = lane: sums over the 32 points
+      {
+        const float4* dzr = reinterpret_cast<const float4*>(L.dz + lane * DZS);
+        const float4* dhr = reinterpret_cast<const float4*>(L.dh + lane * DZS);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float4 a4 = dzr[q], b4 = dhr[q];
+          g_b2 += (a4.x + a4.y) + (a4.z + a4.w);
+          g_w3 += (b4.x + b4.y) + (b4.z + b4.w);
+        }
+      }
+      // gW2[j][k] += sum_c dz2^T[j][c] h1[c][k]; contraction c(s, h) = 16 h + s
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        const float* arow = L.dz + (32 * jb + c) * DZS + 16 * h;
+        float av[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 a4 = *reinterpret_cast<const float4*>(arow + 4 * q);
+          av[4 * q] = a4.x; av[4 * q + 1] = a4.y; av[4 * q + 2] = a4.z; av[4 * q + 3] = a4.w;
+        }
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int s2 = 0; s2 < 16; ++s2)
+            gw2[jb][kb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s2], L.h1[(16 * h + s2) * H1S + 32 * kb + c],
+                                                               gw2[jb][kb], 0, 0, 0);
+      }
+      // backward: dh1^T[k][c] = sum_j W2[j][k] dz2^T[j][c], contraction j(s, h) = 32 (s / 16) + acc_row(s % 16, h)
+      float dz1r[2][16];
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        f32x16 d = f32x16{};
+#pragma unroll
+        for (int s2 = 0; s2 < 32; ++s2) {
+          const int j = 32 * (s2 >> 4) + acc_row(s2 & 15, h);
+          d = __builtin_amdgcn_mfma_f32_32x32x2f32(th[OW2 + j * MLP_W + 32 * kb + c], dz2r[s2 >> 4][s2 & 15], d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dz1r[kb][r] = d[r] * (1.0f - h1r[kb][r] * h1r[kb][r]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) L.dz[(32 * kb + acc_row(r, h)) * DZS + c] = dz1r[kb][r];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // gW1[k][.], gb1[k] for k = lane: sums over the 32 points
+      {
+        const float4* dzr = reinterpret_cast<const float4*>(L.dz + lane * DZS);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float4 a4 = dzr[q];
+          const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int cc = 4 * q + e;
+            g_w1x += av[e] * L.xy[cc][0];
+            g_w1y += av[e] * L.xy[cc][1];
+            g_b1 += av[e];
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    // loss and gb3 of the wave (lanes with h == 0 hold one point each)
+    for (int off = 32; off > 0; off >>= 1) {
+      loss += __shfl_xor(loss, off, 64);
+      g_b3 += __shfl_xor(g_b3, off, 64);
+    }
+    // sum the four waves' gradients into G (the wave buffers are free now), in wave order
+    __syncthreads();
+    float* G = reinterpret_cast<float*>(WL);
+    for (int ww = 0; ww < TW; ++ww) {
+      if (w == ww) {
+        auto put = [&](int q, float v) __attribute__((always_inline)) { G[q] = (ww == 0) ? v : G[q] + v; };
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              put(OW2 + (32 * jb + acc_row(r, h)) * MLP_W + 32 * kb + c, gw2[jb][kb][r]);
+        put(OW1 + 2 * lane, g_w1x);
+        put(OW1 + 2 * lane + 1, g_w1y);
+        put(OB1 + lane, g_b1);
+        put(OB2 + lane, g_b2);
+        put(OW3 + lane, g_w3);
+        if (lane == 0) put(OB3, g_b3);
+        if (lane == 0) G[MLP_PARAMS] = (ww == 0) ? loss : G[MLP_PARAMS] + loss;
       }
       __syncthreads();
     }
-    // loss of the step (block reduction)
-    float lw = loss;
-    for (int off = 32; off > 0; off >>= 1) lw += __shfl_xor(lw, off, 64);
-    if ((tid & 63) == 0) sred[tid >> 6] = lw;
-    __syncthreads();
-    if (tid == 0 && A.losses) A.losses[step] = sred[0] + sred[1] + sred[2] + sred[3];
+    if (tid == 0 && A.losses) A.losses[step] = G[MLP_PARAMS];
     if (!A.update) {
-#pragma unroll
-      for (int i = 0; i < OWN; ++i) {
-        const int q = tid + BLK * i;
-        if (q < MLP_PARAMS) A.grad_out[q] = g[i];
-      }
+      for (int q = tid; q < MLP_PARAMS; q += TW * 64) A.grad_out[q] = G[q];
       return;
     }
     // Adam (bias-corrected), beta1 = 0.9, beta2 = 0.999, eps = 1e-8
     const int tstep = A.step0 + step + 1;
     const float c1 = 1.0f - powf(0.9f, (float)tstep);
     const float c2 = 1.0f - powf(0.999f, (float)tstep);
-#pragma unroll
-    for (int i = 0; i < OWN; ++i) {
-      const int q = tid + BLK * i;
-      if (q >= MLP_PARAMS) break;
-      const float mq = 0.9f * A.m[q] + 0.1f * g[i];
-      const float sq = 0.999f * A.s[q] + 0.001f * g[i] * g[i];
+    for (int q = tid; q < MLP_PARAMS; q += TW * 64) {
+      const float g = G[q];
+      const float mq = 0.9f * A.m[q] + 0.1f * g;
+      const float sq = 0.999f * A.s[q] + 0.001f * g * g;
       A.m[q] = mq;
       A.s[q] = sq;
       th[q] -= A.lr * (mq / c1) / (sqrtf(sq / c2) + 1e-8f);
     }
     __syncthreads();
   }
-  for (int i = tid; i < MLP_PARAMS; i += BLK) A.params[i] = th[i];
+  for (int i = tid; i < MLP_PARAMS; i += TW * 64) A.params[i] = th[i];
 }
 
 }  // namespace
@@ -275,7 +381,11 @@ pdd_status run_mlp_train(pdd_ctx* ctx, float* params, float* m, float* s, int64_
   A.update = grad_out ? 0 : 1;
   A.grad_out = grad_out;
   A.losses = losses;
-  hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(BLK), 0, ctx->stream, A);
+  // more than 64 KiB of LDS for one workgroup (gfx950 allows 160 KiB)
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_train),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)train_lds_bytes());
+  if (e != hipSuccess) return check_hip(ctx, e, "hipFuncSetAttribute(mlp_train)");
+  hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(TW * 64), train_lds_bytes(), ctx->stream, A);
   return check_hip(ctx, hipGetLastError(), "launch mlp_train");
 }
 
