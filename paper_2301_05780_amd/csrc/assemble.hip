@@ -599,34 +599,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 // Sum a knot's partial rows (ticket order, then side order) into its CSR row,
 // b entry and diagnostics.  One wave per knot.
 __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
+  extern __shared__ double fsum[];
   const int lane = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (F.ticket_counter && blockIdx.x == 0 && threadIdx.x < 8) F.ticket_counter[threadIdx.x] = 0u;
   if (k >= F.n) return;
-  const KnotDesc d = F.desc[k];
-  const int tb = F.ticket_begin[k], te = F.ticket_begin[k + 1];
-  const double N = (double)F.n_paths[k];
   const int RL = F.row_len, SL = F.slot_len;
+  double* row = fsum + (size_t)(threadIdx.x >> 6) * RL;
+  const int tb = F.ticket_begin[k], te = F.ticket_begin[k + 1];
+  // the knot's partial rows summed slot by slot in ticket order (coalesced reads)
+  for (int i = lane; i < RL; i += 64) {
+    double sacc = 0.0;
+#pragma unroll 8
+    for (int t = tb; t < te; ++t) sacc += F.partial[(size_t)t * RL + i];
+    row[i] = sacc;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const KnotDesc d = F.desc[k];
+  const double N = (double)F.n_paths[k];
   for (int pos = F.row_ptr[k] + lane; pos < F.row_ptr[k + 1]; pos += 64) {
     const int col = F.col_idx[pos];
     if (col == (int)k) { F.val[pos] = 1.0; continue; }
     const int cx = F.knot_ij[2 * col], cy = F.knot_ij[2 * col + 1];
-    double s = 0.0;
+    double sv = 0.0;
     for (int o = 0; o < 4; ++o) {
       if ((d.bmask >> o) & 1) continue;
       const bool vert = (o == 0 || o == 2);
       const int on = vert ? cx : cy, q = vert ? cy : cx;
       if (on != d.at[o] || q < d.clo[o] || q > d.chi[o]) continue;
-      const int slot = o * SL + (q - d.clo[o]);
-      double so = 0.0;
-      for (int t = tb; t < te; ++t) so += F.partial[(size_t)t * RL + slot];
-      s += so;
+      sv += row[o * SL + (q - d.clo[o])];
     }
-    F.val[pos] = -s / N;
+    F.val[pos] = -sv / N;
   }
   if (lane < EX_COUNT) {
-    double e = 0.0;
-    for (int t = tb; t < te; ++t) e += F.partial[(size_t)t * RL + 4 * SL + lane];
+    const double e = row[4 * SL + lane];
     if (lane == EX_B) F.b[k] = e / N;
     if (F.diag) {
       // diag layout: sum K, N, exits E, N, W, S, sum s, sum s^2
@@ -729,9 +736,16 @@ hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int bloc
 }
 
 hipError_t launch_finalize(const FinalizeParams& p, hipStream_t stream) {
-  const int block = 256;
-  const int64_t grid = (p.n + 3) / 4;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(block), 0, stream, p);
+  // one summed row per wave in LDS (at most 160 KiB per workgroup)
+  const int block = (size_t)4 * p.row_len * sizeof(double) <= 163840 ? 256 : 64;
+  const int64_t grid = (p.n + block / 64 - 1) / (block / 64);
+  const size_t lds = (size_t)(block / 64) * p.row_len * sizeof(double);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_finalize),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(block), lds, stream, p);
   return hipGetLastError();
 }
 
