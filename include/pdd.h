@@ -332,6 +332,13 @@ enum { PDD_SCHEDULE_STATIC = 0, PDD_SCHEDULE_DYNAMIC = 1 };
  * Results do not depend on these except through float64 summation order. */
 pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t paths_per_ticket,
                           int32_t schedule);
+/* Deferred refill: a wave refills the lanes whose paths have exited only once
+ * at least min_idle of its 64 lanes are idle, or none is running (1, the
+ * default, refills at once; at most 64).  Larger values trade idle lanes for
+ * fewer refill passes.  Results do not depend on it except through float64
+ * summation order.  pdd_autotune also tries 8, 16 and 32 on its best shape
+ * and leaves the winner set. */
+pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle);
 /* Shape of the last assembly launch: grid, block and number of tickets. */
 pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets);
 /* enable != 0: bracket every assembly kernel launched from now on with a pair

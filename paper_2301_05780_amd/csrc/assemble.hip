@@ -444,6 +444,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     while (true) {
       const uint64_t idle = __ballot(!active);
       if (idle == 0) break;
+      // deferred refill: while some lanes still run, wait for enough idle ones
+      if (P.refill_min > 1 && idle != ~0ull && __popcll(idle) < P.refill_min) break;
       const int nx = cur ? nx1 : nx0, en = cur ? en1 : en0;
       if (nx >= en) {
         const int old = cur ^ 1;

@@ -251,6 +251,7 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   P.u_ref = nullptr;
   P.lattice = nullptr;
   P.ticket_counter = ctx->schedule == PDD_SCHEDULE_DYNAMIC ? ctx->ticket_counter.as<uint32_t>() : nullptr;
+  P.refill_min = ctx->refill_min;
 
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (ctx->timing && !capturing && ctx->ev_used < 4096) {
@@ -361,7 +362,7 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   for (const auto& c : ctx->tune_cache) {
     if (c.sig == sig) {
       ctx->force_block = c.block; ctx->force_grid = c.grid; ctx->force_per_ticket = c.per_ticket;
-      ctx->schedule = c.schedule;
+      ctx->schedule = c.schedule; ctx->refill_min = c.refill;
       *best_ms = c.ms;
       if (report && report_len > 0) snprintf(report, report_len, "cached: %s", c.report.c_str());
       return PDD_OK;
@@ -376,9 +377,33 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   };
   std::string rep;
   double best = 1e300;
-  int bb = 0, bg = 0, bt = 0, bs = 0;
+  int bb = 0, bg = 0, bt = 0, bs = 0, br = 1;
+  // mean kernel time of `reps` launches with the context's current shape
+  auto time_shape = [&](double* ms_out) -> pdd_status {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    const bool was = ctx->timing;
+    ctx->timing = true;
+    ctx->ev_used = 0;
+    pdd_status st = PDD_OK;
+    for (int r = 0; r < reps && st == PDD_OK; ++r) st = run_once();
+    double ms = 0.0;
+    for (int r = 0; r < ctx->ev_used && st == PDD_OK; ++r) {
+      float t = 0.0f;
+      if ((e = hipEventSynchronize(ctx->ev_pool[2 * r + 1])) != hipSuccess)
+        st = check_hip(ctx, e, "hipEventSynchronize");
+      else if ((e = hipEventElapsedTime(&t, ctx->ev_pool[2 * r], ctx->ev_pool[2 * r + 1])) != hipSuccess)
+        st = check_hip(ctx, e, "hipEventElapsedTime");
+      ms += t;
+    }
+    *ms_out = ms / std::max(ctx->ev_used, 1);
+    ctx->timing = was;
+    ctx->ev_used = 0;
+    return st;
+  };
   const int blocks[] = {256, 128};
   const int tickets[] = {256, 384, 512, 768, 1024};
+  ctx->refill_min = 1;
   for (int blk : blocks) {
     for (int per_cu_sub = 0; per_cu_sub < 2; ++per_cu_sub) {
       for (int ppt : tickets) {
@@ -397,25 +422,11 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
             ctx->force_grid = grid;
             if ((st = run_once()) != PDD_OK) return st;
           }
-          hipError_t e = hipStreamSynchronize(ctx->stream);
-          if (e != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
-          const bool was = ctx->timing;
-          ctx->timing = true;
-          ctx->ev_used = 0;
-          for (int r = 0; r < reps; ++r)
-            if ((st = run_once()) != PDD_OK) return st;
           double ms = 0.0;
-          for (int r = 0; r < ctx->ev_used; ++r) {
-            float t = 0.0f;
-            if ((e = hipEventSynchronize(ctx->ev_pool[2 * r + 1])) != hipSuccess) return check_hip(ctx, e, "hipEventSynchronize");
-            if ((e = hipEventElapsedTime(&t, ctx->ev_pool[2 * r], ctx->ev_pool[2 * r + 1])) != hipSuccess) return check_hip(ctx, e, "hipEventElapsedTime");
-            ms += t;
-          }
-          ms /= std::max(ctx->ev_used, 1);
-          ctx->timing = was;
-          ctx->ev_used = 0;
-          snprintf(buf, sizeof(buf), "block %3d grid %5d tickets %7lld ppt %5d %s: %.4f ms\n", ctx->last_block,
-                   ctx->last_grid, (long long)ctx->last_tickets, ppt, sched ? "dynamic" : "static ", ms);
+          if ((st = time_shape(&ms)) != PDD_OK) return st;
+          snprintf(buf, sizeof(buf), "block %3d grid %5d tickets %7lld ppt %5d %s refill  1: %.4f ms\n",
+                   ctx->last_block, ctx->last_grid, (long long)ctx->last_tickets, ppt,
+                   sched ? "dynamic" : "static ", ms);
           rep += buf;
           if (ms < best) {
             best = ms;
@@ -425,10 +436,23 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
       }
     }
   }
+  // deferred refill on the best shape: a wave waits until this many of its lanes are idle
   ctx->force_block = bb; ctx->force_grid = bg; ctx->force_per_ticket = bt; ctx->schedule = bs;
+  for (int refill : {8, 16, 32}) {
+    ctx->refill_min = refill;
+    double ms = 0.0;
+    pdd_status st = run_once();
+    if (st != PDD_OK) return st;
+    if ((st = time_shape(&ms)) != PDD_OK) return st;
+    snprintf(buf, sizeof(buf), "best shape, refill %2d: %.4f ms\n", refill, ms);
+    rep += buf;
+    if (ms < best) { best = ms; br = refill; }
+  }
+  ctx->refill_min = br;
   *best_ms = best;
   TuneEntry te;
-  te.sig = sig; te.block = bb; te.grid = bg; te.per_ticket = bt; te.schedule = bs; te.ms = best; te.report = rep;
+  te.sig = sig; te.block = bb; te.grid = bg; te.per_ticket = bt; te.schedule = bs; te.refill = br; te.ms = best;
+  te.report = rep;
   ctx->tune_cache.push_back(te);
   if (report && report_len > 0) snprintf(report, report_len, "%s", rep.c_str());
   return PDD_OK;

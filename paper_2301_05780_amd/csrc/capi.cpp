@@ -345,6 +345,13 @@ pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t pat
   return PDD_OK;
 }
 
+pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_refill: null context");
+  if (min_idle < 1 || min_idle > 64) return fail(ctx, PDD_EINVAL, "pdd_set_refill: need 1 <= min_idle <= 64");
+  ctx->refill_min = min_idle;
+  return PDD_OK;
+}
+
 pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets) {
   if (!ctx || !grid || !block || !tickets) return fail(nullptr, PDD_EINVAL, "pdd_last_launch: null argument");
   *grid = ctx->last_grid;

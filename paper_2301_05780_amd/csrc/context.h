@@ -68,7 +68,7 @@ struct BatchCache {
 
 struct TuneEntry {
   std::string sig;
-  int block, grid, per_ticket, schedule;
+  int block, grid, per_ticket, schedule, refill;
   double ms;
   std::string report;
 };
@@ -106,6 +106,7 @@ struct pdd_ctx {
   // launch overrides (0 = automatic), set by the tuner
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
   int schedule = PDD_SCHEDULE_STATIC;
+  int refill_min = 1;                // refill idle lanes once at least this many are idle
   pdd::DeviceBuffer ticket_counter;
   pdd::DeviceBuffer lut_max;         // LUT + GM: table-wide |sigma| maxima
   pdd::DeviceBuffer lut_cells;       // float32 LUT assembly: cell-major copy of the table

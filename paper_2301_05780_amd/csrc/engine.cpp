@@ -289,6 +289,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.order = tc->order.as<int32_t>();
   P.n_tickets = (int32_t)tc->n_tickets;
   P.xcd_begin = xcd_split ? tc->xcd_begin.as<int32_t>() : nullptr;
+  P.refill_min = ctx->refill_min;
   P.row_len = row_len;
   P.slot_len = slot_len;
   P.partial = ctx->partial.as<double>();

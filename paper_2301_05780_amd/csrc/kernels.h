@@ -66,6 +66,7 @@ struct AsmParams {
   // blockIdx % 8 == x take order[xcd_begin[x] .. xcd_begin[x+1]) among
   // themselves, in a fixed stride
   const int32_t* xcd_begin;
+  int32_t refill_min;         // refill a wave's idle lanes once at least this many are idle (>= 1)
   int32_t row_len;            // doubles per partial row: 4 slot_len + 8
   int32_t slot_len;           // G slots per side
   int32_t L;                  // lattice intervals per direction

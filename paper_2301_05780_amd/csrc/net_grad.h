@@ -26,16 +26,39 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-// Network operands staged in LDS for the MFMA path.
+// Network operands staged in LDS for the MFMA path (bf16).
+//   W1x: layer 1 as an MFMA with K = 8 used columns: for unit k,
+//        (W1x_hi, W1x_hi, W1x_lo, W1y_hi, W1y_hi, W1y_lo, b1_hi, b1_lo) against the
+//        point column (x_hi, x_lo, x_hi, y_hi, y_lo, y_hi, 1, 1): the hi/lo
+//        bf16 splits recover W1 x + b1 to about 2^-16 relative.
+//   W2b:  W2 [out][in].
+//   W2Tb: W2^T [in][out] scaled by w3[out] (folds the output weight into the
+//         backward product).
+//   Afin: the final contraction grad v = W1^T d as an MFMA: rows 0..3 are
+//         W1x_hi, W1y_hi, W1x_lo, W1y_lo, stored per (chunk, row, half) in the
+//         contraction order of the chunk.
 struct NetLds {
-  __bf16 W2b[MLP_W * MLP_W];    // W2 [out][in]
-  __bf16 W2Tb[MLP_W * MLP_W];   // W2^T [in][out]
-  float W1[2 * MLP_W], b1[MLP_W], b2[MLP_W], w3[MLP_W];
+  __bf16 W1x[MLP_W * 8];
+  __bf16 W2b[MLP_W * MLP_W];
+  __bf16 W2Tb[MLP_W * MLP_W];
+  __bf16 Afin[4 * 4 * 2 * 8];
+  float b2[MLP_W];
 };
 
 __device__ __forceinline__ float tanh_fast(float z) {
   const float e = __builtin_amdgcn_exp2f(z * 2.8853900817779268f);   // exp(2z)
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+__device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
+// unit of contraction slot i in chunk (kb, h) for lane half g: the row order
+// of the 32 x 32 accumulator
+__device__ __forceinline__ int chunk_unit(int kb, int h, int g, int i) {
+  return 32 * kb + 16 * h + 8 * (i >> 2) + 4 * g + (i & 3);
 }
 
 // Fill NetLds from the float32 parameter vector (all threads of the block).
@@ -44,13 +67,24 @@ __device__ __forceinline__ void net_stage(NetLds* N, const float* __restrict__ t
     const int o = i / MLP_W, k = i % MLP_W;
     const float w = th[OW2 + i];
     N->W2b[i] = (__bf16)w;
-    N->W2Tb[k * MLP_W + o] = (__bf16)w;
+    N->W2Tb[k * MLP_W + o] = (__bf16)(w * th[OW3 + o]);
   }
-  for (int i = threadIdx.x; i < 2 * MLP_W; i += blockDim.x) N->W1[i] = th[OW1 + i];
-  for (int i = threadIdx.x; i < MLP_W; i += blockDim.x) {
-    N->b1[i] = th[OB1 + i];
-    N->b2[i] = th[OB2 + i];
-    N->w3[i] = th[OW3 + i];
+  for (int k = threadIdx.x; k < MLP_W; k += blockDim.x) {
+    __bf16 xh, xl, yh, yl, bh, bl;
+    split_bf16(th[OW1 + 2 * k], xh, xl);
+    split_bf16(th[OW1 + 2 * k + 1], yh, yl);
+    split_bf16(th[OB1 + k], bh, bl);
+    __bf16* r = N->W1x + 8 * k;
+    r[0] = xh; r[1] = xh; r[2] = xl; r[3] = yh; r[4] = yh; r[5] = yl; r[6] = bh; r[7] = bl;
+    N->b2[k] = th[OB2 + k];
+  }
+  for (int e = threadIdx.x; e < 4 * 4 * 2 * 8; e += blockDim.x) {
+    const int i = e & 7, g = (e >> 3) & 1, m = (e >> 4) & 3, ch = e >> 6;
+    const int unit = chunk_unit(ch >> 1, ch & 1, g, i);
+    __bf16 xh, xl, yh, yl;
+    split_bf16(th[OW1 + 2 * unit], xh, xl);
+    split_bf16(th[OW1 + 2 * unit + 1], yh, yl);
+    N->Afin[e] = (m == 0) ? xh : (m == 1) ? yh : (m == 2) ? xl : yl;
   }
 }
 
@@ -63,38 +97,50 @@ __device__ __forceinline__ bf16x8 load_frag(const __bf16* row, int base) {
 
 // grad v at every lane's (x, y); all 64 lanes must be active.  The two
 // 32-point column blocks are processed one after the other to bound the live
-// operand fragments.
+// operand fragments.  Per block: layer 1, layer 2, the backward product and
+// the final contraction are four MFMA stages; tanh and the elementwise
+// factors run on the VALU.
 __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, float x, float y, float& gx, float& gy) {
   const int lane = (int)(threadIdx.x & 63);
   const int g = lane >> 5, c = lane & 31;
   const float xo = __shfl_xor(x, 32, 64), yo = __shfl_xor(y, 32, 64);
-  float own_x = 0.0f, own_y = 0.0f, oth_x = 0.0f, oth_y = 0.0f;
+  const bf16x8 zero8 = {};
+  float res_x[2], res_y[2];
 #pragma unroll 1
   for (int pb = 0; pb < 2; ++pb) {
     // the network operands are loop-invariant LDS data: keep the compiler
-    // from hoisting ~200 of them into registers for the whole kernel
+    // from hoisting them into registers for the whole kernel
     __asm__ __volatile__("" ::: "memory");
     const bool mine = (pb == g);
     const float xp = mine ? x : xo, yp = mine ? y : yo;
-    // layer 1: h1^T as B operands; chunk (kb, h) slot i holds k1 = 32 kb + 16 h + 8 (i / 4) + 4 g + i % 4
+    // layer 1: z1^T = W1x (32 units x 16) . X (16 x 32 points); only lanes of half 0 carry the 8 used rows
+    bf16x8 B1 = zero8;
+    if (g == 0) {
+      __bf16 xh, xl, yh, yl;
+      split_bf16(xp, xh, xl);
+      split_bf16(yp, yh, yl);
+      const __bf16 one = (__bf16)1.0f;
+      B1 = bf16x8{xh, xl, xh, yh, yl, yh, one, one};
+    }
     bf16x8 Bf[2][2];
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
+    for (int kb = 0; kb < 2; ++kb) {
+      const bf16x8 A1 = (g == 0) ? *reinterpret_cast<const bf16x8*>(N->W1x + 8 * (32 * kb + c)) : zero8;
+      const f32x16 z1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1, f32x16{}, 0, 0, 0);
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k1 = 32 * kb + 16 * h + 8 * (i >> 2) + 4 * g + (i & 3);
-          Bf[kb][h][i] = (__bf16)tanh_fast(N->W1[2 * k1] * xp + N->W1[2 * k1 + 1] * yp + N->b1[k1]);
-          // bound the scheduler's look-ahead so operand loads are not all issued up front
-          if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-        }
-    // layer 2: z2^T tile (ob) = sum over chunks W2[out rows][chunk] h1^T[chunk][points]
+      for (int r = 0; r < 16; ++r) {
+        Bf[kb][r >> 3][r & 7] = (__bf16)tanh_fast(z1[r]);
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // layer 2: z2^T tile (ob) = b2 + W2[out rows][chunk] h1^T[chunk][points]
     bf16x8 G2[2][2];
 #pragma unroll
     for (int ob = 0; ob < 2; ++ob) {
       const __bf16* wrow = N->W2b + (32 * ob + c) * MLP_W;
-      f32x16 acc = {};
+      f32x16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = N->b2[32 * ob + 8 * (r >> 2) + 4 * g + (r & 3)];
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
@@ -103,39 +149,45 @@ __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, floa
                                                         0);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int out = 32 * ob + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float h2 = tanh_fast(acc[r] + N->b2[out]);
-        G2[ob][r >> 3][r & 7] = (__bf16)((1.0f - h2 * h2) * N->w3[out]);
+        const float h2 = tanh_fast(acc[r]);
+        G2[ob][r >> 3][r & 7] = (__bf16)(1.0f - h2 * h2);
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     }
-    // backward: dh1^T tile (kb) = W2^T[k1 rows][chunk] g2^T[chunk][points]; chunk (ob, h)
-    float px = 0.0f, py = 0.0f;
+    // backward: dh1^T tile (kb) = (W2^T w3)[k1 rows][chunk] g2^T[chunk][points]; d = dh1 (1 - h1^2)
+    f32x16 fin = f32x16{};
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
       const __bf16* wrow = N->W2Tb + (32 * kb + c) * MLP_W;
-      f32x16 acc = {};
+      f32x16 acc = f32x16{};
 #pragma unroll
       for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_frag(wrow, 32 * ob + 16 * h + 4 * g), G2[ob][h], acc, 0, 0,
                                                         0);
+      bf16x8 D[2];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int k1 = 32 * kb + 8 * (r >> 2) + 4 * g + (r & 3);
         const float h1 = (float)Bf[kb][r >> 3][r & 7];
-        const float d = acc[r] * (1.0f - h1 * h1);
-        px += N->W1[2 * k1] * d;
-        py += N->W1[2 * k1 + 1] * d;
-        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        D[r >> 3][r & 7] = (__bf16)(acc[r] * (1.0f - h1 * h1));
+      }
+      // final contraction: rows 0..3 of W1^T (hi/lo splits) against d
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bf16x8 Af = (c < 4) ? *reinterpret_cast<const bf16x8*>(N->Afin + (((2 * kb + h) * 4 + c) * 2 + g) * 8)
+                                  : zero8;
+        fin = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af, D[h], fin, 0, 0, 0);
       }
     }
-    if (mine) { own_x = px; own_y = py; } else { oth_x = px; oth_y = py; }
+    // rows 0..3 sit in registers 0..3 of the lanes of half 0
+    res_x[pb] = fin[0] + fin[2];
+    res_y[pb] = fin[1] + fin[3];
   }
-  // a point's k1 rows are split between lanes c and c + 32
-  gx = own_x + __shfl_xor(oth_x, 32, 64);
-  gy = own_y + __shfl_xor(oth_y, 32, 64);
+  // block 0 holds the points of lanes 0..31, block 1 those of lanes 32..63 (in lanes 0..31)
+  const float tx = __shfl_xor(res_x[1], 32, 64), ty = __shfl_xor(res_y[1], 32, 64);
+  gx = g ? tx : res_x[0];
+  gy = g ? ty : res_y[0];
 }
 
 // float64 grad v of one point from float32 parameters (staged in LDS).

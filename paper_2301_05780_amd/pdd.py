@@ -97,6 +97,7 @@ def lib():
             "pdd_assemble": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots),
                              C.POINTER(Run), vp, vp, vp, vp, vp],
             "pdd_set_launch": [vp, i32, i32, i32, i32],
+            "pdd_set_refill": [vp, i32],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
             "pdd_assemble_batch": [vp, i32, vp],
@@ -202,6 +203,9 @@ class Context:
     def set_launch(self, block=0, grid=0, paths_per_ticket=0, schedule="static"):
         sched = {"static": 0, "dynamic": 1}[schedule]
         self.check(lib().pdd_set_launch(self.h, block, grid, paths_per_ticket, sched))
+
+    def set_refill(self, min_idle=1):
+        self.check(lib().pdd_set_refill(self.h, int(min_idle)))
 
     def last_launch(self):
         g, b, t = C.c_int32(), C.c_int32(), C.c_int64()

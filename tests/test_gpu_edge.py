@@ -141,3 +141,27 @@ def test_argument_validation(ctx):
     with pytest.raises(pdd.PddError) as e:
         ctx.assemble(dict(w, exit_rule="naive", h=-1.0))
     assert e.value.status == pdd.EINVAL
+
+
+@pytest.mark.parametrize("refill", [16, 64])
+def test_deferred_refill_matches_the_oracle(ctx, refill):
+    """A wave that refills only once `refill` lanes are idle (64: only when the
+    whole wave is idle) runs the same paths: the float64 sums may change order,
+    nothing else."""
+    w = dict(kind="varcoef", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=300, h=2e-3,
+             seed=21, precision="fp64", exit_rule="gm", instance=4)
+    g, ref = _oracle(w)
+    ctx.set_refill(refill)
+    try:
+        got = fetch(ctx.assemble(w), g)
+        ctx.sync()
+        assert_same_stream(got, g, ref)
+    finally:
+        ctx.set_refill(1)
+
+
+def test_refill_argument_validation(ctx):
+    for bad in (0, 65, -3):
+        with pytest.raises(pdd.PddError) as e:
+            ctx.set_refill(bad)
+        assert e.value.status == pdd.EINVAL
