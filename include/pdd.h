@@ -280,6 +280,12 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
 
 /* ---- control-variate network (eqs. 11, 37-38) ---------------------------- */
 
+/* Initial parameters (device params[PDD_MLP_PARAMS]): zero biases and
+ * Glorot-uniform weights, W1, W2 and w3 each uniform on (-lim, lim) with
+ * lim = sqrt(6 / (fan_in + fan_out)); parameter i draws the first word of
+ * Philox4x32-10 at counter (i, 0, 0, 0), key (seed lo, seed hi). */
+pdd_status pdd_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed);
+
 /* v and/or grad v of the 2-64-64-1 tanh network at n points (float32, device
  * arrays: params[PDD_MLP_PARAMS], xy[2n], v[n] nullable, grad[2n] nullable). */
 pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad);

@@ -457,7 +457,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         cur = tgt;
         continue;
       }
-      const int take = min(__popcll(idle), en - nx);
+      const int take = min((int)__popcll(idle), en - nx);   // int min (mixed types pick the double overload)
       const int rank = lane_rank(idle);
       if (!active && rank < take) {
         p = (uint32_t)(nx + rank);

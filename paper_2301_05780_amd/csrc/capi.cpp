@@ -261,6 +261,12 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
   return run_eval_subdomain(ctx, *coeffs, *part, *knots, u_knots, n_pts, xy, *run, u, se);
 }
 
+pdd_status pdd_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_init: null context");
+  if (!params) return fail(ctx, PDD_EINVAL, "pdd_mlp_init: null params");
+  return run_mlp_init(ctx, params, seed);
+}
+
 pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad) {
   if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_eval: null context");
   if (!params || !xy || n < 0 || (!v && !grad)) return fail(ctx, PDD_EINVAL, "pdd_mlp_eval: bad arguments");

@@ -15,6 +15,7 @@ constexpr int MLP_PARAMS = PDD_MLP_PARAMS;      // 4417
 constexpr int OW1 = 0, OB1 = 128, OW2 = 192, OB2 = 4288, OW3 = 4352, OB3 = 4416;
 static_assert(OB3 + 1 == MLP_PARAMS, "parameter layout");
 
+pdd_status run_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed);
 pdd_status run_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* g);
 pdd_status run_mlp_bake(pdd_ctx* ctx, const float* params, const pdd_partition& part, int32_t lut_n, float* out);
 pdd_status run_mlp_train(pdd_ctx* ctx, float* params, float* m, float* s, int64_t n_points, const float* xy,

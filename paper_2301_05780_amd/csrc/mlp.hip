@@ -355,7 +355,32 @@ __global__ __launch_bounds__(TW * 64) void k_mlp_train(TrainArgs A) {
   for (int i = tid; i < MLP_PARAMS; i += TW * 64) A.params[i] = th[i];
 }
 
+
+// Glorot-uniform weights, zero biases: parameter i of a weight matrix with
+// fan sum F is lim (2u - 1), lim = sqrt(6 / F), u the float64 uniform of the
+// first word of Philox4x32-10 at counter (i, 0, 0, 0), key (seed lo, seed hi)
+__global__ __launch_bounds__(BLK) void k_mlp_init(float* __restrict__ params, uint32_t k0, uint32_t k1) {
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  if (i >= MLP_PARAMS) return;
+  int fan = 0;
+  if (i < OB1) fan = MLP_W + 2;
+  else if (i >= OW2 && i < OB2) fan = 2 * MLP_W;
+  else if (i >= OW3 && i < OB3) fan = MLP_W + 1;
+  float w = 0.0f;
+  if (fan) {
+    const double u = uniform64(philox10((uint32_t)i, 0u, 0u, 0u, k0, k1).a);
+    w = (float)(sqrt(6.0 / fan) * (2.0 * u - 1.0));
+  }
+  params[i] = w;
+}
+
 }  // namespace
+
+pdd_status run_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed) {
+  hipLaunchKernelGGL(k_mlp_init, dim3((MLP_PARAMS + BLK - 1) / BLK), dim3(BLK), 0, ctx->stream, params,
+                     (uint32_t)seed, (uint32_t)(seed >> 32));
+  return check_hip(ctx, hipGetLastError(), "launch mlp_init");
+}
 
 pdd_status run_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* g) {
   const int grid = (int)std::min<int64_t>(4096, (n + BLK - 1) / BLK);

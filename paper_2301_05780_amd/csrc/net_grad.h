@@ -195,27 +195,44 @@ __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, floa
 // c_j = sum_k W2[j][k] (1 - h1_k^2) W1[k]: the same sum as
 // W1^T [(1 - h1^2) * (W2^T g2)] taken in another order, which keeps only h1
 // live across the loop over j (64 doubles instead of 128).
+// float64 parity form, in chunks of NG_J output units j so that few values
+// are live: for each chunk, one pass over the hidden units k (h1_k =
+// tanh(W1_k x + b1_k) recomputed per chunk) accumulates
+//   z_j = b2_j + sum_k W2_jk h1_k   and   c_j = sum_k W2_jk (1 - h1_k^2) W1_k,
+// then grad v += (1 - tanh(z_j)^2) w3_j c_j in j order.
+constexpr int NG_J = 8;
 __device__ __forceinline__ void net_grad_f64(const float* th, double x, double y, double& gx, double& gy) {
-  double h1[MLP_W];
-#pragma unroll
-  for (int k = 0; k < MLP_W; ++k)
-    h1[k] = tanh((double)th[OW1 + 2 * k] * x + (double)th[OW1 + 2 * k + 1] * y + (double)th[OB1 + k]);
   double ax = 0.0, ay = 0.0;
 #pragma unroll 1
-  for (int j = 0; j < MLP_W; ++j) {
-    double z = (double)th[OB2 + j], cx = 0.0, cy = 0.0;
+  for (int j0 = 0; j0 < MLP_W; j0 += NG_J) {
+    double z[NG_J], cx[NG_J], cy[NG_J];
 #pragma unroll
-    for (int k = 0; k < MLP_W; ++k) {
-      const double w = (double)th[OW2 + j * MLP_W + k];
-      z += w * h1[k];
-      const double s = w * (1.0 - h1[k] * h1[k]);
-      cx += s * (double)th[OW1 + 2 * k];
-      cy += s * (double)th[OW1 + 2 * k + 1];
+    for (int jj = 0; jj < NG_J; ++jj) {
+      z[jj] = (double)th[OB2 + j0 + jj];
+      cx[jj] = 0.0;
+      cy[jj] = 0.0;
     }
-    const double h2 = tanh(z);
-    const double g2 = (1.0 - h2 * h2) * (double)th[OW3 + j];
-    ax += g2 * cx;
-    ay += g2 * cy;
+#pragma unroll 1
+    for (int k = 0; k < MLP_W; ++k) {
+      const double w1x = (double)th[OW1 + 2 * k], w1y = (double)th[OW1 + 2 * k + 1];
+      const double h = tanh(w1x * x + w1y * y + (double)th[OB1 + k]);
+      const double sk = 1.0 - h * h;
+#pragma unroll
+      for (int jj = 0; jj < NG_J; ++jj) {
+        const double w = (double)th[OW2 + (j0 + jj) * MLP_W + k];
+        z[jj] += w * h;
+        const double t = w * sk;
+        cx[jj] += t * w1x;
+        cy[jj] += t * w1y;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < NG_J; ++jj) {
+      const double h2 = tanh(z[jj]);
+      const double g2 = (1.0 - h2 * h2) * (double)th[OW3 + j0 + jj];
+      ax += g2 * cx[jj];
+      ay += g2 * cy[jj];
+    }
   }
   gx = ax;
   gy = ay;

@@ -99,6 +99,7 @@ def lib():
             "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_set_refill": [vp, i32],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
+            "pdd_mlp_init": [vp, vp, C.c_uint64],
             "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
             "pdd_assemble_batch": [vp, i32, vp],
             "pdd_graph_begin": [vp],
@@ -286,6 +287,12 @@ class Context:
         return ms.value, rep.value.decode()
 
     # ---- control-variate network ---------------------------------------------
+    def mlp_init(self, seed=0):
+        """Initial network parameters on the device (zero biases, Glorot-uniform weights)."""
+        params = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.device)
+        self.check(lib().pdd_mlp_init(self.h, _ptr(params), int(seed) & ((1 << 64) - 1)))
+        return params
+
     def mlp_eval(self, params, xy):
         n = xy.shape[0]
         v = self.torch.empty(n, dtype=self.torch.float32, device=self.device)

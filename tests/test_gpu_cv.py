@@ -33,6 +33,32 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a).astype(dtype)).to("cuda")
 
 
+def test_mlp_init_follows_the_counter_stream(ctx):
+    """Zero biases; weight i = lim (2u - 1), u from the first Philox word at
+    counter (i, 0, 0, 0): recomputed with the oracle's own generator."""
+    from oracle.philox import philox4x32_10
+    seed = (7 << 32) + 11
+    th = ctx.mlp_init(seed).cpu().numpy().astype(np.float64)
+    ctx.sync()
+    w = workloads.MLP_WIDTH
+    r0 = philox4x32_10(np.arange(workloads.MLP_PARAMS), 0, 0, 0, seed & 0xFFFFFFFF, seed >> 32)[0]
+    u = (r0.astype(np.float64) + 0.5) * 2.0 ** -32
+    fan = np.zeros(workloads.MLP_PARAMS)
+    fan[0:2 * w] = w + 2                                   # W1
+    fan[3 * w:3 * w + w * w] = 2 * w                       # W2
+    fan[4 * w + w * w:5 * w + w * w] = w + 1               # w3
+    ref = np.where(fan > 0, np.sqrt(6.0 / np.maximum(fan, 1)) * (2.0 * u - 1.0), 0.0).astype(np.float32)
+    assert np.allclose(th, ref, rtol=2.0 ** -22, atol=0.0)
+    assert np.all(th[fan == 0] == 0.0)
+    # the uniform law of each weight block: variance lim^2 / 3
+    W2 = th[3 * w:3 * w + w * w]
+    lim2 = 6.0 / (2 * w)
+    assert abs(W2.var() / (lim2 / 3.0) - 1.0) < 0.1
+    assert np.abs(W2).max() < np.sqrt(lim2)
+    other = ctx.mlp_init(seed + 1).cpu().numpy()
+    assert not np.array_equal(other, th.astype(np.float32))
+
+
 def test_network_eval_and_input_gradient(ctx):
     th = _theta(1)
     rng = np.random.default_rng(2)
