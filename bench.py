@@ -198,15 +198,23 @@ def cv_comparison(ctx, w, n_plain, sweep_n, seeds=16, epochs=4):
 
 
 # ---- runs ---------------------------------------------------------------------
-def time_single(ctx, w, steps, warmup, lut=None, tune=False):
-    import torch
-    out = ctx.assemble(w, lut=lut)                 # allocates outputs, builds caches
+def tuned_single(ctx, w, lut=None, tune=True):
+    """Assemble once (allocating the outputs and the context's caches), then,
+    with `tune`, let the autotuner pick the launch shape, which stays set on
+    the context for the timed launches.  Returns (outputs, tuning record)."""
+    out = ctx.assemble(w, lut=lut)
     ctx.sync()
     tuned = None
     if tune:
         arr, _ = ctx.batch_arrays([w], outs=[out], lut=lut)
         ms, report = ctx.autotune(arr, reps=2)
         tuned = {"best_kernel_ms": ms, "shape": ctx.last_launch()}
+    return out, tuned
+
+
+def time_single(ctx, w, steps, warmup, lut=None, tune=False):
+    import torch
+    out, tuned = tuned_single(ctx, w, lut=lut, tune=tune)
     for _ in range(warmup):
         ctx.assemble(w, out=out, lut=lut)
     ctx.sync()
@@ -225,6 +233,18 @@ def time_single(ctx, w, steps, warmup, lut=None, tune=False):
                 n=int(out["n"]), nnz=int(out["nnz"]), tuned=tuned)
 
 
+def tuned_batched(ctx, ws):
+    """One launch of the instances `ws` (allocating outputs and caches), then
+    the autotuner (block size, grid, ticket size, schedule, refill), whose
+    shape stays set on the context.  Returns (instance array, outputs, best
+    kernel ms)."""
+    arr, outs = ctx.batch_arrays(ws)
+    ctx.assemble_batch(ws, arr=arr)
+    ctx.sync()
+    tuned_ms, _ = ctx.autotune(arr, reps=1)
+    return arr, outs, tuned_ms
+
+
 def time_batched(steps, warmup):
     """64 instances in one launch: eager launches for the kernel time, then a
     captured graph replayed `steps` times for the throughput."""
@@ -234,10 +254,7 @@ def time_batched(steps, warmup):
     with torch.cuda.stream(stream):
         ctx = pdd.Context(0, stream=stream)
         ws = workloads.batched()
-        arr, outs = ctx.batch_arrays(ws)
-        ctx.assemble_batch(ws, arr=arr)
-        ctx.sync()
-        tuned_ms, _ = ctx.autotune(arr, reps=1)        # block size, grid, ticket size, schedule
+        arr, outs, tuned_ms = tuned_batched(ctx, ws)
         for _ in range(warmup):
             ctx.assemble_batch(ws, arr=arr)
         ctx.set_timing(True)

@@ -1,0 +1,116 @@
+"""The benchmark's workloads at full size, in the launch configuration the
+benchmark times: the autotuned shape (block, grid, ticket size, schedule,
+deferred refill) set by the same helpers `bench.py` uses, and for the
+64-instance batch the replay of the captured HIP graph.  Sampled rows are
+checked against the oracle, which computes them one knot at a time, within 3
+Monte Carlo standard errors; patterns are exact and the row sums obey the
+c <= 0 bound 0 <= sum_j G_kj <= 1."""
+import numpy as np
+import pytest
+
+import bench
+from paper_2301_05780_amd import pdd, workloads
+from oracle.geometry import Geometry
+from oracle.coeffs import Coefficients
+from oracle.assemble import assemble as oracle_assemble
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+def _host(out):
+    nnz = out["nnz"]
+    return dict(row_ptr=out["row_ptr"].cpu().numpy(), col_idx=out["col_idx"].cpu().numpy()[:nnz],
+                val=out["val"].cpu().numpy()[:nnz], b=out["b"].cpu().numpy(),
+                diag=out["diag"].cpu().numpy().reshape(out["n"], pdd.DIAG_WIDTH))
+
+
+def _check_rows(w, got, coeffs, knots):
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    assert np.array_equal(got["row_ptr"], g.row_ptr) and np.array_equal(got["col_idx"], g.col_idx)
+    assert np.all(np.isfinite(got["val"])) and np.all(np.isfinite(got["b"]))
+    rs = np.add.reduceat(got["val"], g.row_ptr[:-1])
+    assert np.all(rs > -1e-9) and np.all(rs < 1 + 1e-9)
+    assert np.all(got["diag"][:, 1] == w["n_paths"])
+    ref = oracle_assemble(g, coeffs, w["n_paths"], w["h"], w["seed"], instance=w.get("instance", 0),
+                          exit_rule=w["exit_rule"], knots=np.asarray(knots))["rows"]
+    for k in knots:
+        r = ref[k]
+        a, e = g.row_ptr[k], g.row_ptr[k + 1]
+        assert np.all(np.abs(got["val"][a:e] - r["val"]) <= 3 * r["se_val"] + 1e-6), k
+        assert abs(got["b"][k] - r["b"]) <= 3 * r["se_b"] + 1e-5, k
+        # the same random stream: the step totals agree closely
+        assert abs(got["diag"][k, 0] / r["diag"][0] - 1.0) < 2e-3, k
+
+
+def test_varcoef_in_the_timed_configuration(ctx):
+    w = workloads.varcoef()
+    out, tuned = bench.tuned_single(ctx, w, tune=True)
+    try:
+        ctx.assemble(w, out=out)
+        ctx.sync()
+        assert ctx.last_launch() == tuned["shape"]
+        got = _host(out)
+        n = got["row_ptr"].size - 1
+        rng = np.random.default_rng(3)
+        knots = np.concatenate([[0, n - 1], rng.choice(n, 2, replace=False)])
+        _check_rows(w, got, Coefficients("varcoef", ()), knots)
+    finally:
+        ctx.set_launch(0, 0, 0)
+        ctx.set_refill(1)
+
+
+def test_large_lut_in_the_timed_configuration(ctx):
+    w = workloads.large_lut()
+    tab = workloads.poisson_lut(w["lut_n"])
+    lut = torch.from_numpy(tab).cuda()
+    out, tuned = bench.tuned_single(ctx, w, lut=lut, tune=True)
+    try:
+        ctx.assemble(w, out=out, lut=lut)
+        ctx.sync()
+        assert ctx.last_launch() == tuned["shape"]
+        got = _host(out)
+        n = got["row_ptr"].size - 1
+        assert n == 62465
+        rng = np.random.default_rng(4)
+        knots = np.concatenate([[n // 2], rng.choice(n, 2, replace=False)])
+        _check_rows(w, got, Coefficients("lut", lut=tab, lut_n=w["lut_n"]), knots)
+    finally:
+        ctx.set_launch(0, 0, 0)
+        ctx.set_refill(1)
+
+
+def test_batched_graph_replay_in_the_timed_configuration():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gctx = pdd.Context(0, stream=stream)
+        ws = workloads.batched()
+        arr, outs, tuned_ms = bench.tuned_batched(gctx, ws)
+        assert tuned_ms > 0
+        gctx.graph_begin()
+        gctx.assemble_batch(ws, arr=arr)
+        gctx.graph_end()
+        for o in outs:
+            o["b"].fill_(np.nan)
+        gctx.graph_launch()
+        gctx.sync()
+        rng = np.random.default_rng(5)
+        for i in (3, 29, 60):
+            w = ws[i]
+            got = _host(outs[i])
+            n = got["row_ptr"].size - 1
+            _check_rows(w, got, Coefficients("amplitude", w["param"]), rng.choice(n, 2, replace=False))
+        for o in outs:
+            assert np.all(np.isfinite(o["b"].cpu().numpy()))
+        gctx.close()
