@@ -87,14 +87,12 @@ def committed_traffic(workload):
 _ORACLE_INPUTS = {}
 
 
-def _oracle_sample(args):
-    """Worker: run the oracle on one knot and return its path-step count."""
-    w, k = args
+def _oracle_inputs(w):
+    """Geometry and coefficients of the oracle, built once per process."""
     from oracle.geometry import Geometry
     from oracle.coeffs import Coefficients
-    from oracle.assemble import integrate_knot, exit_points, knot_row
     key = w["name"]
-    if key not in _ORACLE_INPUTS:            # geometry and coefficients, once per worker
+    if key not in _ORACLE_INPUTS:
         g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
         if w["kind"] == "lut":
             from paper_2301_05780_amd import workloads
@@ -102,32 +100,58 @@ def _oracle_sample(args):
         else:
             c = Coefficients(w["kind"], w.get("param", ()))
         _ORACLE_INPUTS[key] = (g, c)
-    g, c = _ORACLE_INPUTS[key]
+    return _ORACLE_INPUTS[key]
+
+
+def _oracle_sample(args):
+    """Worker: run the oracle on one knot and return its path-step count."""
+    w, k = args
+    from oracle.assemble import integrate_knot, exit_points, knot_row
+    g, c = _oracle_inputs(w)
     rec = integrate_knot(g, c, k, w["n_paths"], w["h"], w["seed"], w.get("instance", 0), w["exit_rule"])
     ex = exit_points(g, c, k, rec)
     knot_row(g, c, k, rec, ex)
     return int(rec["K"].sum())
 
 
-def cpu_baseline(w, n_knots, workers):
+def cpu_baseline(w, workers, target_s=15.0):
+    """The oracle's throughput on `workers` host processes over a bounded
+    sample of the workload's knots (evenly spaced, all paths of each).  Set-up
+    (process start, geometry and tables), a warm-up round of one knot per worker
+    and a pilot round of two are outside the timed region; the pilot sizes the timed
+    sample to about `target_s` seconds of wall time."""
     import multiprocessing as mp
     import numpy as np
     from paper_2301_05780_amd import pdd
     n = pdd.pattern(w)[0]
-    knots = np.linspace(0, n - 1, n_knots).round().astype(int).tolist()
-    if workers == 1:
-        _oracle_sample((w, knots[0]))          # set-up (geometry, tables) outside the timed sample
-        knots = knots[1:]
-    t0 = time.perf_counter()
+
+    def spread(count, shift):
+        return ((np.arange(count) + shift) * n / count).astype(int).clip(0, n - 1).tolist()
+
+    pool = None
     if workers > 1:
-        with mp.get_context("spawn").Pool(workers) as pool:
-            steps = pool.map(_oracle_sample, [(w, k) for k in knots])
+        pool = mp.get_context("spawn").Pool(workers, initializer=_oracle_inputs, initargs=(w,))
+        run = lambda ks: pool.map(_oracle_sample, [(w, k) for k in ks], chunksize=1)   # noqa: E731
     else:
-        steps = [_oracle_sample((w, k)) for k in knots]
-    dt = time.perf_counter() - t0
+        _oracle_inputs(w)
+        run = lambda ks: [_oracle_sample((w, k)) for k in ks]                            # noqa: E731
+    try:
+        run(spread(workers, 0.25))                     # warm-up: imports, first-call costs
+        t0 = time.perf_counter()
+        run(spread(2 * workers, 0.75))                 # pilot, two knots per worker, sizes the sample
+        t_knot = max(time.perf_counter() - t0, 1e-3) / (2 * workers)
+        count = int(min(n, workers * max(1, round(target_s / (t_knot * workers)))))
+        knots = spread(count, 0.0)
+        t0 = time.perf_counter()
+        steps = run(knots)
+        dt = time.perf_counter() - t0
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
     return dict(value=sum(steps) / dt, unit="path-steps/s", cores=workers, kind="oracle",
-                sample=f"{n_knots} of {n} knots (evenly spaced), all {w['n_paths']} paths each, "
-                       f"{sum(steps)} path-steps in {dt:.1f} s")
+                sample=f"{count} of {n} knots (evenly spaced), all {w['n_paths']} paths each, "
+                       f"{sum(steps)} path-steps in {dt:.1f} s wall on {workers} processes")
 
 
 # ---- control-variate comparison (RMSE x time) ------------------------------
@@ -305,7 +329,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="varcoef", choices=["varcoef", "poisson_small", "large_lut", "batched"])
     ap.add_argument("--exit-rule", default="gm", choices=["gm", "naive"])
-    ap.add_argument("--cpu-knots", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="wall time of the timed oracle sample on the host")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv-compare", action="store_true")
@@ -399,7 +424,7 @@ def main():
         cw = dict(w)
         if args.workload == "batched":
             cw = workloads.batched()[0]
-        rec["cpu_baseline"] = cpu_baseline(cw, args.cpu_knots if w["kind"] != "lut" else 8, workers)
+        rec["cpu_baseline"] = cpu_baseline(cw, workers, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 
 
