@@ -301,10 +301,11 @@ def time_batched(steps, warmup):
         ps = sum(float(o["diag"].view(-1, 8)[:, 0].sum().item()) for o in outs)
         paths = sum(float(o["diag"].view(-1, 8)[:, 1].sum().item()) for o in outs)
         grid, block, tickets = ctx.last_launch()
+        refill = ctx.refill()
         ctx.close()
     return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3, path_steps=ps, paths=paths,
                 n=sum(int(o["n"]) for o in outs), nnz=sum(int(o["nnz"]) for o in outs),
-                launch={"grid": grid, "block": block, "tickets": tickets, "graph_nodes": nodes,
+                launch={"grid": grid, "block": block, "tickets": tickets, "refill": refill, "graph_nodes": nodes,
                 "autotuned_kernel_ms": tuned_ms})
 
 
@@ -370,7 +371,8 @@ def main():
         ctx = pdd.Context(0)
         r = time_single(ctx, w, args.steps, args.warmup, lut=lut, tune=args.autotune)
         grid, block, tickets = ctx.last_launch()
-        launch = {"grid": grid, "block": block, "tickets": tickets, "autotuned": args.autotune}
+        launch = {"grid": grid, "block": block, "tickets": tickets, "refill": ctx.refill(),
+                  "autotuned": args.autotune}
         ctx.set_launch(0, 0, 0)                   # later runs (control-variate comparison) size themselves
         desc = (f"{w['name']}: {w['kind']} coefficients, {w['H']}x{w['H']} subdomains, knot spacing "
                 f"1/{w['H'] * w['m']}, N={w['n_paths']}, h={w['h']}, {w['exit_rule']} exits")

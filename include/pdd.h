@@ -345,6 +345,9 @@ pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t pat
  * summation order.  pdd_autotune also tries 8, 16 and 32 on its best shape
  * and leaves the winner set. */
 pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle);
+/* The context's current refill threshold (as set by pdd_set_refill or chosen
+ * by pdd_autotune). */
+pdd_status pdd_get_refill(const pdd_ctx* ctx, int32_t* min_idle);
 /* Shape of the last assembly launch: grid, block and number of tickets. */
 pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets);
 /* enable != 0: bracket every assembly kernel launched from now on with a pair

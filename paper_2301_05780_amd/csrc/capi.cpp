@@ -358,6 +358,12 @@ pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle) {
   return PDD_OK;
 }
 
+pdd_status pdd_get_refill(const pdd_ctx* ctx, int32_t* min_idle) {
+  if (!ctx || !min_idle) return PDD_EINVAL;
+  *min_idle = ctx->refill_min;
+  return PDD_OK;
+}
+
 pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets) {
   if (!ctx || !grid || !block || !tickets) return fail(nullptr, PDD_EINVAL, "pdd_last_launch: null argument");
   *grid = ctx->last_grid;

@@ -98,6 +98,7 @@ def lib():
                              C.POINTER(Run), vp, vp, vp, vp, vp],
             "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_set_refill": [vp, i32],
+            "pdd_get_refill": [vp, C.POINTER(i32)],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_init": [vp, vp, C.c_uint64],
             "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
@@ -207,6 +208,11 @@ class Context:
 
     def set_refill(self, min_idle=1):
         self.check(lib().pdd_set_refill(self.h, int(min_idle)))
+
+    def refill(self):
+        r = C.c_int32()
+        self.check(lib().pdd_get_refill(self.h, C.byref(r)))
+        return r.value
 
     def last_launch(self):
         g, b, t = C.c_int32(), C.c_int32(), C.c_int64()

@@ -152,6 +152,7 @@ def test_deferred_refill_matches_the_oracle(ctx, refill):
              seed=21, precision="fp64", exit_rule="gm", instance=4)
     g, ref = _oracle(w)
     ctx.set_refill(refill)
+    assert ctx.refill() == refill
     try:
         got = fetch(ctx.assemble(w), g)
         ctx.sync()
