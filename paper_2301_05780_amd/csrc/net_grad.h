@@ -34,13 +34,17 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 //   W2b:  W2 [out][in].
 //   W2Tb: W2^T [in][out] scaled by w3[out] (folds the output weight into the
 //         backward product).
+//   Both matrices are stored with a row stride of NW = 72 elements (144 B):
+//   the 32 lanes of a fragment read read 32 different rows at one column, and
+//   a 128-byte stride would put every row on the same LDS banks.
 //   Afin: the final contraction grad v = W1^T d as an MFMA: rows 0..3 are
 //         W1x_hi, W1y_hi, W1x_lo, W1y_lo, stored per (chunk, row, half) in the
 //         contraction order of the chunk.
+constexpr int NW = MLP_W + 8;
 struct NetLds {
   __bf16 W1x[MLP_W * 8];
-  __bf16 W2b[MLP_W * MLP_W];
-  __bf16 W2Tb[MLP_W * MLP_W];
+  __bf16 W2b[MLP_W * NW];
+  __bf16 W2Tb[MLP_W * NW];
   __bf16 Afin[4 * 4 * 2 * 8];
   float b2[MLP_W];
 };
@@ -66,8 +70,8 @@ __device__ __forceinline__ void net_stage(NetLds* N, const float* __restrict__ t
   for (int i = threadIdx.x; i < MLP_W * MLP_W; i += blockDim.x) {
     const int o = i / MLP_W, k = i % MLP_W;
     const float w = th[OW2 + i];
-    N->W2b[i] = (__bf16)w;
-    N->W2Tb[k * MLP_W + o] = (__bf16)(w * th[OW3 + o]);
+    N->W2b[o * NW + k] = (__bf16)w;
+    N->W2Tb[k * NW + o] = (__bf16)(w * th[OW3 + o]);
   }
   for (int k = threadIdx.x; k < MLP_W; k += blockDim.x) {
     __bf16 xh, xl, yh, yl, bh, bl;
@@ -137,7 +141,7 @@ __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, floa
     bf16x8 G2[2][2];
 #pragma unroll
     for (int ob = 0; ob < 2; ++ob) {
-      const __bf16* wrow = N->W2b + (32 * ob + c) * MLP_W;
+      const __bf16* wrow = N->W2b + (32 * ob + c) * NW;
       f32x16 acc;
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = N->b2[32 * ob + 8 * (r >> 2) + 4 * g + (r & 3)];
@@ -158,7 +162,7 @@ __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, floa
     f32x16 fin = f32x16{};
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
-      const __bf16* wrow = N->W2Tb + (32 * kb + c) * MLP_W;
+      const __bf16* wrow = N->W2Tb + (32 * kb + c) * NW;
       f32x16 acc = f32x16{};
 #pragma unroll
       for (int ob = 0; ob < 2; ++ob)
@@ -190,12 +194,8 @@ __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, floa
   gy = g ? ty : res_y[0];
 }
 
-// float64 grad v of one point from float32 parameters (staged in LDS).
-// grad v = sum_j g2_j c_j with g2_j = (1 - h2_j^2) w3_j and
-// c_j = sum_k W2[j][k] (1 - h1_k^2) W1[k]: the same sum as
-// W1^T [(1 - h1^2) * (W2^T g2)] taken in another order, which keeps only h1
-// live across the loop over j (64 doubles instead of 128).
-// float64 parity form, in chunks of NG_J output units j so that few values
+// float64 grad v of one point from float32 parameters (staged in LDS), the
+// parity form, in chunks of NG_J output units j so that few values
 // are live: for each chunk, one pass over the hidden units k (h1_k =
 // tanh(W1_k x + b1_k) recomputed per chunk) accumulates
 //   z_j = b2_j + sum_k W2_jk h1_k   and   c_j = sum_k W2_jk (1 - h1_k^2) W1_k,
