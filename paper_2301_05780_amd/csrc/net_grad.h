@@ -32,8 +32,10 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 //        point column (x_hi, x_lo, x_hi, y_hi, y_lo, y_hi, 1, 1): the hi/lo
 //        bf16 splits recover W1 x + b1 to about 2^-16 relative.
 //   W2b:  W2 [out][in].
-//   W2Tb: W2^T [in][out] scaled by w3[out] (folds the output weight into the
-//         backward product).
+//   W2Tb: W2^T [in][out] scaled by 4 w3[out] (folds the output weight and the
+//         factor 4 of 1 - tanh^2 = 4 r (1 - r) into the backward product).
+//   W1x, W2b and b2 carry the factor S = 2 log2(e), so that the accumulators
+//   hold S z and tanh z = 1 - 2 r with r = 1 / (2^(S z) + 1).
 //   Both matrices are stored with a row stride of NW = 72 elements (144 B):
 //   the 32 lanes of a fragment read read 32 different rows at one column, and
 //   a 128-byte stride would put every row on the same LDS banks.
@@ -41,6 +43,7 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 //         W1x_hi, W1y_hi, W1x_lo, W1y_lo, stored per (chunk, row, half) in the
 //         contraction order of the chunk.
 constexpr int NW = MLP_W + 8;
+constexpr float NET_S = 2.8853900817779268f;   // 2 log2(e)
 struct NetLds {
   __bf16 W1x[MLP_W * 8];
   __bf16 W2b[MLP_W * NW];
@@ -49,9 +52,10 @@ struct NetLds {
   float b2[MLP_W];
 };
 
-__device__ __forceinline__ float tanh_fast(float z) {
-  const float e = __builtin_amdgcn_exp2f(z * 2.8853900817779268f);   // exp(2z)
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+// r = 1 / (2^u + 1) for an accumulator holding u = S z: tanh z = 1 - 2 r and
+// 1 - tanh^2 z = 4 r (1 - r); exact limits at +-infinity
+__device__ __forceinline__ float net_r(float u) {
+  return __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(u) + 1.0f);
 }
 
 __device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
@@ -70,17 +74,17 @@ __device__ __forceinline__ void net_stage(NetLds* N, const float* __restrict__ t
   for (int i = threadIdx.x; i < MLP_W * MLP_W; i += blockDim.x) {
     const int o = i / MLP_W, k = i % MLP_W;
     const float w = th[OW2 + i];
-    N->W2b[o * NW + k] = (__bf16)w;
-    N->W2Tb[k * NW + o] = (__bf16)(w * th[OW3 + o]);
+    N->W2b[o * NW + k] = (__bf16)(NET_S * w);
+    N->W2Tb[k * NW + o] = (__bf16)(4.0f * w * th[OW3 + o]);
   }
   for (int k = threadIdx.x; k < MLP_W; k += blockDim.x) {
     __bf16 xh, xl, yh, yl, bh, bl;
-    split_bf16(th[OW1 + 2 * k], xh, xl);
-    split_bf16(th[OW1 + 2 * k + 1], yh, yl);
-    split_bf16(th[OB1 + k], bh, bl);
+    split_bf16(NET_S * th[OW1 + 2 * k], xh, xl);
+    split_bf16(NET_S * th[OW1 + 2 * k + 1], yh, yl);
+    split_bf16(NET_S * th[OB1 + k], bh, bl);
     __bf16* r = N->W1x + 8 * k;
     r[0] = xh; r[1] = xh; r[2] = xl; r[3] = yh; r[4] = yh; r[5] = yl; r[6] = bh; r[7] = bl;
-    N->b2[k] = th[OB2 + k];
+    N->b2[k] = NET_S * th[OB2 + k];
   }
   for (int e = threadIdx.x; e < 4 * 4 * 2 * 8; e += blockDim.x) {
     const int i = e & 7, g = (e >> 3) & 1, m = (e >> 4) & 3, ch = e >> 6;
@@ -127,61 +131,87 @@ __device__ __forceinline__ void net_grad_mfma(const NetLds* __restrict__ N, floa
       B1 = bf16x8{xh, xl, xh, yh, yl, yh, one, one};
     }
     bf16x8 Bf[2][2];
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
-      const bf16x8 A1 = (g == 0) ? *reinterpret_cast<const bf16x8*>(N->W1x + 8 * (32 * kb + c)) : zero8;
-      const f32x16 z1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1, f32x16{}, 0, 0, 0);
+    {
+      const bf16x8 A10 = (g == 0) ? *reinterpret_cast<const bf16x8*>(N->W1x + 8 * c) : zero8;
+      const bf16x8 A11 = (g == 0) ? *reinterpret_cast<const bf16x8*>(N->W1x + 8 * (32 + c)) : zero8;
+      const f32x16 z10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A10, B1, f32x16{}, 0, 0, 0);
+      const f32x16 z11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A11, B1, f32x16{}, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        Bf[kb][r >> 3][r & 7] = (__bf16)tanh_fast(z1[r]);
+        Bf[0][r >> 3][r & 7] = (__bf16)__builtin_fmaf(-2.0f, net_r(z10[r]), 1.0f);
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        Bf[1][r >> 3][r & 7] = (__bf16)__builtin_fmaf(-2.0f, net_r(z11[r]), 1.0f);
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     }
-    // layer 2: z2^T tile (ob) = b2 + W2[out rows][chunk] h1^T[chunk][points]
+    // layer 2: z2^T tile (ob) = b2 + W2[out rows][chunk] h1^T[chunk][points]; the two
+    // output tiles' MFMA chains are interleaved, then G2/4 = r (1 - r)
     bf16x8 G2[2][2];
+    {
+      const __bf16* w0 = N->W2b + c * NW;
+      const __bf16* w1 = N->W2b + (32 + c) * NW;
+      f32x16 acc0, acc1;
 #pragma unroll
-    for (int ob = 0; ob < 2; ++ob) {
-      const __bf16* wrow = N->W2b + (32 * ob + c) * NW;
-      f32x16 acc;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = N->b2[32 * ob + 8 * (r >> 2) + 4 * g + (r & 3)];
+      for (int r = 0; r < 16; ++r) {
+        acc0[r] = N->b2[8 * (r >> 2) + 4 * g + (r & 3)];
+        acc1[r] = N->b2[32 + 8 * (r >> 2) + 4 * g + (r & 3)];
+      }
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_frag(wrow, 32 * kb + 16 * h + 4 * g), Bf[kb][h], acc, 0, 0,
-                                                        0);
+        for (int h = 0; h < 2; ++h) {
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_frag(w0, 32 * kb + 16 * h + 4 * g), Bf[kb][h], acc0,
+                                                         0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_frag(w1, 32 * kb + 16 * h + 4 * g), Bf[kb][h], acc1,
+                                                         0, 0, 0);
+        }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float h2 = tanh_fast(acc[r]);
-        G2[ob][r >> 3][r & 7] = (__bf16)(1.0f - h2 * h2);
+        const float q = net_r(acc0[r]);
+        G2[0][r >> 3][r & 7] = (__bf16)__builtin_fmaf(-q, q, q);
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float q = net_r(acc1[r]);
+        G2[1][r >> 3][r & 7] = (__bf16)__builtin_fmaf(-q, q, q);
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     }
-    // backward: dh1^T tile (kb) = (W2^T w3)[k1 rows][chunk] g2^T[chunk][points]; d = dh1 (1 - h1^2)
+    // backward: dh1^T tile (kb) = (4 W2^T w3)[k1 rows][chunk] (g2/4)^T[chunk][points], the two
+    // tiles' chains interleaved; d = dh1 (1 - h1^2); then the final contraction
     f32x16 fin = f32x16{};
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
-      const __bf16* wrow = N->W2Tb + (32 * kb + c) * NW;
-      f32x16 acc = f32x16{};
+    {
+      const __bf16* w0 = N->W2Tb + c * NW;
+      const __bf16* w1 = N->W2Tb + (32 + c) * NW;
+      f32x16 acc0 = f32x16{}, acc1 = f32x16{};
 #pragma unroll
       for (int ob = 0; ob < 2; ++ob)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_frag(wrow, 32 * ob + 16 * h + 4 * g), G2[ob][h], acc, 0, 0,
-                                                        0);
-      bf16x8 D[2];
+        for (int h = 0; h < 2; ++h) {
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_frag(w0, 32 * ob + 16 * h + 4 * g), G2[ob][h], acc0,
+                                                         0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_frag(w1, 32 * ob + 16 * h + 4 * g), G2[ob][h], acc1,
+                                                         0, 0, 0);
+        }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float h1 = (float)Bf[kb][r >> 3][r & 7];
-        D[r >> 3][r & 7] = (__bf16)(acc[r] * (1.0f - h1 * h1));
-      }
-      // final contraction: rows 0..3 of W1^T (hi/lo splits) against d
+      for (int kb = 0; kb < 2; ++kb) {
+        bf16x8 D[2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const bf16x8 Af = (c < 4) ? *reinterpret_cast<const bf16x8*>(N->Afin + (((2 * kb + h) * 4 + c) * 2 + g) * 8)
-                                  : zero8;
-        fin = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af, D[h], fin, 0, 0, 0);
+        for (int r = 0; r < 16; ++r) {
+          const float h1 = (float)Bf[kb][r >> 3][r & 7];
+          D[r >> 3][r & 7] = (__bf16)((kb ? acc1[r] : acc0[r]) * (1.0f - h1 * h1));
+        }
+        // final contraction: rows 0..3 of W1^T (hi/lo splits) against d
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bf16x8 Af = (c < 4) ? *reinterpret_cast<const bf16x8*>(N->Afin + (((2 * kb + h) * 4 + c) * 2 + g) * 8)
+                                    : zero8;
+          fin = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af, D[h], fin, 0, 0, 0);
+        }
       }
     }
     // rows 0..3 sit in registers 0..3 of the lanes of half 0
