@@ -170,6 +170,28 @@ const char* pdd_last_error(const pdd_ctx* ctx);
 pdd_status pdd_pattern(const pdd_partition* part, const pdd_knots* knots,
                        int64_t* n, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx);
 
+/* Work decomposition of pdd_assemble (host only; needs no device or
+ * context): the tickets (knot, path range) that a single-instance assembly
+ * hands to its waves, the order in which the waves claim them, and the split
+ * of that order over the eight XCDs.
+ *   n_paths_per_knot: host, one entry >= 1 per knot in canonical order.
+ *   paths_per_ticket >= 1: knot k's paths are cut into
+ *     ceil(N_k / paths_per_ticket) near-equal contiguous ranges.
+ *   spatial != 0: the order used with tabulated coefficients, the tickets
+ *     sorted by the Morton (Z) index of their knot's subdomain; else the
+ *     longest expected work first (patch area x paths, the mean exit time
+ *     growing with the patch area, eq. 26).  Both sorts are stable.
+ *   grid: workgroups of the launch, for the XCD split (workgroup b runs on
+ *     XCD b mod 8; XCD x takes order positions [xcd_begin[x], xcd_begin[x+1])
+ *     with the share of the expected cost that matches its share of
+ *     workgroups).  Only with spatial != 0 and grid >= 8.
+ * Outputs (host, nullable): *n_tickets; tickets[3 n_tickets] = (knot, first
+ * path, end path) by ticket index; order[n_tickets]; xcd_begin[9].  Call
+ * with tickets = order = xcd_begin = NULL to size the arrays. */
+pdd_status pdd_plan_tickets(const pdd_partition* part, const pdd_knots* knots, const int32_t* n_paths_per_knot,
+                            int32_t paths_per_ticket, int32_t spatial, int32_t grid, int64_t* n_tickets,
+                            int32_t* tickets, int32_t* order, int32_t* xcd_begin);
+
 /* Knot coordinates in canonical order: xy = host double[2 n] (x0, y0, x1, y1, ...). */
 pdd_status pdd_knot_xy(const pdd_partition* part, const pdd_knots* knots, double* xy);
 

@@ -13,6 +13,7 @@
 #include "geometry.h"
 #include "kernels.h"
 #include "mlp.h"
+#include "plan.h"
 
 using namespace pdd;
 
@@ -195,6 +196,33 @@ pdd_status pdd_pattern(const pdd_partition* part, const pdd_knots* knots, int64_
   *nnz = g.nnz;
   if (row_ptr) std::copy(g.row_ptr.begin(), g.row_ptr.end(), row_ptr);
   if (col_idx) std::copy(g.col_idx.begin(), g.col_idx.end(), col_idx);
+  return PDD_OK;
+}
+
+pdd_status pdd_plan_tickets(const pdd_partition* part, const pdd_knots* knots, const int32_t* n_paths_per_knot,
+                            int32_t paths_per_ticket, int32_t spatial, int32_t grid, int64_t* n_tickets,
+                            int32_t* tickets, int32_t* order, int32_t* xcd_begin) {
+  if (!part || !knots || !n_paths_per_knot || !n_tickets) return fail(nullptr, PDD_EINVAL, "pdd_plan_tickets: null argument");
+  if (paths_per_ticket < 1) return fail(nullptr, PDD_EINVAL, "pdd_plan_tickets: paths_per_ticket must be >= 1");
+  if (xcd_begin && (!spatial || grid < 8))
+    return fail(nullptr, PDD_EINVAL, "pdd_plan_tickets: the XCD split needs the spatial order and grid >= 8");
+  Geometry g;
+  std::string err;
+  pdd_status st = build_geometry(*part, *knots, g, err, false);
+  if (st != PDD_OK) return fail(nullptr, st, err);
+  std::vector<int32_t> npk(n_paths_per_knot, n_paths_per_knot + g.n);
+  TicketPlan plan;
+  if ((st = plan_tickets(g, npk, paths_per_ticket, spatial != 0, 0u, plan, err)) != PDD_OK) return fail(nullptr, st, err);
+  *n_tickets = (int64_t)plan.tickets.size();
+  if (tickets) {
+    for (size_t i = 0; i < plan.tickets.size(); ++i) {
+      tickets[3 * i] = plan.tickets[i].knot;
+      tickets[3 * i + 1] = plan.tickets[i].p0;
+      tickets[3 * i + 2] = plan.tickets[i].p1;
+    }
+  }
+  if (order) std::copy(plan.order.begin(), plan.order.end(), order);
+  if (xcd_begin) xcd_split(plan.cum_cost, (int64_t)plan.tickets.size(), grid, xcd_begin);
   return PDD_OK;
 }
 

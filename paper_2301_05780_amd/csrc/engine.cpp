@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "context.h"
+#include "plan.h"
 
 namespace pdd {
 
@@ -179,52 +180,13 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     fresh->npk = npk;
     fresh->per_ticket = (int32_t)per_ticket;
     fresh->inst = run.instance;
-    std::vector<Ticket> tk;
-    std::vector<int32_t> tb(g.n + 1, 0);
-    std::vector<double> cost;
-    for (int64_t k = 0; k < g.n; ++k) {
-      const int64_t N = npk[k];
-      const int64_t c = (N + per_ticket - 1) / per_ticket;
-      // expected steps per path scale with the patch area (mean exit time, eq. 26)
-      const double area = (double)(g.box[4 * k + 1] - g.box[4 * k + 0]) * (double)(g.box[4 * k + 3] - g.box[4 * k + 2]);
-      for (int64_t i = 0; i < c; ++i) {
-        Ticket t;
-        t.knot = (int32_t)k;
-        t.p0 = (int32_t)(N * i / c);
-        t.p1 = (int32_t)(N * (i + 1) / c);
-        t.inst = run.instance;
-        tk.push_back(t);
-        cost.push_back(area * (double)(t.p1 - t.p0));
-      }
-      if ((int64_t)tk.size() > INT32_MAX) return bad(ctx, PDD_EUNSUPPORTED, "too many tickets");
-      tb[k + 1] = (int32_t)tk.size();
-    }
-    std::vector<int32_t> order(tk.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-    if (spatial) {
-      // subdomain of each knot in Morton (Z) order, knots and path ranges in order within it
-      auto spread = [](uint32_t v) {
-        v &= 0xFFFFu;
-        v = (v | (v << 8)) & 0x00FF00FFu;
-        v = (v | (v << 4)) & 0x0F0F0F0Fu;
-        v = (v | (v << 2)) & 0x33333333u;
-        v = (v | (v << 1)) & 0x55555555u;
-        return v;
-      };
-      std::vector<uint32_t> key(tk.size());
-      for (size_t i = 0; i < tk.size(); ++i) {
-        const int32_t k = tk[i].knot;
-        const uint32_t sx = (uint32_t)(g.ix[k] / job.knots.m), sy = (uint32_t)(g.iy[k] / job.knots.m);
-        key[i] = spread(sx) | (spread(sy) << 1);
-      }
-      std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
-      fresh->cum_cost.resize(order.size() + 1);
-      fresh->cum_cost[0] = 0.0;
-      for (size_t i = 0; i < order.size(); ++i) fresh->cum_cost[i + 1] = fresh->cum_cost[i] + cost[order[i]];
-    } else {
-      // longest-expected-first order (stable: ties keep knot order)
-      std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
-    }
+    TicketPlan plan;
+    std::string err;
+    if ((st = plan_tickets(g, npk, per_ticket, spatial, run.instance, plan, err)) != PDD_OK) return bad(ctx, st, err.c_str());
+    const std::vector<Ticket>& tk = plan.tickets;
+    const std::vector<int32_t>& tb = plan.begin;
+    const std::vector<int32_t>& order = plan.order;
+    fresh->cum_cost = plan.cum_cost;
     fresh->spatial = spatial;
     fresh->n_tickets = (int64_t)tk.size();
     if ((e = fresh->tickets.reserve(tk.size() * sizeof(Ticket))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(tickets)");
@@ -249,20 +211,11 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   // of the order with the same fraction of the expected cost; its waves take
   // the share in a fixed stride (static) or from the XCD's own counter
   // (dynamic)
-  const bool xcd_split = tc->spatial && grid >= 8;
-  if (xcd_split && tc->xcd_grid != (int32_t)grid) {
+  const bool split_xcd = tc->spatial && grid >= 8;
+  if (split_xcd && tc->xcd_grid != (int32_t)grid) {
     if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: XCD split not cached for this grid; run once before capturing");
     int32_t xb[9];
-    xb[0] = 0;
-    const double total_cost = tc->cum_cost.back();
-    int64_t blocks_before = 0;
-    for (int x = 0; x < 8; ++x) {
-      blocks_before += (grid - x + 7) / 8;
-      const double target = total_cost * (double)blocks_before / (double)grid;
-      const auto it = std::lower_bound(tc->cum_cost.begin(), tc->cum_cost.end(), target);
-      xb[x + 1] = (x == 7) ? (int32_t)tc->n_tickets
-                           : std::max(xb[x], (int32_t)std::min<int64_t>(it - tc->cum_cost.begin(), tc->n_tickets));
-    }
+    xcd_split(tc->cum_cost, tc->n_tickets, grid, xb);
     if ((e = tc->xcd_begin.reserve(sizeof(xb))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(xcd split)");
     if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
     if ((e = hipMemcpy(tc->xcd_begin.ptr, xb, sizeof(xb), hipMemcpyHostToDevice)) != hipSuccess)
@@ -288,7 +241,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.tickets = tc->tickets.as<Ticket>();
   P.order = tc->order.as<int32_t>();
   P.n_tickets = (int32_t)tc->n_tickets;
-  P.xcd_begin = xcd_split ? tc->xcd_begin.as<int32_t>() : nullptr;
+  P.xcd_begin = split_xcd ? tc->xcd_begin.as<int32_t>() : nullptr;
   P.refill_min = ctx->refill_min;
   P.row_len = row_len;
   P.slot_len = slot_len;

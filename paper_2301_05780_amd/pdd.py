@@ -98,6 +98,8 @@ def lib():
                              C.POINTER(Run), vp, vp, vp, vp, vp],
             "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_set_refill": [vp, i32],
+            "pdd_plan_tickets": [C.POINTER(Partition), C.POINTER(Knots), vp, i32, i32, i32, C.POINTER(i64), vp, vp,
+                                 vp],
             "pdd_get_refill": [vp, C.POINTER(i32)],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_init": [vp, vp, C.c_uint64],
@@ -160,6 +162,26 @@ def pattern(w):
     _check(lib().pdd_pattern(C.byref(part), C.byref(kn), C.byref(n), C.byref(nnz),
                              rp.ctypes.data, ci.ctypes.data))
     return n.value, nnz.value, rp, ci[:nnz.value]
+
+
+def plan_tickets(w, paths_per_ticket, spatial=False, grid=0):
+    """The work decomposition of a single-instance assembly of w (host only):
+    (tickets int32[T, 3] = knot, first path, end path; claim order int32[T];
+    XCD split int32[9] of the order, or None unless spatial and grid >= 8)."""
+    part, kn = partition_of(w), knots_of(w)
+    n = pattern(w)[0]
+    npk = w.get("n_paths_per_knot")
+    npk = np.full(n, int(w["n_paths"]), dtype=np.int32) if npk is None else np.ascontiguousarray(npk, dtype=np.int32)
+    T = C.c_int64()
+    args = (C.byref(part), C.byref(kn), npk.ctypes.data, int(paths_per_ticket), 1 if spatial else 0, int(grid),
+            C.byref(T))
+    _check(lib().pdd_plan_tickets(*args, None, None, None))
+    tickets = np.empty((max(T.value, 1), 3), dtype=np.int32)
+    order = np.empty(max(T.value, 1), dtype=np.int32)
+    xb = np.empty(9, dtype=np.int32) if (spatial and grid >= 8) else None
+    _check(lib().pdd_plan_tickets(*args, tickets.ctypes.data, order.ctypes.data,
+                                  None if xb is None else xb.ctypes.data))
+    return tickets[:T.value], order[:T.value], xb
 
 
 def knot_xy(w):
