@@ -426,10 +426,13 @@ __device__ __forceinline__ uint32_t lut_gm_refine(const CoefParams& cp, R sqrt_h
                                                   uint32_t cand) {
   const R xE = (R)line[0], yN = (R)line[1], xW = (R)line[2], yS = (R)line[3];
   uint32_t fl = 0;
-#pragma unroll
-  for (int o = 0; o < 4; ++o) {
-    if (!((cand >> o) & 1u)) continue;
-    const bool vert = (o == 0 || o == 2);
+  // one candidate side per pass (lowest first): a wave makes as many passes
+  // as its lanes have candidates at most, almost always one
+  uint32_t rest = cand;
+  while (rest != 0u) {
+    const int o = __builtin_ctz(rest);
+    rest &= rest - 1u;
+    const bool vert = (o & 1) == 0;                 // E (0) and W (2)
     const R lpos = (o == 0) ? xE : (o == 1) ? yN : (o == 2) ? xW : yS;
     const R px = vert ? lpos : fmin(fmax(x, xW), xE);
     const R py = vert ? fmin(fmax(y, yS), yN) : lpos;
