@@ -35,14 +35,27 @@ namespace {
 constexpr int QCAP = 128;          // exit records per wave (processed at >= 64)
 constexpr uint32_t MAX_STEPS = (1u << 24) - 2;
 
+// Per-buffer row header: the ticket's knot, the instance parameters (batched
+// launches only), the strict exit thresholds x > e[0], y > e[1], x < e[2],
+// y < e[3] in the path precision, and the ticket.
+template <typename R, bool BATCH>
 struct WaveBuf {
   KnotDesc d;
-  InstDesc I;          // instance parameters (batched launches)
-  double ebox[4];      // strict exit thresholds: x > e[0], y > e[1], x < e[2], y < e[3]
+  R ebox[4];
   int32_t ticket, p0, p1;
   uint32_t inst;
 };
-static_assert(sizeof(WaveBuf) % 16 == 0, "WaveBuf alignment");
+template <typename R>
+struct WaveBuf<R, true> {
+  KnotDesc d;
+  InstDesc I;
+  R ebox[4];
+  int32_t ticket, p0, p1;
+  uint32_t inst;
+};
+static_assert(sizeof(WaveBuf<float, false>) % 16 == 0 && sizeof(WaveBuf<double, false>) % 16 == 0 &&
+                  sizeof(WaveBuf<float, true>) % 16 == 0 && sizeof(WaveBuf<double, true>) % 16 == 0,
+              "WaveBuf alignment");
 
 template <typename R>
 struct ExitRec {
@@ -68,9 +81,9 @@ static_assert(sizeof(CoopLds) % 16 == 0, "CoopLds alignment");
 
 // per-wave LDS bytes: two row headers, the exit queue (records + meta words),
 // two tally rows, and the cooperative-read block when COOP
-template <typename R, bool COOP>
+template <typename R, bool COOP, bool BATCH>
 constexpr size_t wave_lds_bytes(int row_len) {
-  return 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>) + QCAP * sizeof(uint32_t) +
+  return 2 * sizeof(WaveBuf<R, BATCH>) + QCAP * sizeof(ExitRec<R>) + QCAP * sizeof(uint32_t) +
          2 * (size_t)row_len * sizeof(double) + (COOP ? sizeof(CoopLds) : 0);
 }
 
@@ -190,13 +203,14 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     }
     __syncthreads();
   }
-  unsigned char* wbase = lds0 + net_lds_bytes<F64, CV>() + (size_t)wid * wave_lds_bytes<R, COOP>(RL);
-  WaveBuf* B = reinterpret_cast<WaveBuf*>(wbase);
-  ExitRec<R>* Q = reinterpret_cast<ExitRec<R>*>(wbase + 2 * sizeof(WaveBuf));
-  uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>));
-  double* rows = reinterpret_cast<double*>(wbase + 2 * sizeof(WaveBuf) + QCAP * sizeof(ExitRec<R>) +
+  using WB = WaveBuf<R, BATCH>;
+  unsigned char* wbase = lds0 + net_lds_bytes<F64, CV>() + (size_t)wid * wave_lds_bytes<R, COOP, BATCH>(RL);
+  WB* B = reinterpret_cast<WB*>(wbase);
+  ExitRec<R>* Q = reinterpret_cast<ExitRec<R>*>(wbase + 2 * sizeof(WB));
+  uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WB) + QCAP * sizeof(ExitRec<R>));
+  double* rows = reinterpret_cast<double*>(wbase + 2 * sizeof(WB) + QCAP * sizeof(ExitRec<R>) +
                                            QCAP * sizeof(uint32_t));
-  CoopLds* CW = reinterpret_cast<CoopLds*>(wbase + wave_lds_bytes<R, false>(RL));   // COOP only
+  CoopLds* CW = reinterpret_cast<CoopLds*>(wbase + wave_lds_bytes<R, false, BATCH>(RL));   // COOP only
   // next ticket this wave takes: fixed stride over the whole order (static
   // schedule, reproducible sums), fixed stride over its XCD's share of the
   // order (static, spatially ordered tickets: the workgroups of one XCD, which
@@ -239,7 +253,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   R ehx = 0, ehy = 0, elx = 0, ely = 0;
   R lh = (R)P.h, lsq = (R)P.sqrt_h, la = (R)P.coef.a;   // per lane in batched launches
 
-  auto geo = [&](const WaveBuf& W) __attribute__((always_inline)) -> GeoView<R> {
+  auto geo = [&](const WB& W) __attribute__((always_inline)) -> GeoView<R> {
     GeoView<R> G;
     if constexpr (BATCH) {
       G.x0 = (R)W.I.x0; G.x1 = (R)W.I.x1; G.y0 = (R)W.I.y0; G.y1 = (R)W.I.y1;
@@ -286,7 +300,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         if (isnan(r.x) || isnan(r.y)) { r.Y = (R)NAN; r.bp = (R)NAN; }
         rb = (int)((meta >> 24) & 1u);
         const bool forced = (meta >> 25) & 1u;
-        const WaveBuf& W = B[rb];
+        const WB& W = B[rb];
         const KnotDesc& d = W.d;
         const GeoView<R> G = geo(W);
         bool fE, fN, fW, fS;
@@ -388,7 +402,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     next_ticket = claim(slot);
     const uint32_t t = (uint32_t)P.order[slot];
     const Ticket T = P.tickets[t];
-    WaveBuf& W = B[b];
+    WB& W = B[b];
     const double* src = reinterpret_cast<const double*>(P.desc + T.knot);
     if (lane < (int)(sizeof(KnotDesc) / sizeof(double)))
       reinterpret_cast<double*>(&W.d)[lane] = src[lane];
@@ -408,7 +422,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       CoefParams cp = P.coef;
       double sqh = P.sqrt_h;
       if constexpr (BATCH) { cp.a = W.I.a; sqh = W.I.sqrt_h; }
-      W.ebox[lane] = (double)exit_threshold<KIND, R>(cp, P.exit_rule, sqh, W.d, lane);
+      W.ebox[lane] = exit_threshold<KIND, R>(cp, P.exit_rule, sqh, W.d, lane);
     }
     wave_sync();
     BufU<R> u;
@@ -710,15 +724,17 @@ const void* assemble_kernel(int precision, int kind, int cv, bool batch) {
 
 }  // namespace
 
-size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode) {
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch) {
   const size_t waves = (size_t)block / 64;
   if (precision == PDD_FP64_SAME_STREAM) {
     const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<true, PDD_CV_NETWORK>() : 0;
-    return net + waves * wave_lds_bytes<double, false>(row_len);
+    return net + waves * (batch ? wave_lds_bytes<double, false, true>(row_len)
+                                : wave_lds_bytes<double, false, false>(row_len));
   }
   const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<false, PDD_CV_NETWORK>() : 0;
-  return net + waves * (kind == PDD_COEF_LUT && cv_mode != PDD_CV_NETWORK ? wave_lds_bytes<float, true>(row_len)
-                                                                          : wave_lds_bytes<float, false>(row_len));
+  if (batch) return net + waves * wave_lds_bytes<float, false, true>(row_len);
+  return net + waves * (kind == PDD_COEF_LUT && cv_mode != PDD_CV_NETWORK ? wave_lds_bytes<float, true, false>(row_len)
+                                                                          : wave_lds_bytes<float, false, false>(row_len));
 }
 
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,

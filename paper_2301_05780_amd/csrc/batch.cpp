@@ -88,10 +88,10 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   auto shape = [&](int slot_len, int& blk, size_t& lds, int64_t& grid) -> pdd_status {
     const int row_len = 4 * slot_len + EX_COUNT;
     blk = block;
-    lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE);
+    lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true);
     while (lds > 65536 && blk > 64) {
       blk /= 2;
-      lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE);
+      lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true);
     }
     if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
     int per_cu = 0;

@@ -144,10 +144,10 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   const int row_len = 4 * slot_len + EX_COUNT;
   const int cv_mode = run.cv ? run.cv->mode : PDD_CV_NONE;
   int block = ctx->force_block ? ctx->force_block : 256;
-  size_t lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode);
+  size_t lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false);
   while (lds > 65536 && block > 64) {
     block /= 2;
-    lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode);
+    lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false);
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;

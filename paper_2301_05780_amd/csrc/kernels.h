@@ -123,7 +123,7 @@ hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipS
 // Cell-major copy of a LUT (lut.hip): cells[(j (n-1) + i) 8 + q], (n-1)^2 cells of 128 B.
 hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream);
 // Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
-size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode);
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch);
 // Kernel attribute query for occupancy-based grid sizing.
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
                               int* blocks_per_cu);
