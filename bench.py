@@ -116,18 +116,16 @@ def _oracle_sample(args):
 
 def cpu_baseline(w, workers, target_s=15.0):
     """The oracle's throughput on `workers` host processes over a bounded
-    sample of the workload's knots (evenly spaced, all paths of each).  Set-up
-    (process start, geometry and tables), a warm-up round of one knot per worker
-    and a pilot round of two are outside the timed region; the pilot sizes the timed
-    sample to about `target_s` seconds of wall time."""
+    sample of the workload's knots (all paths of each).  The knots are taken
+    in a well-spread order (sorted by frac(i / golden ratio)) until the timed
+    region has run `target_s` seconds of wall time.  Process start, the
+    oracle's set-up and a warm-up round of one knot per worker stay outside
+    the timed region."""
     import multiprocessing as mp
     import numpy as np
     from paper_2301_05780_amd import pdd
     n = pdd.pattern(w)[0]
-
-    def spread(count, shift):
-        return ((np.arange(count) + shift) * n / count).astype(int).clip(0, n - 1).tolist()
-
+    spread = np.argsort((np.arange(n) * 0.6180339887498949) % 1.0, kind="stable").tolist()
     pool = None
     if workers > 1:
         pool = mp.get_context("spawn").Pool(workers, initializer=_oracle_inputs, initargs=(w,))
@@ -136,22 +134,33 @@ def cpu_baseline(w, workers, target_s=15.0):
         _oracle_inputs(w)
         run = lambda ks: [_oracle_sample((w, k)) for k in ks]                            # noqa: E731
     try:
-        run(spread(workers, 0.25))                     # warm-up: imports, first-call costs
+        run(spread[-workers:])                         # warm-up: imports, first-call costs
+        steps, count = 0, 0
         t0 = time.perf_counter()
-        run(spread(2 * workers, 0.75))                 # pilot, two knots per worker, sizes the sample
-        t_knot = max(time.perf_counter() - t0, 1e-3) / (2 * workers)
-        count = int(min(n, workers * max(1, round(target_s / (t_knot * workers)))))
-        knots = spread(count, 0.0)
-        t0 = time.perf_counter()
-        steps = run(knots)
-        dt = time.perf_counter() - t0
+        dt = 0.0
+        if pool is None:
+            for k in spread:
+                steps += _oracle_sample((w, k))
+                count += 1
+                dt = time.perf_counter() - t0
+                if dt >= target_s:
+                    break
+        else:
+            # knots stream to the workers; the sample ends with the first
+            # completion after target_s (the knots still in flight are dropped)
+            for st in pool.imap_unordered(_oracle_sample, [(w, k) for k in spread], chunksize=1):
+                steps += st
+                count += 1
+                dt = time.perf_counter() - t0
+                if dt >= target_s:
+                    break
     finally:
         if pool is not None:
-            pool.close()
+            pool.terminate()
             pool.join()
-    return dict(value=sum(steps) / dt, unit="path-steps/s", cores=workers, kind="oracle",
-                sample=f"{count} of {n} knots (evenly spaced), all {w['n_paths']} paths each, "
-                       f"{sum(steps)} path-steps in {dt:.1f} s wall on {workers} processes")
+    return dict(value=steps / dt, unit="path-steps/s", cores=workers, kind="oracle",
+                sample=f"{count} of {n} knots (spread over the domain), all {w['n_paths']} paths each, "
+                       f"{steps} path-steps in {dt:.1f} s wall on {workers} processes")
 
 
 # ---- control-variate comparison (RMSE x time) ------------------------------
