@@ -351,8 +351,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the assembly shards by knot rows, and this build "
-              "runs and measures the one-GPU share (use --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU only: the assembly would shard by knot rows, and this "
+              "benchmark runs and measures one GPU's share (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
