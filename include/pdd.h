@@ -291,7 +291,8 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
  * domain give NaN.
  * Inputs (device): u_knots[n] (canonical knot order, e.g. from pdd_solve),
  * xy[2 n_pts] float64 interleaved.  Outputs (device): u[n_pts], se[n_pts]
- * (nullable) the Monte Carlo standard error of each value.
+ * (nullable) the Monte Carlo standard error of each value.  n_pts = 0 does
+ * nothing (xy and u may then be NULL).
  * run: seed, instance (< 2^31), precision, exit_rule, n_paths (paths per
  * point), h; cv, n_paths_per_knot and dump must be unset.  Path p of point i
  * draws from the Philox counter (draw, p, i, instance + 2^31), disjoint from
@@ -309,7 +310,8 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
 pdd_status pdd_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed);
 
 /* v and/or grad v of the 2-64-64-1 tanh network at n points (float32, device
- * arrays: params[PDD_MLP_PARAMS], xy[2n], v[n] nullable, grad[2n] nullable). */
+ * arrays: params[PDD_MLP_PARAMS], xy[2n], v[n] nullable, grad[2n] nullable;
+ * n = 0 does nothing, and xy, v and grad may then all be NULL). */
 pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad);
 
 /* Gradient of the loss L = mean_i (v(x_i) - t_i)^2 / 2 over the n points with

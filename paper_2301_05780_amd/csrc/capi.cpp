@@ -297,7 +297,7 @@ pdd_status pdd_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed) {
 
 pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad) {
   if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_eval: null context");
-  if (!params || !xy || n < 0 || (!v && !grad)) return fail(ctx, PDD_EINVAL, "pdd_mlp_eval: bad arguments");
+  if (!params || n < 0 || (n > 0 && (!xy || (!v && !grad)))) return fail(ctx, PDD_EINVAL, "pdd_mlp_eval: bad arguments");
   if (n == 0) return PDD_OK;
   return run_mlp_eval(ctx, params, n, xy, v, grad);
 }

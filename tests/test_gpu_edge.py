@@ -166,3 +166,17 @@ def test_refill_argument_validation(ctx):
         with pytest.raises(pdd.PddError) as e:
             ctx.set_refill(bad)
         assert e.value.status == pdd.EINVAL
+
+
+def test_empty_point_sets(ctx):
+    """Zero points: the calls succeed and touch nothing."""
+    w = workloads.poisson_small()
+    u = torch.zeros(29, dtype=torch.float64, device="cuda")
+    xy = torch.zeros(0, 2, dtype=torch.float64, device="cuda")
+    val, se = ctx.eval_subdomain(w, u, xy, 10)
+    ctx.sync()
+    assert val.numel() == 0 and se.numel() == 0
+    params = ctx.mlp_init(1)
+    v, g = ctx.mlp_eval(params, torch.zeros(0, 2, dtype=torch.float32, device="cuda"))
+    ctx.sync()
+    assert v.numel() == 0 and g.numel() == 0
