@@ -3,13 +3,15 @@
 //
 // Work decomposition.  The host cuts every knot's N_k paths into tickets
 // (knot, path range).  Each wave of the persistent grid takes tickets in a
-// fixed stride (wave w: tickets w, w + W, w + 2W, ...) and owns two LDS tally
-// rows.  Every lane integrates one path at a time; when its path exits, the
-// lane is refilled at once with the next path of the wave's current ticket,
-// ranked among the idle lanes by a ballot (no atomics).  When the current
-// ticket has handed out all its paths, the next ticket opens in the other row
-// while the stragglers of the previous one drain, so lanes never wait for the
-// slowest path of a ticket.  A drained row is written once to the ticket's
+// fixed stride (wave w: tickets w, w + W, w + 2W, ...; or from a device
+// counter) and owns two LDS tally rows.  Every lane integrates one path at a
+// time; when its path exits, the lane is refilled with the next path of the
+// wave's current ticket, ranked among the idle lanes by a ballot (no
+// atomics), at once or, with a refill threshold, once enough lanes are idle.
+// When the current ticket has handed out all its paths, the next ticket opens
+// in the other row while the stragglers of the previous one drain, so lanes
+// wait for the slowest path of a ticket only when a whole ticket is handed
+// out before its predecessor drains.  A drained row is written once to the ticket's
 // partial row in HBM; a second kernel sums a knot's partial rows in ticket
 // order into the CSR values and b (deterministic for a fixed launch shape).
 //
