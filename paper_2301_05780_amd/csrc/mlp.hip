@@ -113,7 +113,8 @@ __global__ __launch_bounds__(BLK) void k_mlp_bake(const float* __restrict__ para
 // operands straight from registers; the batch contractions read the wave's
 // LDS copies.  The four waves' gradients are summed in wave order (fixed,
 // reproducible), then every thread applies Adam to the parameters it owns.
-// Parameters stay in LDS; Adam moments live in global memory.
+// Parameters stay in LDS; each thread keeps the Adam moments of the
+// parameters it owns in registers for the whole call.
 struct TrainArgs {
   float* params;
   float* m;
@@ -147,6 +148,9 @@ struct TrainWaveLds {
 };
 
 constexpr size_t train_lds_bytes() { return PARAM_PAD * sizeof(float) + TW * sizeof(TrainWaveLds); }
+constexpr int OWN = (MLP_PARAMS + TW * 64 - 1) / (TW * 64);   // parameters per thread in Adam
+constexpr int GSTRIDE = PARAM_PAD + 4;                         // one wave's gradient slice (+ loss)
+static_assert(TW * GSTRIDE * sizeof(float) <= TW * sizeof(TrainWaveLds), "gradient slices fit the wave buffers");
 
 // accumulator register r of a 32 x 32 tile holds row 8 (r / 4) + 4 h + r % 4
 __device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
@@ -158,6 +162,13 @@ __global__ __launch_bounds__(TW * 64) void k_mlp_train(TrainArgs A) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, c = lane & 31;
   TrainWaveLds& L = WL[w];
   for (int i = tid; i < MLP_PARAMS; i += TW * 64) th[i] = A.params[i];
+  float mown[OWN], sown[OWN];           // Adam moments of parameters tid + i TW 64
+#pragma unroll
+  for (int i = 0; i < OWN; ++i) {
+    const int q = tid + i * TW * 64;
+    mown[i] = (q < MLP_PARAMS && A.update) ? A.m[q] : 0.0f;
+    sown[i] = (q < MLP_PARAMS && A.update) ? A.s[q] : 0.0f;
+  }
   __syncthreads();
   const float inv_b = 1.0f / (float)A.batch;
   const int rounds = (A.batch + 32 * TW - 1) / (32 * TW);
@@ -310,47 +321,58 @@ __global__ __launch_bounds__(TW * 64) void k_mlp_train(TrainArgs A) {
       loss += __shfl_xor(loss, off, 64);
       g_b3 += __shfl_xor(g_b3, off, 64);
     }
-    // sum the four waves' gradients into G (the wave buffers are free now), in wave order
+    // the four waves' gradients into four slices of the (now free) wave
+    // buffers, then summed per parameter in wave order (fixed, reproducible)
     __syncthreads();
-    float* G = reinterpret_cast<float*>(WL);
-    for (int ww = 0; ww < TW; ++ww) {
-      if (w == ww) {
-        auto put = [&](int q, float v) __attribute__((always_inline)) { G[q] = (ww == 0) ? v : G[q] + v; };
+    float* Gw = reinterpret_cast<float*>(WL) + w * GSTRIDE;
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
+    for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-          for (int kb = 0; kb < 2; ++kb)
+      for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-              put(OW2 + (32 * jb + acc_row(r, h)) * MLP_W + 32 * kb + c, gw2[jb][kb][r]);
-        put(OW1 + 2 * lane, g_w1x);
-        put(OW1 + 2 * lane + 1, g_w1y);
-        put(OB1 + lane, g_b1);
-        put(OB2 + lane, g_b2);
-        put(OW3 + lane, g_w3);
-        if (lane == 0) put(OB3, g_b3);
-        if (lane == 0) G[MLP_PARAMS] = (ww == 0) ? loss : G[MLP_PARAMS] + loss;
-      }
-      __syncthreads();
-    }
-    if (tid == 0 && A.losses) A.losses[step] = G[MLP_PARAMS];
+        for (int r = 0; r < 16; ++r) Gw[OW2 + (32 * jb + acc_row(r, h)) * MLP_W + 32 * kb + c] = gw2[jb][kb][r];
+    Gw[OW1 + 2 * lane] = g_w1x;
+    Gw[OW1 + 2 * lane + 1] = g_w1y;
+    Gw[OB1 + lane] = g_b1;
+    Gw[OB2 + lane] = g_b2;
+    Gw[OW3 + lane] = g_w3;
+    if (lane == 0) { Gw[OB3] = g_b3; Gw[MLP_PARAMS] = loss; }
+    __syncthreads();
+    const float* G0 = reinterpret_cast<const float*>(WL);
+    auto gsum = [&](int q) __attribute__((always_inline)) {
+      return ((G0[q] + G0[GSTRIDE + q]) + G0[2 * GSTRIDE + q]) + G0[3 * GSTRIDE + q];
+    };
+    if (tid == 0 && A.losses) A.losses[step] = gsum(MLP_PARAMS);
     if (!A.update) {
-      for (int q = tid; q < MLP_PARAMS; q += TW * 64) A.grad_out[q] = G[q];
+      for (int q = tid; q < MLP_PARAMS; q += TW * 64) A.grad_out[q] = gsum(q);
       return;
     }
-    // Adam (bias-corrected), beta1 = 0.9, beta2 = 0.999, eps = 1e-8
+    // Adam (bias-corrected), beta1 = 0.9, beta2 = 0.999, eps = 1e-8; each
+    // thread keeps the moments of the parameters it owns in registers
     const int tstep = A.step0 + step + 1;
     const float c1 = 1.0f - powf(0.9f, (float)tstep);
     const float c2 = 1.0f - powf(0.999f, (float)tstep);
-    for (int q = tid; q < MLP_PARAMS; q += TW * 64) {
-      const float g = G[q];
-      const float mq = 0.9f * A.m[q] + 0.1f * g;
-      const float sq = 0.999f * A.s[q] + 0.001f * g * g;
-      A.m[q] = mq;
-      A.s[q] = sq;
-      th[q] -= A.lr * (mq / c1) / (sqrtf(sq / c2) + 1e-8f);
+#pragma unroll
+    for (int i = 0; i < OWN; ++i) {
+      const int q = tid + i * TW * 64;
+      if (q < MLP_PARAMS) {
+        const float g = gsum(q);
+        const float mq = 0.9f * mown[i] + 0.1f * g;
+        const float sq = 0.999f * sown[i] + 0.001f * g * g;
+        mown[i] = mq;
+        sown[i] = sq;
+        th[q] -= A.lr * (mq / c1) / (sqrtf(sq / c2) + 1e-8f);
+      }
     }
     __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < OWN; ++i) {
+    const int q = tid + i * TW * 64;
+    if (q < MLP_PARAMS && A.update) {
+      A.m[q] = mown[i];
+      A.s[q] = sown[i];
+    }
   }
   for (int i = tid; i < MLP_PARAMS; i += TW * 64) A.params[i] = th[i];
 }
