@@ -268,7 +268,8 @@ def time_single(ctx, w, steps, warmup, lut=None, tune=False):
 
 def tuned_batched(ctx, ws):
     """One launch of the instances `ws` (allocating outputs and caches), then
-    the autotuner (block size, grid, ticket size, schedule, refill), whose
+    the autotuner (block size, grid, ticket size, schedule, refill, spare
+    tally rows), whose
     shape stays set on the context.  Returns (instance array, outputs, best
     kernel ms)."""
     arr, outs = ctx.batch_arrays(ws)
@@ -311,11 +312,12 @@ def time_batched(steps, warmup):
         paths = sum(float(o["diag"].view(-1, 8)[:, 1].sum().item()) for o in outs)
         grid, block, tickets = ctx.last_launch()
         refill = ctx.refill()
+        spare = ctx.spare_rows()
         ctx.close()
     return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3, path_steps=ps, paths=paths,
                 n=sum(int(o["n"]) for o in outs), nnz=sum(int(o["nnz"]) for o in outs),
-                launch={"grid": grid, "block": block, "tickets": tickets, "refill": refill, "graph_nodes": nodes,
-                "autotuned_kernel_ms": tuned_ms})
+                launch={"grid": grid, "block": block, "tickets": tickets, "refill": refill, "spare_rows": spare,
+                        "graph_nodes": nodes, "autotuned_kernel_ms": tuned_ms})
 
 
 def copy_calibration():
@@ -381,8 +383,10 @@ def main():
         r = time_single(ctx, w, args.steps, args.warmup, lut=lut, tune=args.autotune)
         grid, block, tickets = ctx.last_launch()
         launch = {"grid": grid, "block": block, "tickets": tickets, "refill": ctx.refill(),
-                  "autotuned": args.autotune}
+                  "spare_rows": ctx.spare_rows(), "autotuned": args.autotune}
         ctx.set_launch(0, 0, 0)                   # later runs (control-variate comparison) size themselves
+        ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
         desc = (f"{w['name']}: {w['kind']} coefficients, {w['H']}x{w['H']} subdomains, knot spacing "
                 f"1/{w['H'] * w['m']}, N={w['n_paths']}, h={w['h']}, {w['exit_rule']} exits")
         if w["kind"] == "lut":

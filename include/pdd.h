@@ -255,10 +255,14 @@ pdd_status pdd_graph_launch(pdd_ctx* ctx);
 /* Time the assembly of the given instance(s) (n_inst == 1: pdd_assemble;
  * otherwise pdd_assemble_batch) over a grid of launch shapes -- threads per
  * block, workgroups per compute unit, paths per ticket, static or dynamic
- * schedule -- with `reps` timed repetitions each, and keep the fastest as the
- * context's launch shape (pdd_set_launch).  *best_ms receives its mean
+ * schedule -- then, on the fastest, refill thresholds (pdd_set_refill) and
+ * spare tally rows with larger tickets (pdd_set_spare_rows), with `reps`
+ * timed repetitions each, and keep the fastest as the context's launch shape
+ * (pdd_set_launch, pdd_set_refill, pdd_set_spare_rows).  *best_ms receives its mean
  * kernel time; `report` (nullable, report_len bytes) a text table of every
- * shape tried.  Results are cached per workload signature in the context. */
+ * shape tried.  Results are cached per workload signature in the context.
+ * The call ends with one assembly in the chosen shape (also on a cache hit),
+ * so pdd_last_launch reports it and its tables are ready for graph capture. */
 pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, int32_t reps, double* best_ms,
                         char* report, int32_t report_len);
 
@@ -369,6 +373,18 @@ pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t pat
  * summation order.  pdd_autotune also tries 8, 16 and 32 on its best shape
  * and leaves the winner set. */
 pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle);
+/* Tally rows of an assembly workgroup: its waves share a pool of one row per
+ * wave plus `spare` more (at most one more per wave; -1, the default: one
+ * more per wave, so every wave can hold its current and its draining ticket
+ * at once).  Fewer rows use less LDS per wave, so more waves fit on a CU; a
+ * wave that finds no free row for its next ticket keeps stepping its running
+ * paths, or, with none running, waits for another wave of the workgroup to
+ * flush one.  Results do not depend on it except through float64 summation
+ * order.  pdd_autotune also tries 2, 1 and 0 on its best block size and
+ * schedule, with tickets of up to 4096 paths. */
+pdd_status pdd_set_spare_rows(pdd_ctx* ctx, int32_t spare);
+/* The context's current spare-row setting (-1: one per wave). */
+pdd_status pdd_get_spare_rows(const pdd_ctx* ctx, int32_t* spare);
 /* The context's current refill threshold (as set by pdd_set_refill or chosen
  * by pdd_autotune). */
 pdd_status pdd_get_refill(const pdd_ctx* ctx, int32_t* min_idle);

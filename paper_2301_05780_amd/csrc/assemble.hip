@@ -4,7 +4,9 @@
 // Work decomposition.  The host cuts every knot's N_k paths into tickets
 // (knot, path range).  Each wave of the persistent grid takes tickets in a
 // fixed stride (wave w: tickets w, w + W, w + 2W, ...; or from a device
-// counter) and owns two LDS tally rows.  Every lane integrates one path at a
+// counter) and holds up to two LDS tally rows, taken from a pool shared by
+// the waves of its workgroup (two per wave unless the launch asks for fewer,
+// which trades waiting for occupancy).  Every lane integrates one path at a
 // time; when its path exits, the lane is refilled with the next path of the
 // wave's current ticket, ranked among the idle lanes by a ballot (no
 // atomics), at once or, with a refill threshold, once enough lanes are idle.
@@ -81,13 +83,15 @@ struct CoopLds {
 };
 static_assert(sizeof(CoopLds) % 16 == 0, "CoopLds alignment");
 
-// per-wave LDS bytes: two row headers, the exit queue (records + meta words),
-// two tally rows, and the cooperative-read block when COOP
+// per-wave LDS bytes: two row headers, the exit queue (records + meta words)
+// and the cooperative-read block when COOP; the tally rows follow all waves'
+// blocks as the workgroup's pool (a 16-byte free mask, then the rows)
 template <typename R, bool COOP, bool BATCH>
-constexpr size_t wave_lds_bytes(int row_len) {
+constexpr size_t wave_lds_bytes() {
   return 2 * sizeof(WaveBuf<R, BATCH>) + QCAP * sizeof(ExitRec<R>) + QCAP * sizeof(uint32_t) +
-         2 * (size_t)row_len * sizeof(double) + (COOP ? sizeof(CoopLds) : 0);
+         (COOP ? sizeof(CoopLds) : 0);
 }
+constexpr size_t POOL_HEAD = 16;
 
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -206,13 +210,35 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     __syncthreads();
   }
   using WB = WaveBuf<R, BATCH>;
-  unsigned char* wbase = lds0 + net_lds_bytes<F64, CV>() + (size_t)wid * wave_lds_bytes<R, COOP, BATCH>(RL);
+  unsigned char* gbase = lds0 + net_lds_bytes<F64, CV>();
+  unsigned char* wbase = gbase + (size_t)wid * wave_lds_bytes<R, COOP, BATCH>();
   WB* B = reinterpret_cast<WB*>(wbase);
   ExitRec<R>* Q = reinterpret_cast<ExitRec<R>*>(wbase + 2 * sizeof(WB));
   uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WB) + QCAP * sizeof(ExitRec<R>));
-  double* rows = reinterpret_cast<double*>(wbase + 2 * sizeof(WB) + QCAP * sizeof(ExitRec<R>) +
-                                           QCAP * sizeof(uint32_t));
-  CoopLds* CW = reinterpret_cast<CoopLds*>(wbase + wave_lds_bytes<R, false, BATCH>(RL));   // COOP only
+  CoopLds* CW = reinterpret_cast<CoopLds*>(wbase + wave_lds_bytes<R, false, BATCH>());   // COOP only
+  // the workgroup's pool of tally rows and its free mask (bit r: row r free)
+  unsigned char* pbase = gbase + (size_t)waves_per_block * wave_lds_bytes<R, COOP, BATCH>();
+  uint32_t* pool = reinterpret_cast<uint32_t*>(pbase);
+  double* rows = reinterpret_cast<double*>(pbase + POOL_HEAD);
+  {
+    const int n_rows = P.pool_rows > 0 ? P.pool_rows : 2 * waves_per_block;
+    if (threadIdx.x == 0) *pool = n_rows >= 32 ? ~0u : (1u << n_rows) - 1u;
+    __syncthreads();
+  }
+  // a free row of the pool (wave-uniform), or -1 when every row is taken
+  auto pool_take = [&]() __attribute__((always_inline)) -> int {
+    int r = -1;
+    if (lane == 0) {
+      uint32_t m = atomicOr(pool, 0u);
+      while (m != 0u) {                 // each pass takes a row or drops a taken bit from m
+        const int b = __builtin_ctz(m);
+        const uint32_t old = atomicAnd(pool, ~(1u << b));
+        if (old & (1u << b)) { r = b; break; }
+        m = old & ~(1u << b);
+      }
+    }
+    return __builtin_amdgcn_readfirstlane(r);
+  };
   // next ticket this wave takes: fixed stride over the whole order (static
   // schedule, reproducible sums), fixed stride over its XCD's share of the
   // order (static, spatially ordered tickets: the workgroups of one XCD, which
@@ -240,8 +266,9 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   };
   if (P.ticket_counter) next_ticket = claim(0);
 
-  // wave-uniform ticket state of the two rows
+  // wave-uniform ticket state of the two buffers and their pool rows
   int tk0 = -1, tk1 = -1;
+  int ri0 = -1, ri1 = -1;
   int nx0 = 0, en0 = 0, nx1 = 0, en1 = 0;
   int cur = 0;
   int qn = 0;                    // queued exit records
@@ -335,7 +362,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           R w;
           hat_weights<R, F64>(along, vert ? G.y0 : G.x0, vert ? G.dy : G.dx, vert ? G.inv_dy : G.inv_dx,
                               clo, chi, q0, w);
-          double* row = rows + (size_t)rb * RL + o * SL;
+          double* row = rows + (size_t)(rb ? ri1 : ri0) * RL + o * SL;
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int q = q0 + e;
@@ -373,7 +400,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       // pipe serialises the same-address lanes; no VALU reduction needed),
       // exit-side counts through ballots
       if (valid) {
-        double* ex = rows + (size_t)rb * RL + 4 * SL;
+        double* ex = rows + (size_t)(rb ? ri1 : ri0) * RL + 4 * SL;
         lds_add(ex + EX_B, vb);
         lds_add(ex + EX_S, vs);
         lds_add(ex + EX_S2, vs * vs);
@@ -387,7 +414,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         const int cW = __popcll(__ballot(mine && o == 2));
         const int cS = __popcll(__ballot(mine && o == 3));
         if (lane == 0 && (cE | cN | cW | cS) != 0) {
-          double* ex = rows + (size_t)b * RL + 4 * SL;
+          double* ex = rows + (size_t)(b ? ri1 : ri0) * RL + 4 * SL;
           ex[EX_E] += (double)cE;
           ex[EX_N] += (double)cN;
           ex[EX_W] += (double)cW;
@@ -417,7 +444,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       W.ticket = (int32_t)t; W.p0 = T.p0; W.p1 = T.p1;
       W.inst = BATCH ? P.insts[T.inst].inst_id : T.inst;
     }
-    double* row = rows + (size_t)b * RL;
+    double* row = rows + (size_t)(b ? ri1 : ri0) * RL;
     for (int i = lane; i < RL; i += 64) row[i] = 0.0;
     wave_sync();
     if (lane < 4) {
@@ -448,11 +475,13 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   auto flush = [&](int b) __attribute__((always_inline)) {
     if (qn > 0) process_queue();
     const int t = b ? tk1 : tk0;
-    const double* row = rows + (size_t)b * RL;
+    const double* row = rows + (size_t)(b ? ri1 : ri0) * RL;
     double* dst = P.partial + (size_t)t * RL;
     for (int i = lane; i < RL; i += 64) dst[i] = row[i];
     wave_sync();
-    if (b) tk1 = -1; else tk0 = -1;
+    // the row goes back to the pool after the wave's reads of it
+    if (lane == 0) atomicOr(pool, 1u << (b ? ri1 : ri0));
+    if (b) { tk1 = -1; ri1 = -1; } else { tk0 = -1; ri0 = -1; }
   };
 
   while (true) {
@@ -469,6 +498,17 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         if ((old ? tk1 : tk0) < 0) tgt = old;
         else if ((cur ? tk1 : tk0) < 0) tgt = cur;
         if (tgt < 0 || next_ticket >= t_end) break;
+        const int r = pool_take();
+        if (r < 0) {
+          // every row of the pool is taken: step the running lanes and try
+          // again; with every lane idle this wave holds no row (its drained
+          // tickets were flushed), so the rows are held by other waves of
+          // the workgroup, which free them as their tickets drain
+          if (idle != ~0ull) break;
+          __builtin_amdgcn_s_sleep(2);
+          continue;
+        }
+        if (tgt) ri1 = r; else ri0 = r;
         acquire(tgt);
         cur = tgt;
         continue;
@@ -726,17 +766,17 @@ const void* assemble_kernel(int precision, int kind, int cv, bool batch) {
 
 }  // namespace
 
-size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch) {
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch, int pool_rows) {
   const size_t waves = (size_t)block / 64;
+  const size_t rows = POOL_HEAD + (size_t)(pool_rows > 0 ? pool_rows : 2 * (int)waves) * row_len * sizeof(double);
   if (precision == PDD_FP64_SAME_STREAM) {
     const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<true, PDD_CV_NETWORK>() : 0;
-    return net + waves * (batch ? wave_lds_bytes<double, false, true>(row_len)
-                                : wave_lds_bytes<double, false, false>(row_len));
+    return net + rows + waves * (batch ? wave_lds_bytes<double, false, true>() : wave_lds_bytes<double, false, false>());
   }
   const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<false, PDD_CV_NETWORK>() : 0;
-  if (batch) return net + waves * wave_lds_bytes<float, false, true>(row_len);
-  return net + waves * (kind == PDD_COEF_LUT && cv_mode != PDD_CV_NETWORK ? wave_lds_bytes<float, true, false>(row_len)
-                                                                          : wave_lds_bytes<float, false, false>(row_len));
+  if (batch) return net + rows + waves * wave_lds_bytes<float, false, true>();
+  return net + rows + waves * (kind == PDD_COEF_LUT && cv_mode != PDD_CV_NETWORK ? wave_lds_bytes<float, true, false>()
+                                                                                 : wave_lds_bytes<float, false, false>());
 }
 
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,

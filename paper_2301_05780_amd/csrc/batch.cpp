@@ -88,10 +88,10 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   auto shape = [&](int slot_len, int& blk, size_t& lds, int64_t& grid) -> pdd_status {
     const int row_len = 4 * slot_len + EX_COUNT;
     blk = block;
-    lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true);
+    lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true, pool_rows_for(ctx, blk));
     while (lds > 65536 && blk > 64) {
       blk /= 2;
-      lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true);
+      lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true, pool_rows_for(ctx, blk));
     }
     if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
     int per_cu = 0;
@@ -252,6 +252,7 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   P.lattice = nullptr;
   P.ticket_counter = ctx->schedule == PDD_SCHEDULE_DYNAMIC ? ctx->ticket_counter.as<uint32_t>() : nullptr;
   P.refill_min = ctx->refill_min;
+  P.pool_rows = pool_rows_for(ctx, blk);
 
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (ctx->timing && !capturing && ctx->ev_used < 4096) {
@@ -359,15 +360,6 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
              q.run.exit_rule, q.coeffs.param[0], q.part.x0, q.part.x1, q.part.y0, q.part.y1);
     sig += buf;
   }
-  for (const auto& c : ctx->tune_cache) {
-    if (c.sig == sig) {
-      ctx->force_block = c.block; ctx->force_grid = c.grid; ctx->force_per_ticket = c.per_ticket;
-      ctx->schedule = c.schedule; ctx->refill_min = c.refill;
-      *best_ms = c.ms;
-      if (report && report_len > 0) snprintf(report, report_len, "cached: %s", c.report.c_str());
-      return PDD_OK;
-    }
-  }
   auto run_once = [&]() -> pdd_status {
     if (n_inst == 1) {
       const pdd_instance& q = inst[0];
@@ -375,6 +367,15 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
     }
     return run_assemble_batch(ctx, n_inst, inst);
   };
+  for (const auto& c : ctx->tune_cache) {
+    if (c.sig == sig) {
+      ctx->force_block = c.block; ctx->force_grid = c.grid; ctx->force_per_ticket = c.per_ticket;
+      ctx->schedule = c.schedule; ctx->refill_min = c.refill; ctx->spare_rows = c.spare;
+      *best_ms = c.ms;
+      if (report && report_len > 0) snprintf(report, report_len, "cached: %s", c.report.c_str());
+      return run_once();              // tables for the cached shape, and pdd_last_launch
+    }
+  }
   std::string rep;
   double best = 1e300;
   int bb = 0, bg = 0, bt = 0, bs = 0, br = 1;
@@ -404,6 +405,7 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   const int blocks[] = {256, 128};
   const int tickets[] = {256, 384, 512, 768, 1024};
   ctx->refill_min = 1;
+  ctx->spare_rows = -1;
   for (int blk : blocks) {
     for (int per_cu_sub = 0; per_cu_sub < 2; ++per_cu_sub) {
       for (int ppt : tickets) {
@@ -449,9 +451,38 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
     if (ms < best) { best = ms; br = refill; }
   }
   ctx->refill_min = br;
+  int bt2 = bt;
+  // fewer tally rows per workgroup on the best block and schedule, with the
+  // grid the smaller LDS allows (more resident waves, which sometimes wait
+  // for a row) and larger tickets, which make those waits rarer
+  int bsp = -1;
+  for (int spare : {2, 1, 0}) {
+    for (int ppt : {bt, 2048, 4096}) {
+      if (ppt != bt && ppt <= bt) continue;
+      ctx->spare_rows = spare;
+      ctx->force_grid = 0;
+      ctx->force_per_ticket = ppt;
+      double ms = 0.0;
+      pdd_status st = run_once();
+      if (st != PDD_OK) return st;
+      if ((st = time_shape(&ms)) != PDD_OK) return st;
+      snprintf(buf, sizeof(buf), "best shape, %d spare rows, ppt %5d, grid %5d: %.4f ms\n", spare, ppt,
+               ctx->last_grid, ms);
+      rep += buf;
+      if (ms < best) { best = ms; bsp = spare; bg = 0; bt2 = ppt; }
+    }
+  }
+  bt = bt2;
+  ctx->force_per_ticket = bt;
+  ctx->spare_rows = bsp;
+  ctx->force_grid = bg;
+  // one launch with the chosen settings: its tables are the cached ones (a
+  // graph captured next replays them) and pdd_last_launch reports its shape
+  if (pdd_status st = run_once(); st != PDD_OK) return st;
   *best_ms = best;
   TuneEntry te;
-  te.sig = sig; te.block = bb; te.grid = bg; te.per_ticket = bt; te.schedule = bs; te.refill = br; te.ms = best;
+  te.sig = sig; te.block = bb; te.grid = bg; te.per_ticket = bt; te.schedule = bs; te.refill = br; te.spare = bsp;
+  te.ms = best;
   te.report = rep;
   ctx->tune_cache.push_back(te);
   if (report && report_len > 0) snprintf(report, report_len, "%s", rep.c_str());

@@ -386,6 +386,19 @@ pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle) {
   return PDD_OK;
 }
 
+pdd_status pdd_set_spare_rows(pdd_ctx* ctx, int32_t spare) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_spare_rows: null context");
+  if (spare < -1) return fail(ctx, PDD_EINVAL, "pdd_set_spare_rows: need spare >= 0, or -1 for one per wave");
+  ctx->spare_rows = spare;
+  return PDD_OK;
+}
+
+pdd_status pdd_get_spare_rows(const pdd_ctx* ctx, int32_t* spare) {
+  if (!ctx || !spare) return PDD_EINVAL;
+  *spare = ctx->spare_rows;
+  return PDD_OK;
+}
+
 pdd_status pdd_get_refill(const pdd_ctx* ctx, int32_t* min_idle) {
   if (!ctx || !min_idle) return PDD_EINVAL;
   *min_idle = ctx->refill_min;

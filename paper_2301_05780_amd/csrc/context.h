@@ -1,6 +1,8 @@
 // Library context: device, stream, caches and scratch owned by one pdd_ctx.
 #pragma once
 
+#include <algorithm>
+
 #include <hip/hip_runtime.h>
 
 #include <memory>
@@ -68,7 +70,7 @@ struct BatchCache {
 
 struct TuneEntry {
   std::string sig;
-  int block, grid, per_ticket, schedule, refill;
+  int block, grid, per_ticket, schedule, refill, spare;
   double ms;
   std::string report;
 };
@@ -107,6 +109,7 @@ struct pdd_ctx {
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
   int schedule = PDD_SCHEDULE_STATIC;
   int refill_min = 1;                // refill idle lanes once at least this many are idle
+  int spare_rows = -1;               // tally rows per workgroup beyond one per wave (-1: one per wave)
   pdd::DeviceBuffer ticket_counter;
   pdd::DeviceBuffer lut_max;         // LUT + GM: table-wide |sigma| maxima
   pdd::DeviceBuffer lut_cells;       // float32 LUT assembly: cell-major copy of the table
@@ -147,5 +150,12 @@ pdd_status run_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_part
                               double* se);
 pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                      const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres);
+
+// Tally rows in an assembly workgroup's pool: one per wave plus the context's
+// spare rows (at most one more per wave).
+inline int pool_rows_for(const pdd_ctx* ctx, int block) {
+  const int w = block / 64;
+  return ctx->spare_rows < 0 ? 2 * w : w + std::min(ctx->spare_rows, w);
+}
 
 }  // namespace pdd

@@ -67,6 +67,7 @@ struct AsmParams {
   // themselves, in a fixed stride
   const int32_t* xcd_begin;
   int32_t refill_min;         // refill a wave's idle lanes once at least this many are idle (>= 1)
+  int32_t pool_rows;          // tally rows per workgroup, shared by its waves (0: two per wave)
   int32_t row_len;            // doubles per partial row: 4 slot_len + 8
   int32_t slot_len;           // G slots per side
   int32_t L;                  // lattice intervals per direction
@@ -123,7 +124,9 @@ hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipS
 // Cell-major copy of a LUT (lut.hip): cells[(j (n-1) + i) 8 + q], (n-1)^2 cells of 128 B.
 hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream);
 // Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
-size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch);
+// LDS bytes of an assembly workgroup; pool_rows tally rows shared by its
+// waves (0: two per wave)
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch, int pool_rows);
 // Kernel attribute query for occupancy-based grid sizing.
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
                               int* blocks_per_cu);

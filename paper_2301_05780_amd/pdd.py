@@ -101,6 +101,8 @@ def lib():
             "pdd_plan_tickets": [C.POINTER(Partition), C.POINTER(Knots), vp, i32, i32, i32, C.POINTER(i64), vp, vp,
                                  vp],
             "pdd_get_refill": [vp, C.POINTER(i32)],
+            "pdd_set_spare_rows": [vp, i32],
+            "pdd_get_spare_rows": [vp, C.POINTER(i32)],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_init": [vp, vp, C.c_uint64],
             "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
@@ -230,6 +232,14 @@ class Context:
 
     def set_refill(self, min_idle=1):
         self.check(lib().pdd_set_refill(self.h, int(min_idle)))
+
+    def set_spare_rows(self, spare=-1):
+        self.check(lib().pdd_set_spare_rows(self.h, int(spare)))
+
+    def spare_rows(self):
+        r = C.c_int32()
+        self.check(lib().pdd_get_spare_rows(self.h, C.byref(r)))
+        return r.value
 
     def refill(self):
         r = C.c_int32()

@@ -129,6 +129,8 @@ def test_autotune_keeps_results(ctx):
     ctx.sync()
     tuned = [_host(o) for o in outs]
     ctx.set_launch(0, 0, 0)
+    ctx.set_refill(1)
+    ctx.set_spare_rows(-1)
     ctx.assemble_batch(ws, arr=arr)
     ctx.sync()
     for i, o in enumerate(outs):

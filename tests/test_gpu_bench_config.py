@@ -67,6 +67,7 @@ def test_varcoef_in_the_timed_configuration(ctx):
     finally:
         ctx.set_launch(0, 0, 0)
         ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
 
 
 def test_large_lut_in_the_timed_configuration(ctx):
@@ -87,6 +88,7 @@ def test_large_lut_in_the_timed_configuration(ctx):
     finally:
         ctx.set_launch(0, 0, 0)
         ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
 
 
 def test_batched_graph_replay_in_the_timed_configuration():

@@ -180,3 +180,53 @@ def test_empty_point_sets(ctx):
     v, g = ctx.mlp_eval(params, torch.zeros(0, 2, dtype=torch.float32, device="cuda"))
     ctx.sync()
     assert v.numel() == 0 and g.numel() == 0
+
+
+@pytest.mark.parametrize("spare", [0, 1])
+def test_shared_row_pool_matches_the_oracle(ctx, spare):
+    """Four waves sharing 4 (or 5) tally rows, with tickets of 16 paths so that
+    waves often find no free row for their next ticket and wait: same rows as
+    the oracle (float64 sums may change order)."""
+    w = dict(kind="varcoef", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=150, h=2e-3,
+             seed=23, precision="fp64", exit_rule="gm", instance=5)
+    g, ref = _oracle(w)
+    ctx.set_launch(256, 0, 16, "static")
+    ctx.set_spare_rows(spare)
+    assert ctx.spare_rows() == spare
+    try:
+        for _ in range(2):
+            got = fetch(ctx.assemble(w), g)
+            ctx.sync()
+            assert_same_stream(got, g, ref)
+    finally:
+        ctx.set_launch(0, 0, 0)
+        ctx.set_spare_rows(-1)
+
+
+def test_shared_row_pool_in_a_batch(ctx):
+    """The batched kernel with one row per wave (no spare), dynamic schedule."""
+    ws = []
+    for i, w in enumerate(workloads.batched()[:3]):
+        w = dict(w, H=min(w["H"], 4), m=min(w["m"], 6), n_paths=90 + 11 * i, h=2e-3, precision="fp64")
+        w["ext"] = w["m"] // 2
+        ws.append(w)
+    ctx.set_launch(128, 0, 8, "dynamic")
+    ctx.set_spare_rows(0)
+    try:
+        outs = ctx.assemble_batch(ws)
+        ctx.sync()
+        for w, o in zip(ws, outs):
+            g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+            c = Coefficients(w["kind"], w["param"])
+            rows = oracle_assemble(g, c, w["n_paths"], w["h"], w["seed"], instance=w["instance"],
+                                   exit_rule=w["exit_rule"])["rows"]
+            assert_same_stream(fetch(o, g), g, to_csr(g, rows))
+    finally:
+        ctx.set_launch(0, 0, 0)
+        ctx.set_spare_rows(-1)
+
+
+def test_spare_row_argument_validation(ctx):
+    with pytest.raises(pdd.PddError) as e:
+        ctx.set_spare_rows(-2)
+    assert e.value.status == pdd.EINVAL
