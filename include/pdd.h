@@ -381,7 +381,7 @@ pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle);
  * paths, or, with none running, waits for another wave of the workgroup to
  * flush one.  Results do not depend on it except through float64 summation
  * order.  pdd_autotune also tries 2, 1 and 0 on its best block size and
- * schedule, with tickets of up to 4096 paths. */
+ * schedule, with tickets of 1024 to 4096 paths. */
 pdd_status pdd_set_spare_rows(pdd_ctx* ctx, int32_t spare);
 /* The context's current spare-row setting (-1: one per wave). */
 pdd_status pdd_get_spare_rows(const pdd_ctx* ctx, int32_t* spare);

@@ -654,6 +654,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   assemble_body<KIND, false, PDD_CV_NONE, false>(P);
 }
 
+// float32 table family without a control variate: capped at 128 VGPRs, i.e.
+// 4 waves per SIMD, which fits the LDS when the workgroup shares fewer tally
+// rows (the path is latency-bound on its table reads and gains with every
+// resident wave)
+template <int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble_w4(AsmParams P) {
+  assemble_body<KIND, false, PDD_CV_NONE, false>(P);
+}
+
 // Sum a knot's partial rows (ticket order, then side order) into its CSR row,
 // b entry and diagnostics.  One wave per knot.
 __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
@@ -716,6 +725,8 @@ template <int KIND, bool F64, int CV, bool BATCH = false>
 const void* kernel_ptr() {
   if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND != PDD_COEF_LUT)
     return reinterpret_cast<const void*>(&k_assemble_w6<KIND>);
+  else if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND == PDD_COEF_LUT)
+    return reinterpret_cast<const void*>(&k_assemble_w4<KIND>);
   else
     return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
 }

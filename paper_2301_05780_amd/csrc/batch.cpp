@@ -457,7 +457,7 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   // for a row) and larger tickets, which make those waits rarer
   int bsp = -1;
   for (int spare : {2, 1, 0}) {
-    for (int ppt : {bt, 2048, 4096}) {
+    for (int ppt : {bt, 1024, 2048, 4096}) {
       if (ppt != bt && ppt <= bt) continue;
       ctx->spare_rows = spare;
       ctx->force_grid = 0;
