@@ -373,10 +373,11 @@ pdd_status pdd_set_launch(pdd_ctx* ctx, int32_t block, int32_t grid, int32_t pat
  * summation order.  pdd_autotune also tries 8, 16 and 32 on its best shape
  * and leaves the winner set. */
 pdd_status pdd_set_refill(pdd_ctx* ctx, int32_t min_idle);
-/* Tally rows of an assembly workgroup: its waves share a pool of one row per
- * wave plus `spare` more (at most one more per wave; -1, the default: one
- * more per wave, so every wave can hold its current and its draining ticket
- * at once).  Fewer rows use less LDS per wave, so more waves fit on a CU; a
+/* Tally rows of an assembly workgroup (batched launches and the LUT family;
+ * other single-instance assemblies keep two rows per wave): its waves share
+ * a pool of one row per wave plus `spare` more (at most one more per wave;
+ * -1, the default: one more per wave, so every wave can hold its current and
+ * its draining ticket at once).  Fewer rows use less LDS per wave, so more waves fit on a CU; a
  * wave that finds no free row for its next ticket keeps stepping its running
  * paths, or, with none running, waits for another wave of the workgroup to
  * flush one.  Results do not depend on it except through float64 summation

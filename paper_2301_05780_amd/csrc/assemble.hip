@@ -39,14 +39,15 @@ namespace {
 constexpr int QCAP = 128;          // exit records per wave (processed at >= 64)
 constexpr uint32_t MAX_STEPS = (1u << 24) - 2;
 
-// Per-buffer row header: the ticket's knot, the instance parameters (batched
+// Per-buffer header: the ticket's knot, the instance parameters (batched
 // launches only), the strict exit thresholds x > e[0], y > e[1], x < e[2],
-// y < e[3] in the path precision, and the ticket.
+// y < e[3] in the path precision, the pool row holding the buffer's tallies
+// and the instance word.
 template <typename R, bool BATCH>
 struct WaveBuf {
   KnotDesc d;
   R ebox[4];
-  int32_t ticket, p0, p1;
+  int32_t row, pad0, pad1;
   uint32_t inst;
 };
 template <typename R>
@@ -54,7 +55,7 @@ struct WaveBuf<R, true> {
   KnotDesc d;
   InstDesc I;
   R ebox[4];
-  int32_t ticket, p0, p1;
+  int32_t row, pad0, pad1;
   uint32_t inst;
 };
 static_assert(sizeof(WaveBuf<float, false>) % 16 == 0 && sizeof(WaveBuf<double, false>) % 16 == 0 &&
@@ -220,11 +221,21 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   unsigned char* pbase = gbase + (size_t)waves_per_block * wave_lds_bytes<R, COOP, BATCH>();
   uint32_t* pool = reinterpret_cast<uint32_t*>(pbase);
   double* rows = reinterpret_cast<double*>(pbase + POOL_HEAD);
-  {
+  // Batched launches and the table family share the rows through the pool;
+  // elsewhere wave w keeps rows 2w and 2w + 1 (no mask, no extra registers)
+  constexpr bool POOL = BATCH || KIND == PDD_COEF_LUT;
+  if constexpr (POOL) {
     const int n_rows = P.pool_rows > 0 ? P.pool_rows : 2 * waves_per_block;
     if (threadIdx.x == 0) *pool = n_rows >= 32 ? ~0u : (1u << n_rows) - 1u;
     __syncthreads();
   }
+  // the row of buffer b (header W), counted from `wrows`: the pool's first
+  // row, or this wave's own first row
+  double* wrows = POOL ? rows : rows + (size_t)2 * wid * RL;
+  auto row_of = [&](int b, const WaveBuf<R, BATCH>& W) __attribute__((always_inline)) -> int {
+    if constexpr (POOL) return W.row;
+    else return b;
+  };
   // a free row of the pool (wave-uniform), or -1 when every row is taken
   auto pool_take = [&]() __attribute__((always_inline)) -> int {
     int r = -1;
@@ -266,9 +277,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   };
   if (P.ticket_counter) next_ticket = claim(0);
 
-  // wave-uniform ticket state of the two buffers and their pool rows
+  // wave-uniform ticket state of the two buffers
   int tk0 = -1, tk1 = -1;
-  int ri0 = -1, ri1 = -1;
   int nx0 = 0, en0 = 0, nx1 = 0, en1 = 0;
   int cur = 0;
   int qn = 0;                    // queued exit records
@@ -362,7 +372,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           R w;
           hat_weights<R, F64>(along, vert ? G.y0 : G.x0, vert ? G.dy : G.dx, vert ? G.inv_dy : G.inv_dx,
                               clo, chi, q0, w);
-          double* row = rows + (size_t)(rb ? ri1 : ri0) * RL + o * SL;
+          double* row = wrows + (size_t)row_of(rb, W) * RL + o * SL;
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int q = q0 + e;
@@ -400,7 +410,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       // pipe serialises the same-address lanes; no VALU reduction needed),
       // exit-side counts through ballots
       if (valid) {
-        double* ex = rows + (size_t)(rb ? ri1 : ri0) * RL + 4 * SL;
+        double* ex = wrows + (size_t)row_of(rb, B[rb]) * RL + 4 * SL;
         lds_add(ex + EX_B, vb);
         lds_add(ex + EX_S, vs);
         lds_add(ex + EX_S2, vs * vs);
@@ -414,7 +424,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         const int cW = __popcll(__ballot(mine && o == 2));
         const int cS = __popcll(__ballot(mine && o == 3));
         if (lane == 0 && (cE | cN | cW | cS) != 0) {
-          double* ex = rows + (size_t)(b ? ri1 : ri0) * RL + 4 * SL;
+          double* ex = wrows + (size_t)row_of(b, B[b]) * RL + 4 * SL;
           ex[EX_E] += (double)cE;
           ex[EX_N] += (double)cN;
           ex[EX_W] += (double)cW;
@@ -426,7 +436,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     qn = 0;
   };
 
-  auto acquire = [&](int b) __attribute__((always_inline)) {
+  auto acquire = [&](int b, int prow) __attribute__((always_inline)) {
     const uint32_t slot = next_ticket;
     next_ticket = claim(slot);
     const uint32_t t = (uint32_t)P.order[slot];
@@ -441,10 +451,10 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         reinterpret_cast<double*>(&W.I)[lane] = isrc[lane];
     }
     if (lane == 0) {
-      W.ticket = (int32_t)t; W.p0 = T.p0; W.p1 = T.p1;
+      if constexpr (POOL) W.row = prow;
       W.inst = BATCH ? P.insts[T.inst].inst_id : T.inst;
     }
-    double* row = rows + (size_t)(b ? ri1 : ri0) * RL;
+    double* row = wrows + (size_t)prow * RL;
     for (int i = lane; i < RL; i += 64) row[i] = 0.0;
     wave_sync();
     if (lane < 4) {
@@ -475,13 +485,16 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   auto flush = [&](int b) __attribute__((always_inline)) {
     if (qn > 0) process_queue();
     const int t = b ? tk1 : tk0;
-    const double* row = rows + (size_t)(b ? ri1 : ri0) * RL;
+    const int prow = row_of(b, B[b]);
+    const double* row = wrows + (size_t)prow * RL;
     double* dst = P.partial + (size_t)t * RL;
     for (int i = lane; i < RL; i += 64) dst[i] = row[i];
     wave_sync();
     // the row goes back to the pool after the wave's reads of it
-    if (lane == 0) atomicOr(pool, 1u << (b ? ri1 : ri0));
-    if (b) { tk1 = -1; ri1 = -1; } else { tk0 = -1; ri0 = -1; }
+    if constexpr (POOL) {
+      if (lane == 0) atomicOr(pool, 1u << prow);
+    }
+    if (b) tk1 = -1; else tk0 = -1;
   };
 
   while (true) {
@@ -498,8 +511,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         if ((old ? tk1 : tk0) < 0) tgt = old;
         else if ((cur ? tk1 : tk0) < 0) tgt = cur;
         if (tgt < 0 || next_ticket >= t_end) break;
-        const int r = pool_take();
-        if (r < 0) {
+        const int r = POOL ? pool_take() : tgt;
+        if (POOL && r < 0) {
           // every row of the pool is taken: step the running lanes and try
           // again; with every lane idle this wave holds no row (its drained
           // tickets were flushed), so the rows are held by other waves of
@@ -508,8 +521,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           __builtin_amdgcn_s_sleep(2);
           continue;
         }
-        if (tgt) ri1 = r; else ri0 = r;
-        acquire(tgt);
+        acquire(tgt, r);
         cur = tgt;
         continue;
       }

@@ -144,12 +144,13 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   const int row_len = 4 * slot_len + EX_COUNT;
   const int cv_mode = run.cv ? run.cv->mode : PDD_CV_NONE;
   int block = ctx->force_block ? ctx->force_block : 256;
-  size_t lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false,
-                                  pool_rows_for(ctx, block));
+  // the tally rows of a workgroup: a shared pool for the table family (spare
+  // rows as set on the context), two per wave otherwise
+  auto rows_for = [&](int blk) { return job.coeffs.kind == PDD_COEF_LUT ? pool_rows_for(ctx, blk) : 2 * (blk / 64); };
+  size_t lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false, rows_for(block));
   while (lds > 65536 && block > 64) {
     block /= 2;
-    lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false,
-                             pool_rows_for(ctx, block));
+    lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false, rows_for(block));
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;
@@ -245,7 +246,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.n_tickets = (int32_t)tc->n_tickets;
   P.xcd_begin = split_xcd ? tc->xcd_begin.as<int32_t>() : nullptr;
   P.refill_min = ctx->refill_min;
-  P.pool_rows = pool_rows_for(ctx, block);
+  P.pool_rows = rows_for(block);
   P.row_len = row_len;
   P.slot_len = slot_len;
   P.partial = ctx->partial.as<double>();

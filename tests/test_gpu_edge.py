@@ -184,18 +184,20 @@ def test_empty_point_sets(ctx):
 
 @pytest.mark.parametrize("spare", [0, 1])
 def test_shared_row_pool_matches_the_oracle(ctx, spare):
-    """Four waves sharing 4 (or 5) tally rows, with tickets of 16 paths so that
-    waves often find no free row for their next ticket and wait: same rows as
-    the oracle (float64 sums may change order)."""
-    w = dict(kind="varcoef", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=150, h=2e-3,
-             seed=23, precision="fp64", exit_rule="gm", instance=5)
-    g, ref = _oracle(w)
+    """Four waves sharing 4 (or 5) tally rows (table family), with tickets of
+    16 paths so that waves often find no free row for their next ticket and
+    wait: same rows as the oracle (float64 sums may change order)."""
+    tab = workloads.varied_lut(65)
+    w = dict(kind="lut", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=150, h=2e-3,
+             seed=23, precision="fp64", exit_rule="gm", instance=5, lut_n=65)
+    g, ref = _oracle(w, tab)
+    lut = torch.from_numpy(tab).cuda()
     ctx.set_launch(256, 0, 16, "static")
     ctx.set_spare_rows(spare)
     assert ctx.spare_rows() == spare
     try:
         for _ in range(2):
-            got = fetch(ctx.assemble(w), g)
+            got = fetch(ctx.assemble(w, lut=lut), g)
             ctx.sync()
             assert_same_stream(got, g, ref)
     finally:
