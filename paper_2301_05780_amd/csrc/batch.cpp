@@ -456,7 +456,10 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   // grid the smaller LDS allows (more resident waves, which sometimes wait
   // for a row) and larger tickets, which make those waits rarer
   int bsp = -1;
+  // (single-instance assemblies share rows only with tabulated coefficients)
+  const bool pooled = n_inst > 1 || inst[0].coeffs.kind == PDD_COEF_LUT;
   for (int spare : {2, 1, 0}) {
+    if (!pooled) break;
     for (int ppt : {bt, 1024, 2048, 4096}) {
       if (ppt != bt && ppt <= bt) continue;
       ctx->spare_rows = spare;
