@@ -234,8 +234,11 @@ typedef struct pdd_instance {
  * lengths share the machine.  Every instance's result equals what
  * pdd_assemble gives it alone, up to float64 summation order.  Restrictions:
  * all instances share precision, exit rule, coefficient family (POISSON,
- * VARCOEF or AMPLITUDE) and seed; no control variate, u_ref or dump.
- * Instances are told apart in the random stream by run.instance. */
+ * VARCOEF or AMPLITUDE) and seed; no u_ref or dump.  A control variate is
+ * allowed when every instance names the same one (same mode and the same
+ * table or parameter pointers) and the instances share the domain; the
+ * network mode is float32 only here.  Instances are told apart in the random
+ * stream by run.instance (e.g. independent replicas of one problem). */
 pdd_status pdd_assemble_batch(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst);
 
 /* ---- graph capture ---------------------------------------------------------- */

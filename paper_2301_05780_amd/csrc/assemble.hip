@@ -743,12 +743,26 @@ const void* kernel_ptr() {
     return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
 }
 
-template <bool F64>
-const void* pick_batch(int kind) {
+template <bool F64, int CV>
+const void* pick_batch_kind(int kind) {
   switch (kind) {
-    case PDD_COEF_POISSON: return kernel_ptr<PDD_COEF_POISSON, F64, PDD_CV_NONE, true>();
-    case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64, PDD_CV_NONE, true>();
-    case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64, PDD_CV_NONE, true>();
+    case PDD_COEF_POISSON: return kernel_ptr<PDD_COEF_POISSON, F64, CV, true>();
+    case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64, CV, true>();
+    case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64, CV, true>();
+    default: return nullptr;
+  }
+}
+
+// batched launches: no control variate, the gradient table, or (float32
+// only) the network
+template <bool F64>
+const void* pick_batch(int kind, int cv) {
+  switch (cv) {
+    case PDD_CV_NONE: return pick_batch_kind<F64, PDD_CV_NONE>(kind);
+    case PDD_CV_GRAD_LUT: return pick_batch_kind<F64, PDD_CV_GRAD_LUT>(kind);
+    case PDD_CV_NETWORK:
+      if constexpr (!F64) return pick_batch_kind<false, PDD_CV_NETWORK>(kind);
+      else return nullptr;
     default: return nullptr;
   }
 }
@@ -780,10 +794,7 @@ const void* pick(int kind, int cv) {
 }
 
 const void* assemble_kernel(int precision, int kind, int cv, bool batch) {
-  if (batch) {
-    if (cv != PDD_CV_NONE) return nullptr;
-    return precision == PDD_FP64_SAME_STREAM ? pick_batch<true>(kind) : pick_batch<false>(kind);
-  }
+  if (batch) return precision == PDD_FP64_SAME_STREAM ? pick_batch<true>(kind, cv) : pick_batch<false>(kind, cv);
   return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind, cv) : pick<false>(kind, cv);
 }
 

@@ -53,9 +53,25 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
     if (q.run.precision != i0.run.precision || q.run.exit_rule != i0.run.exit_rule ||
         q.coeffs.kind != i0.coeffs.kind || q.run.seed != i0.run.seed)
       return bad(ctx, PDD_EINVAL, "pdd_assemble_batch: instances must share precision, exit rule, family and seed");
-    if ((q.run.cv && q.run.cv->mode != PDD_CV_NONE) || q.run.u_ref || q.run.dump_paths)
-      return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: no control variate, u_ref or dump in batches");
+    if (q.run.u_ref || q.run.dump_paths)
+      return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: no u_ref or dump in batches");
+    // a control variate is shared: the same mode and table or network for
+    // every instance, on one domain (the gradient table spans it)
+    const int qcv = q.run.cv ? q.run.cv->mode : PDD_CV_NONE;
+    const int cv0 = i0.run.cv ? i0.run.cv->mode : PDD_CV_NONE;
+    if (qcv != cv0) return bad(ctx, PDD_EINVAL, "pdd_assemble_batch: instances must share the control variate");
+    if (cv0 != PDD_CV_NONE) {
+      const pdd_cv& a = *q.run.cv;
+      const pdd_cv& b0 = *i0.run.cv;
+      if (a.params != b0.params || a.grad_lut != b0.grad_lut || a.lut_n != b0.lut_n)
+        return bad(ctx, PDD_EINVAL, "pdd_assemble_batch: instances must share the control variate");
+      if (q.part.x0 != i0.part.x0 || q.part.x1 != i0.part.x1 || q.part.y0 != i0.part.y0 || q.part.y1 != i0.part.y1)
+        return bad(ctx, PDD_EINVAL, "pdd_assemble_batch: with a control variate the instances share the domain");
+      if (cv0 == PDD_CV_NETWORK && q.run.precision == PDD_FP64_SAME_STREAM)
+        return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: the network control variate is float32 only in batches");
+    }
   }
+  const int cv_mode = i0.run.cv ? i0.run.cv->mode : PDD_CV_NONE;
   const int kind = i0.coeffs.kind;
   if (kind != PDD_COEF_POISSON && kind != PDD_COEF_VARCOEF && kind != PDD_COEF_AMPLITUDE)
     return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: families POISSON, VARCOEF and AMPLITUDE only");
@@ -88,14 +104,14 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   auto shape = [&](int slot_len, int& blk, size_t& lds, int64_t& grid) -> pdd_status {
     const int row_len = 4 * slot_len + EX_COUNT;
     blk = block;
-    lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true, pool_rows_for(ctx, blk));
+    lds = assemble_lds_bytes(precision, kind, row_len, blk, cv_mode, true, pool_rows_for(ctx, blk));
     while (lds > 65536 && blk > 64) {
       blk /= 2;
-      lds = assemble_lds_bytes(precision, kind, row_len, blk, PDD_CV_NONE, true, pool_rows_for(ctx, blk));
+      lds = assemble_lds_bytes(precision, kind, row_len, blk, cv_mode, true, pool_rows_for(ctx, blk));
     }
     if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
     int per_cu = 0;
-    hipError_t ee = assemble_occupancy(precision, kind, PDD_CV_NONE, true, blk, lds, &per_cu);
+    hipError_t ee = assemble_occupancy(precision, kind, cv_mode, true, blk, lds, &per_cu);
     if (ee != hipSuccess) return check_hip(ctx, ee, "occupancy query");
     grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * std::max(per_cu, 1);
     return PDD_OK;

@@ -284,24 +284,30 @@ class Context:
                     b=torch.empty(n, dtype=torch.float64, device=dev),
                     diag=torch.empty(n * DIAG_WIDTH, dtype=torch.float64, device=dev))
 
-    def _instance(self, w, out, precision=None, lut=None):
+    def _instance(self, w, out, precision=None, lut=None, cvp=None):
         run = Run(int(w["seed"]) & (2 ** 64 - 1), int(w.get("instance", 0)), PRECISION[precision or w["precision"]],
-                  EXIT[w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), None, None, None)
+                  EXIT[w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), cvp, None, None)
         return Instance(self.coeffs_of(w, lut), partition_of(w), knots_of(w), run,
                         _ptr(out["row_ptr"]), _ptr(out["col_idx"]), _ptr(out["val"]), _ptr(out["b"]),
                         _ptr(out["diag"]))
 
-    def batch_arrays(self, ws, outs=None, precision=None, lut=None):
+    def batch_arrays(self, ws, outs=None, precision=None, lut=None, cv=None):
         """Instance array (and outputs) for pdd_assemble_batch / pdd_autotune;
-        ``lut`` is the table of tabulated-coefficient workloads (single instance)."""
+        ``lut`` is the table of tabulated-coefficient workloads (single
+        instance); ``cv`` a CVSpec shared by every instance."""
         outs = outs or [self._outputs(w) for w in ws]
-        arr = (Instance * len(ws))(*[self._instance(w, o, precision, lut) for w, o in zip(ws, outs)])
+        cvp = None
+        if cv is not None:
+            cvs = cv if isinstance(cv, CV) else cv.struct()
+            self._keep_cv = cvs                       # the instances point at it
+            cvp = C.cast(C.pointer(cvs), C.c_void_p)
+        arr = (Instance * len(ws))(*[self._instance(w, o, precision, lut, cvp) for w, o in zip(ws, outs)])
         return arr, outs
 
-    def assemble_batch(self, ws, outs=None, precision=None, arr=None):
+    def assemble_batch(self, ws, outs=None, precision=None, arr=None, cv=None):
         """Assemble every workload of ws in one launch; returns the list of outputs."""
         if arr is None:
-            arr, outs = self.batch_arrays(ws, outs, precision)
+            arr, outs = self.batch_arrays(ws, outs, precision, cv=cv)
         self.check(lib().pdd_assemble_batch(self.h, len(arr), arr))
         self._keep_batch = arr
         return outs

@@ -247,3 +247,62 @@ def test_trained_network_reduces_variance(ctx):
     print("median variance reduction", {k: float(np.median(v)) for k, v in res.items()})
     assert np.median(res["grad_lut"]) > 5.0
     assert np.median(res["network"]) > 5.0
+
+
+def test_cv_in_a_batch_fp64_same_stream(ctx):
+    """Three replicas of one problem (instance words 0, 1, 2) with the gradient
+    table in one batched launch: each equals the oracle's run of its instance
+    to 1e-12 of the row mass."""
+    w = dict(workloads.poisson_small("gm"), n_paths=120, kind="varcoef", H=3, m=6, ext=3, h=2e-3)
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    c = Coefficients("varcoef")
+    th = _theta(6)
+    n = 65
+    xs = np.arange(n) / (n - 1)
+    X, Y = np.meshgrid(xs, xs)
+    table = omlp.grad_input(th, np.stack([X.ravel(), Y.ravel()], axis=1)).reshape(n, n, 2).astype(np.float32)
+    spec = pdd.CVSpec("grad_lut", table=_dev(table, np.float32))
+    ocv = omlp.GradLutCV(table, w["domain"])
+    ws = [dict(w, instance=i) for i in range(3)]
+    outs = ctx.assemble_batch(ws, cv=spec)
+    ctx.sync()
+    row_of = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    for i, out in enumerate(outs):
+        ref = to_csr(g, oracle_assemble(g, c, w["n_paths"], w["h"], w["seed"], instance=i, exit_rule="gm",
+                                        cv=ocv)["rows"])
+        val, b, diag = _fetch(out, g)
+        tol = 1e-12 * ref["mass"]
+        assert np.all(np.abs(val - ref["val"]) <= tol[row_of]), i
+        assert np.all(np.abs(b - ref["b"]) <= tol), i
+        assert np.array_equal(diag[:, :6], ref["diag"][:, :6]), i
+
+
+def test_network_cv_in_a_batch_matches_single_runs(ctx):
+    """float32 network control variate: a batch of replicas gives each
+    replica's single-instance result up to float64 summation order."""
+    w = dict(workloads.poisson_small("gm"), n_paths=150, kind="varcoef", H=3, m=6, ext=3, h=2e-3,
+             precision="fp32")
+    spec = pdd.CVSpec("network", params=_dev(_theta(7), np.float32))
+    ws = [dict(w, instance=i) for i in range(2)]
+    outs = ctx.assemble_batch(ws, cv=spec)
+    ctx.sync()
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    for i, out in enumerate(outs):
+        single = ctx.assemble(ws[i], cv=spec)
+        ctx.sync()
+        a, b = _fetch(out, g), _fetch(single, g)
+        assert np.allclose(a[0], b[0], rtol=0, atol=1e-9) and np.allclose(a[1], b[1], rtol=0, atol=1e-9), i
+        assert np.array_equal(a[2][:, :6], b[2][:, :6]), i
+
+
+def test_batch_rejects_mismatched_control_variates(ctx):
+    w = dict(workloads.poisson_small("gm"), n_paths=50, kind="varcoef", precision="fp32")
+    spec = pdd.CVSpec("network", params=_dev(_theta(8), np.float32))
+    arr, outs = ctx.batch_arrays([w, dict(w, instance=1)], cv=spec)
+    arr[1].run.cv = None
+    with pytest.raises(pdd.PddError) as e:
+        ctx.assemble_batch(None, arr=arr)
+    assert e.value.status == pdd.EINVAL
+    with pytest.raises(pdd.PddError) as e:
+        ctx.assemble_batch([dict(w, precision="fp64"), dict(w, precision="fp64", instance=1)], cv=spec)
+    assert e.value.status == pdd.EUNSUPPORTED
