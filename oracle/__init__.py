@@ -19,4 +19,5 @@ Modules
   solve     linear solve of G u = b and interface errors
   mlp       2-64-64-1 tanh network v(x) for the martingale control variate (eqs. 11, 37-38)
   evaluate  point values inside the subdomains from the knot values (eq. 8 on each square, Sec. 3.3)
+  calibrate Phase II: mixed GM/EM trajectories, bias, variance, correlation, h_i and N_i (eqs. 32-41)
 """
