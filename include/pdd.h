@@ -119,6 +119,8 @@ enum {
 enum { PDD_DIAG_WIDTH = 8 };   /* per knot: sum K, N, exits E/N/W/S, sum s, sum s^2 */
 enum { PDD_DUMP_WIDTH = 8 };   /* per dumped path: K, x_K, y_K, Y_K, Z_K, Xi_K, knot, path */
 enum { PDD_MLP_WIDTH = 64, PDD_MLP_PARAMS = 4417 };
+enum { PDD_CAL_WIDTH = 8 };    /* per knot: sum(phi_EM - phi_GM), sum phi_GM, sum phi_GM^2, sum xi,
+                                  sum xi^2, sum phi_GM xi, sum K_GM, sum K_EM */
 
 /* Control variate of eqs. (37)-(38): Xi accumulates -Y (sigma^T grad v) . dW
  * and is added to b only; the mean of the estimator is unchanged for any v.
@@ -307,6 +309,39 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
 pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
                               const pdd_knots* knots, const double* u_knots, int64_t n_pts, const double* xy,
                               const pdd_run* run, double* u, double* se);
+
+/* ---- Phase II calibration (Sec. 4.1-4.2, eqs. 32-41) ----------------------- */
+
+/* Mixed Gobet-Menozzi / Euler-Maruyama trajectories (Sec. 4.1): for every
+ * knot, run->n_paths paths of step run->h (h0') start at the knot and run
+ * until they leave the closed patch (the naive exit); the first step at
+ * which a path is no longer strictly inside the Gobet-Menozzi-shrunk patch is
+ * its GM exit.  Both exits are resolved as in pdd_assemble and scored with
+ * the warm-up solution, phi = Z_K + Y_K u0(P_K): u0 interpolated from
+ * u_knots (device double[n], e.g. pdd_solve of a warm-up assembly) on
+ * interface sides and the boundary datum g on the domain boundary.  With
+ * run->cv in gradient-table mode, xi (eq. 37) is drawn alongside and taken
+ * at the GM exit (run->cv NULL: xi = 0; the network mode is not accepted).
+ * Path p of knot k draws from the Philox counter (draw, p, k, run->instance)
+ * with key run->seed; run->exit_rule, n_paths_per_knot and dump are not used.
+ * stats: device double[n * PDD_CAL_WIDTH], the per-knot sums listed at
+ * PDD_CAL_WIDTH, each summed over the knot's paths in a fixed order.  Needs
+ * n * n_paths * 40 bytes of scratch (at most 16 GiB). */
+pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part, const pdd_knots* knots,
+                         const pdd_run* run, const double* u_knots, double* stats);
+
+/* Per-knot parameters from the calibration sums (host only; all arrays host):
+ * with N = n_paths and the means over the knot's paths,
+ *   bias[i] = |mean(phi_EM - phi_GM)| / 2                     (eqs. 35-36)
+ *   var[i]  = mean(phi_GM^2) - mean(phi_GM)^2 (>= 0)
+ *   rho2[i] = cov(phi_GM, xi)^2 / (var(phi_GM) var(xi)) (0 if a variance is 0)
+ *   h[i]    = min(h0, 2 h0 eps / (3 |mean(phi_GM - phi_EM)|)) (eq. 40; h0 if 0)
+ *   paths[i]= 9 var (1 - rho2) / eps^2 rounded to the closest k n_job, k >= 1
+ *                                                              (eq. 41)
+ * stats: double[n * PDD_CAL_WIDTH] (pdd_calibrate's, copied to the host);
+ * h, paths: outputs of n entries; bias, var, rho2 nullable. */
+pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths, double h0, double eps, int32_t n_job,
+                                double* h, int32_t* paths, double* bias, double* var, double* rho2);
 
 /* ---- control-variate network (eqs. 11, 37-38) ---------------------------- */
 

@@ -1,0 +1,213 @@
+// Phase II calibration (Sec. 4.1-4.2, eqs. 32-39): mixed Gobet-Menozzi /
+// Euler-Maruyama trajectories scored with the warm-up solution.
+//
+// One thread per path (knot k, path p < N0'), the assembly's random stream,
+// step and exit rules.  A path runs until it leaves the closed patch (the
+// naive exit); on the way, the first step whose iterate is not strictly
+// inside the Gobet-Menozzi-shrunk patch is its GM exit.  Each exit is
+// resolved as in the assembly (side choice, projection, hat weights) and
+// scored with u0: phi = Z_K + Y_K u0(P_K), u0 interpolated from the warm-up
+// knot values on interface sides and the boundary datum g on the domain
+// boundary.  xi is the control variate (eq. 37, with the gradient table) at
+// the GM exit.  Each path writes (phi_EM - phi_GM, phi_GM, xi, K_GM, K_EM);
+// a second kernel sums a knot's paths in a fixed order into
+//   sum(phi_EM - phi_GM), sum phi_GM, sum phi_GM^2, sum xi, sum xi^2,
+//   sum phi_GM xi, sum K_GM, sum K_EM.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "context.h"
+#include "device_common.h"
+#include "net_grad.h"
+
+namespace pdd {
+
+namespace {
+
+constexpr int BLK = 256;
+constexpr int REC = 5;               // per-path record width
+
+struct CalArgs {
+  AsmParams P;                       // geometry, coefficients, step, stream, gradient table
+  int64_t n;                         // knots
+  int32_t n_paths;                   // N0' paths per knot
+  const double* u0;                  // warm-up knot values
+  uint32_t inst;                     // fourth Philox counter word
+  double* rec;                       // REC doubles per path
+};
+
+// u0 at the exit point resolved from the flagged sides `fl` (bit o: side o)
+template <int KIND, typename R, bool F64>
+__device__ R exit_value(const AsmParams& P, const KnotDesc& d, const double* u0, R x, R y, uint32_t fl) {
+  const bool fE = fl & 1u, fN = (fl >> 1) & 1u, fW = (fl >> 2) & 1u, fS = (fl >> 3) & 1u;
+  const int o = choose_side<R>(x, y, fE, fN, fW, fS, d.line);
+  const bool vert = (o == 0 || o == 2);
+  const R along = vert ? y : x;
+  const R lpos = (R)d.line[o];
+  if ((d.bmask >> o) & 1) {
+    const R a0 = vert ? (R)P.y0 : (R)P.x0, a1 = vert ? (R)P.y1 : (R)P.x1;
+    const R pa = fmin(fmax(along, a0), a1);
+    return vert ? g_at<KIND>(lpos, pa) : g_at<KIND>(pa, lpos);
+  }
+  int q0;
+  R w;
+  hat_weights<R, F64>(along, vert ? (R)P.y0 : (R)P.x0, vert ? P.dy : P.dx, vert ? P.inv_dy : P.inv_dx, d.clo[o],
+                      d.chi[o], q0, w);
+  R val = 0;
+  for (int e = 0; e < 2; ++e) {
+    const int q = q0 + e;
+    R v;
+    if (q == 0 || q == P.L) {
+      const R qc = vert ? (R)P.y0 + (R)q * (R)P.dy : (R)P.x0 + (R)q * (R)P.dx;
+      v = vert ? g_at<KIND>(lpos, qc) : g_at<KIND>(qc, lpos);
+    } else {
+      const int lx = vert ? d.at[o] : q, ly = vert ? q : d.at[o];
+      v = (R)u0[P.lattice[(size_t)ly * (P.L + 1) + lx]];
+    }
+    {
+#pragma clang fp contract(off)
+      val = val + (e == 0 ? (R)1 - w : w) * v;
+    }
+  }
+  return val;
+}
+
+template <int KIND, bool F64, bool CVON>
+__global__ __launch_bounds__(BLK) void k_calibrate(CalArgs C) {
+  using R = typename std::conditional<F64, double, float>::type;
+  const AsmParams& P = C.P;
+  const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (gid >= C.n * C.n_paths) return;
+  const int64_t k = gid / C.n_paths;
+  const uint32_t p = (uint32_t)(gid % C.n_paths);
+  const KnotDesc d = P.desc[k];
+  R egm[4], env[4];
+  for (int o = 0; o < 4; ++o) {
+    egm[o] = exit_threshold<KIND, R>(P.coef, PDD_EXIT_GM, P.sqrt_h, d, o);
+    env[o] = exit_threshold<KIND, R>(P.coef, PDD_EXIT_NAIVE, P.sqrt_h, d, o);
+  }
+  const R h = (R)P.h, sq = (R)P.sqrt_h;
+  R x = (R)d.sx, y = (R)d.sy, Y = 1, Z = 0, Xi = 0;
+  R phi_gm = 0, xi_gm = 0, phi_em = 0;
+  uint32_t K = 0, K_gm = 0, j = 0;
+  bool gm_done = false, done = false;
+  while (!done) {
+    const U4 r = philox10(j, p, (uint32_t)k, C.inst, P.key0, P.key1);
+    for (int half = 0; half < 2 && !done; ++half) {
+      R z0, z1;
+      if constexpr (F64) box_muller(uniform64(half ? r.c : r.a), uniform64(half ? r.d : r.b), z0, z1);
+      else box_muller(uniform32(half ? r.c : r.a), uniform32(half ? r.d : r.b), z0, z1);
+      R gx = 0, gy = 0;
+      if constexpr (CVON) grad_lut(P, x, y, gx, gy);
+      em_step<KIND, R, CVON>(P.coef, h, sq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+      ++K;
+      if (!gm_done) {
+        const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_GM, sq, d.line, egm, x, y);
+        if (fl) {
+          phi_gm = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, fl);
+          xi_gm = Xi;
+          K_gm = K;
+          gm_done = true;
+        }
+      }
+      const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_NAIVE, sq, d.line, env, x, y);
+      if (fl) {
+        phi_em = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, fl);
+        done = true;
+      }
+    }
+    ++j;
+    if (!done && 2 * j >= (1u << 24) - 2) {      // step cap: every side flagged
+      if (!gm_done) {
+        phi_gm = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, 15u);
+        xi_gm = Xi;
+        K_gm = K;
+      }
+      phi_em = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, 15u);
+      done = true;
+    }
+  }
+  double* out = C.rec + gid * REC;
+  out[0] = (double)phi_em - (double)phi_gm;
+  out[1] = (double)phi_gm;
+  out[2] = (double)xi_gm;
+  out[3] = (double)K_gm;
+  out[4] = (double)K;
+}
+
+// Per-knot sums of the path records: one wave per knot, lane l takes paths
+// l, l + 64, ... in order, then a fixed butterfly across the lanes.
+__global__ __launch_bounds__(BLK) void k_calibrate_sum(const double* __restrict__ rec, int64_t n, int32_t n_paths,
+                                                       double* __restrict__ stats) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
+  if (k >= n) return;
+  double s[PDD_CAL_WIDTH] = {};
+  for (int32_t p = lane; p < n_paths; p += 64) {
+    const double* r = rec + ((size_t)k * n_paths + p) * REC;
+    s[0] += r[0];
+    s[1] += r[1];
+    s[2] += r[1] * r[1];
+    s[3] += r[2];
+    s[4] += r[2] * r[2];
+    s[5] += r[1] * r[2];
+    s[6] += r[3];
+    s[7] += r[4];
+  }
+#pragma unroll
+  for (int i = 0; i < PDD_CAL_WIDTH; ++i) {
+    for (int off = 32; off > 0; off >>= 1) s[i] += __shfl_xor(s[i], off, 64);
+  }
+  if (lane < PDD_CAL_WIDTH) {
+    double v = s[0];
+#pragma unroll
+    for (int i = 1; i < PDD_CAL_WIDTH; ++i) if (lane == i) v = s[i];
+    stats[k * PDD_CAL_WIDTH + lane] = v;
+  }
+}
+
+template <int KIND, bool F64>
+hipError_t launch_kind(const CalArgs& C, bool cv, hipStream_t stream) {
+  const int64_t threads = C.n * C.n_paths;
+  const unsigned grid = (unsigned)((threads + BLK - 1) / BLK);
+  if (cv) hipLaunchKernelGGL((k_calibrate<KIND, F64, true>), dim3(grid), dim3(BLK), 0, stream, C);
+  else hipLaunchKernelGGL((k_calibrate<KIND, F64, false>), dim3(grid), dim3(BLK), 0, stream, C);
+  return hipGetLastError();
+}
+
+template <bool F64>
+hipError_t launch_prec(const CalArgs& C, bool cv, hipStream_t stream) {
+  switch (C.P.coef.kind) {
+    case PDD_COEF_POISSON: return launch_kind<PDD_COEF_POISSON, F64>(C, cv, stream);
+    case PDD_COEF_VARCOEF: return launch_kind<PDD_COEF_VARCOEF, F64>(C, cv, stream);
+    case PDD_COEF_AMPLITUDE: return launch_kind<PDD_COEF_AMPLITUDE, F64>(C, cv, stream);
+    case PDD_COEF_LUT: return launch_kind<PDD_COEF_LUT, F64>(C, cv, stream);
+    case PDD_COEF_CONSTSOL: return launch_kind<PDD_COEF_CONSTSOL, F64>(C, cv, stream);
+    default: return launch_kind<PDD_COEF_EXITTIME, F64>(C, cv, stream);
+  }
+}
+
+}  // namespace
+
+size_t calibrate_scratch_bytes(int64_t n, int32_t n_paths) { return (size_t)n * n_paths * REC * sizeof(double); }
+
+hipError_t launch_calibrate(const AsmParams& P, int precision, int64_t n, int32_t n_paths, uint32_t inst,
+                            const double* u0, double* rec, double* stats, hipStream_t stream) {
+  CalArgs C;
+  C.P = P;
+  C.n = n;
+  C.n_paths = n_paths;
+  C.u0 = u0;
+  C.inst = inst;
+  C.rec = rec;
+  const bool cv = P.cv_mode == PDD_CV_GRAD_LUT;
+  hipError_t e = precision == PDD_FP64_SAME_STREAM ? launch_prec<true>(C, cv, stream) : launch_prec<false>(C, cv, stream);
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)((n + BLK / 64 - 1) / (BLK / 64));
+  hipLaunchKernelGGL(k_calibrate_sum, dim3(grid), dim3(BLK), 0, stream, rec, n, n_paths, stats);
+  return hipGetLastError();
+}
+
+}  // namespace pdd

@@ -289,6 +289,62 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
   return run_eval_subdomain(ctx, *coeffs, *part, *knots, u_knots, n_pts, xy, *run, u, se);
 }
 
+pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part, const pdd_knots* knots,
+                         const pdd_run* run, const double* u_knots, double* stats) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_calibrate: null context");
+  if (!coeffs || !part || !knots || !run || !u_knots || !stats)
+    return fail(ctx, PDD_EINVAL, "pdd_calibrate: bad arguments");
+  if (run->n_paths < 1 || run->n_paths > INT32_MAX) return fail(ctx, PDD_EINVAL, "pdd_calibrate: need 1 <= n_paths < 2^31");
+  if (run->cv && run->cv->mode == PDD_CV_NETWORK)
+    return fail(ctx, PDD_EINVAL, "pdd_calibrate: xi is drawn with the gradient table (run.cv mode GRAD_LUT) or not at all");
+  pdd_run r = *run;
+  r.exit_rule = PDD_EXIT_GM;
+  r.n_paths_per_knot = nullptr;
+  r.dump = nullptr;
+  r.dump_paths = 0;
+  pdd_status st = validate_run(ctx, *coeffs, r);
+  if (st != PDD_OK) return st;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  GeoCache* gc = nullptr;
+  if ((st = get_geometry(ctx, *part, *knots, &gc)) != PDD_OK) return st;
+  if ((st = get_lattice(ctx, gc)) != PDD_OK) return st;
+  const size_t bytes = calibrate_scratch_bytes(gc->g.n, (int32_t)r.n_paths);
+  if (bytes > ((size_t)16 << 30)) return fail(ctx, PDD_EINVAL, "pdd_calibrate: n * n_paths too large (16 GiB scratch)");
+  if ((e = ctx->calib_scratch.reserve(bytes)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(calibration scratch)");
+  AsmParams P;
+  fill_asm_params(*gc, *coeffs, r, P);
+  if ((st = prepare_lut_bound(ctx, *coeffs, r, P, false)) != PDD_OK) return st;
+  e = launch_calibrate(P, r.precision, gc->g.n, (int32_t)r.n_paths, r.instance, u_knots, ctx->calib_scratch.as<double>(),
+                       stats, ctx->stream);
+  return check_hip(ctx, e, "launch calibrate");
+}
+
+pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths, double h0, double eps, int32_t n_job,
+                                double* h, int32_t* paths, double* bias, double* var, double* rho2) {
+  if (n < 0 || (n > 0 && (!stats || !h || !paths)) || n_paths < 1 || !(h0 > 0.0) || !(eps > 0.0) || n_job < 1)
+    return fail(nullptr, PDD_EINVAL, "pdd_calibration_plan: bad arguments");
+  const double N = (double)n_paths;
+  for (int64_t i = 0; i < n; ++i) {
+    const double* s = stats + i * PDD_CAL_WIDTH;
+    const double mdiff = s[0] / N, mphi = s[1] / N, mxi = s[3] / N;
+    const double vphi = std::max(s[2] / N - mphi * mphi, 0.0);
+    const double vxi = std::max(s[4] / N - mxi * mxi, 0.0);
+    const double cov = s[5] / N - mphi * mxi;
+    const double den = vphi * vxi;
+    const double r2 = den > 0.0 ? std::min(cov * cov / den, 1.0) : 0.0;
+    h[i] = mdiff != 0.0 ? std::min(h0, 2.0 * h0 * eps / (3.0 * std::fabs(mdiff))) : h0;
+    const double nraw = 9.0 * vphi * (1.0 - r2) / (eps * eps);
+    const double k = std::max(std::floor(nraw / n_job + 0.5), 1.0);
+    if (k * n_job > (double)INT32_MAX) return fail(nullptr, PDD_EINVAL, "pdd_calibration_plan: path count overflows int32");
+    paths[i] = (int32_t)(k * n_job);
+    if (bias) bias[i] = 0.5 * std::fabs(mdiff);
+    if (var) var[i] = vphi;
+    if (rho2) rho2[i] = r2;
+  }
+  return PDD_OK;
+}
+
 pdd_status pdd_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed) {
   if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_init: null context");
   if (!params) return fail(ctx, PDD_EINVAL, "pdd_mlp_init: null params");

@@ -104,7 +104,7 @@ struct pdd_ctx {
   std::vector<pdd::TuneEntry> tune_cache;
   pdd::DeviceBuffer partial;
   pdd::DeviceBuffer solve_scratch, solve_flag;
-  pdd::DeviceBuffer collect_scratch, mlp_scratch;
+  pdd::DeviceBuffer collect_scratch, mlp_scratch, calib_scratch;
   // launch overrides (0 = automatic), set by the tuner
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
   int schedule = PDD_SCHEDULE_STATIC;

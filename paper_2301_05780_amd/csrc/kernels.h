@@ -120,6 +120,11 @@ hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot,
                           uint32_t inst, const double* u0, float* xy, float* yz, float* target, hipStream_t stream);
 // Table-wide maxima of |sxx|, |sxy|, |syy| of a LUT (lut.hip): out[0..2]
 // as float bit patterns, out[3] unused.  Two kernels, no memset.
+// Phase II calibration: per-path records (scratch of calibrate_scratch_bytes)
+// and their per-knot sums, stats[n * PDD_CAL_WIDTH]
+size_t calibrate_scratch_bytes(int64_t n, int32_t n_paths);
+hipError_t launch_calibrate(const AsmParams& P, int precision, int64_t n, int32_t n_paths, uint32_t inst,
+                            const double* u0, double* rec, double* stats, hipStream_t stream);
 hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipStream_t stream);
 // Cell-major copy of a LUT (lut.hip): cells[(j (n-1) + i) 8 + q], (n-1)^2 cells of 128 B.
 hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream);

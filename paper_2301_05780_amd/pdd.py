@@ -21,6 +21,7 @@ CV_MODE = {"none": 0, "network": 1, "grad_lut": 2}
 DIAG_WIDTH = 8
 DUMP_WIDTH = 8
 MLP_PARAMS = 4417
+CAL_WIDTH = 8
 
 
 class PddError(RuntimeError):
@@ -98,6 +99,8 @@ def lib():
                              C.POINTER(Run), vp, vp, vp, vp, vp],
             "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_set_refill": [vp, i32],
+            "pdd_calibrate": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots), C.POINTER(Run), vp, vp],
+            "pdd_calibration_plan": [i64, vp, i64, f64, f64, i32, vp, vp, vp, vp, vp],
             "pdd_plan_tickets": [C.POINTER(Partition), C.POINTER(Knots), vp, i32, i32, i32, C.POINTER(i64), vp, vp,
                                  vp],
             "pdd_get_refill": [vp, C.POINTER(i32)],
@@ -184,6 +187,20 @@ def plan_tickets(w, paths_per_ticket, spatial=False, grid=0):
     _check(lib().pdd_plan_tickets(*args, tickets.ctypes.data, order.ctypes.data,
                                   None if xb is None else xb.ctypes.data))
     return tickets[:T.value], order[:T.value], xb
+
+
+def calibration_plan(stats, n_paths, h0, eps, n_job):
+    """Per-knot h_i, N_i, bias bound, variance and rho^2 from calibration sums
+    (host; stats: array [n, CAL_WIDTH])."""
+    st = np.ascontiguousarray(stats, dtype=np.float64).reshape(-1, CAL_WIDTH)
+    n = st.shape[0]
+    h = np.empty(n)
+    paths = np.empty(n, dtype=np.int32)
+    bias, var, rho2 = np.empty(n), np.empty(n), np.empty(n)
+    _check(lib().pdd_calibration_plan(n, st.ctypes.data, int(n_paths), float(h0), float(eps), int(n_job),
+                                      h.ctypes.data, paths.ctypes.data, bias.ctypes.data, var.ctypes.data,
+                                      rho2.ctypes.data))
+    return dict(h=h, n_paths=paths, bias=bias, var=var, rho2=rho2)
 
 
 def knot_xy(w):
@@ -376,6 +393,25 @@ class Context:
         self.check(lib().pdd_collect_training(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
                                               _ptr(u0), int(paths_per_knot), int(points_per_path), _ptr(xy), _ptr(t)))
         return xy, t
+
+    def calibrate(self, w, u_knots, n_paths, h=None, seed=None, instance=0, precision=None, cv=None, lut=None):
+        """Phase II sums (device float64 [n, CAL_WIDTH]) from n_paths mixed
+        GM/EM paths per knot scored with the knot values u_knots."""
+        n = pattern(w)[0]
+        stats = self.torch.empty(n * CAL_WIDTH, dtype=self.torch.float64, device=self.device)
+        cvs = None
+        if cv is not None:
+            cvs = cv if isinstance(cv, CV) else cv.struct()
+        run = Run(int(w["seed"] if seed is None else seed) & (2 ** 64 - 1), int(instance),
+                  PRECISION[precision or w["precision"]], EXIT["gm"], 0, int(n_paths), None,
+                  float(w["h"] if h is None else h),
+                  C.cast(C.pointer(cvs), C.c_void_p) if cvs is not None else None, None, None)
+        co = self.coeffs_of(w, lut)
+        part, kn = partition_of(w), knots_of(w)
+        self.check(lib().pdd_calibrate(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
+                                       _ptr(u_knots), _ptr(stats)))
+        self._keep = (cvs,)
+        return stats.view(n, CAL_WIDTH)
 
     def eval_subdomain(self, w, u_knots, xy, n_paths, h=None, seed=None, instance=None, precision=None,
                        exit_rule=None, lut=None):
