@@ -163,6 +163,9 @@ def cpu_baseline(w, workers, target_s=15.0):
                        f"{steps} path-steps in {dt:.1f} s wall on {workers} processes")
 
 
+_TABLES = {}          # gradient tables baked by cv_comparison, by workload name
+
+
 # ---- control-variate comparison (RMSE x time) ------------------------------
 def cv_comparison(ctx, w, n_plain, sweep_n, seeds=16, epochs=4):
     """Plain estimator at n_plain paths per knot against the trained network
@@ -239,6 +242,7 @@ def cv_comparison(ctx, w, n_plain, sweep_n, seeds=16, epochs=4):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(ctx.stream)
     table = ctx.mlp_bake(params, w, 257)
+    _TABLES[w["name"]] = table
     e1.record(ctx.stream)
     e1.synchronize()
     t_bake = e0.elapsed_time(e1)
@@ -260,6 +264,56 @@ def cv_comparison(ctx, w, n_plain, sweep_n, seeds=16, epochs=4):
     res["training"] = {"pairs": info["pairs"], "adam_steps": info["steps"], "gpu_ms": t_train,
                        "bake_ms": t_bake}
     return res
+
+
+def phases(ctx, w, n0, eps, n_job, table=None):
+    """The paper's three phases on workload w (float32 paths): a warm-up
+    assembly with n0 paths per knot and its solve; the Phase II calibration
+    (n0 mixed GM/EM paths per knot, the control variate drawn alongside with
+    the gradient table); and the Phase III production run with the per-knot
+    path counts of eq. 41 (and the smallest h_i of eq. 40), the control
+    variate on.  Reports the calibration kernel's time and path-steps/s, the
+    plan and the final interface errors against u*."""
+    import numpy as np
+    import torch
+    from paper_2301_05780_amd import pdd
+    from oracle.coeffs import Coefficients     # the manufactured solution only
+    w = dict(w, precision="fp32")
+    xy = pdd.knot_xy(w)
+    ue = Coefficients(w["kind"], w.get("param", ())).exact(xy[:, 0], xy[:, 1])
+
+    def solve(out):
+        u, _, _ = ctx.solve(out["row_ptr"], out["col_idx"], out["val"][:out["nnz"]], out["b"])
+        return u
+
+    u_warm = solve(ctx.assemble(dict(w, n_paths=n0), seed=7))
+    err_warm = np.abs(u_warm.cpu().numpy() - ue)
+    spec = pdd.CVSpec("grad_lut", table=table) if table is not None else None
+    ctx.calibrate(w, u_warm, n0, seed=8, cv=spec)                # warm-up of the kernel
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    stats = ctx.calibrate(w, u_warm, n0, seed=9, cv=spec)
+    e1.record(ctx.stream)
+    e1.synchronize()
+    cal_ms = e0.elapsed_time(e1)
+    st = stats.cpu().numpy()
+    pl = pdd.calibration_plan(st, n0, w["h"], eps, n_job)
+    h3 = float(pl["h"].min())
+    out = ctx.assemble(dict(w, h=h3), seed=10, cv=spec, n_paths_per_knot=pl["n_paths"])
+    err = np.abs(solve(out).cpu().numpy() - ue)
+    steps = float(st[:, 7].sum())
+    return {
+        "workload": w["name"], "n0": n0, "h0": w["h"], "eps": eps, "n_job": n_job,
+        "warm_up": {"rmse": float(np.sqrt(np.mean(err_warm ** 2))), "max_error": float(err_warm.max()),
+                    "fraction_within_eps": float(np.mean(err_warm < eps))},
+        "calibration": {"gpu_ms": cal_ms, "path_steps": steps, "path_steps_per_s": steps / cal_ms * 1e3,
+                        "mean_bias_bound": float(pl["bias"].mean()), "mean_rho2": float(pl["rho2"].mean()),
+                        "knots_with_h_below_h0": int(np.sum(pl["h"] < w["h"])), "h_min": h3,
+                        "paths_total": int(pl["n_paths"].sum()), "paths_median": float(np.median(pl["n_paths"]))},
+        "production": {"rmse": float(np.sqrt(np.mean(err ** 2))), "max_error": float(err.max()),
+                       "fraction_within_eps": float(np.mean(err < eps)),
+                       "paths": int(pl["n_paths"].sum()), "h": h3},
+    }
 
 
 # ---- runs ---------------------------------------------------------------------
@@ -463,6 +517,7 @@ def main():
                 "varcoef": cv_comparison(ctx, workloads.varcoef("gm"), 10000,
                                          (10000, 5000, 2500, 1250, 625, 313)),
             }
+            rec["phases"] = phases(ctx, workloads.varcoef("gm"), 1000, 0.01, 100, _TABLES.get("varcoef"))
         ctx.close()
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
