@@ -29,6 +29,11 @@ takes at least one step.  Readings taken where the paper is terse:
   lattice points i0 and i0 + 1 receive 1 - w and w.  Interior lattice points
   are unknowns (row entries of G); lattice points on the boundary contribute
   Y w g(point) to b.
+* RBF interpolation (eq. 21 with the cardinal functions of eq. 5, the scheme
+  of Sec. 2.1 and 5.1), selected by interp=("rbf", c): every lattice point
+  clo..chi of the side's extended stencil receives its cardinal weight
+  H_q(z) at the clamped exit point z (``rbf.cardinal``), with the same split
+  into unknowns and boundary data as the hat weights.
 * Score split (eqs. 24-25): b_k collects Z_K + Xi_K and Y_K times every
   boundary datum reached; G_kj = -mean(Y_K w_j); G_kk = 1; contributions of
   one column through two sides are summed.  The control variate adds to b only.
@@ -36,6 +41,7 @@ takes at least one step.  Readings taken where the paper is terse:
 import numpy as np
 
 from .philox import normals_for_draw
+from .rbf import cardinal
 
 C_GM = 0.5825971579390106          # -zeta(1/2) / sqrt(2 pi), Gobet-Menozzi constant
 SIDE_CODE = {"E": 0, "N": 1, "W": 2, "S": 3}
@@ -133,13 +139,15 @@ def integrate_knot(geom, coef, k, n_paths, h, seed, instance, exit_rule, cv=None
                            exit_rule, cv)
 
 
-def exit_points(geom, coef, k, rec):
-    """Side choice, projection and hat-function weights for every path.
+def exit_points(geom, coef, k, rec, interp=None):
+    """Side choice, projection and interpolation weights for every path.
 
     Returns dict(side (0..3 for E, N, W, S), boundary (bool), g_side (g at
     the projected point on a boundary side, else 0), and two interface lattice
     contributions (q0, w0), (q1, w1): along-line lattice coordinates and
-    weights (w0 = w1 = 0 on boundary sides).
+    weights (w0 = w1 = 0 on boundary sides).  With interp=("rbf", c) it also
+    holds ``contribs``: per path the list of (q, H_q) over the side stencil
+    (empty on boundary sides), which then replaces the hat pair.
     """
     xlo, xhi, ylo, yhi = geom.box[k]
     x, y, fl = rec["x"], rec["y"], rec["flags"]
@@ -189,8 +197,31 @@ def exit_points(geom, coef, k, rec):
     q0[iface] = i0[iface].astype(np.int64)
     w0[iface] = 1.0 - w[iface]
     w1[iface] = w[iface]
-    return dict(side=side, boundary=boundary, g_side=g_side, q0=q0, w0=w0, w1=w1,
-                line_pos=line_pos, ex_line=ex_line)
+    out = dict(side=side, boundary=boundary, g_side=g_side, q0=q0, w0=w0, w1=w1,
+               line_pos=line_pos, ex_line=ex_line)
+    if interp is not None:
+        kind, c = interp
+        if kind != "rbf":
+            raise ValueError(kind)
+        contribs = []
+        for p in range(N):
+            if boundary[p]:
+                contribs.append([])
+                continue
+            qs = np.arange(int(clo[p]), int(chi[p]) + 1)
+            # nodes and exit point measured from the stencil's first point
+            H = cardinal((qs - clo[p]) * da[p], [(t[p] - clo[p]) * da[p]], c)[:, 0]
+            contribs.append(list(zip(qs.tolist(), H.tolist())))
+        out["contribs"] = contribs
+    return out
+
+
+def _pairs(ex, p):
+    """The (lattice coordinate, weight) contributions of interface path p."""
+    if "contribs" in ex:
+        return ex["contribs"][p]
+    q0 = int(ex["q0"][p])
+    return ((q0, ex["w0"][p]), (q0 + 1, ex["w1"][p]))
 
 
 def _lattice_target(geom, k, side, q):
@@ -227,8 +258,7 @@ def knot_row(geom, coef, k, rec, ex, u_ref=None):
             continue
         side = int(ex["side"][p])
         s = geom.side(k, ("E", "N", "W", "S")[side])
-        q0 = int(ex["q0"][p])
-        for q, w in ((q0, ex["w0"][p]), (q0 + 1, ex["w1"][p])):
+        for q, w in _pairs(ex, p):
             contrib = Yk[p] * w
             j = _lattice_target(geom, k, side, q)
             if j < 0:
@@ -266,10 +296,11 @@ def knot_row(geom, coef, k, rec, ex, u_ref=None):
 
 
 def assemble(geom, coef, n_paths, h, seed, instance=0, exit_rule="gm", cv=None,
-             u_ref=None, knots=None, keep_paths=False):
+             u_ref=None, knots=None, keep_paths=False, interp=None):
     """Assemble the rows of G and entries of b for the given knots (all by default).
 
-    n_paths: int, or per-knot array of length geom.n.
+    n_paths: int, or per-knot array of length geom.n.  interp: None for the
+    hat weights, ("rbf", c) for the inverse-multiquadric cardinal weights.
     Returns dict(rows={k: knot_row(...)}, and the per-path records if keep_paths).
     """
     if exit_rule not in ("naive", "gm"):
@@ -279,7 +310,7 @@ def assemble(geom, coef, n_paths, h, seed, instance=0, exit_rule="gm", cv=None,
     rows, paths = {}, {}
     for k in ks:
         rec = integrate_knot(geom, coef, k, npk[k], h, seed, instance, exit_rule, cv)
-        ex = exit_points(geom, coef, k, rec)
+        ex = exit_points(geom, coef, k, rec, interp)
         rows[k] = knot_row(geom, coef, k, rec, ex, u_ref)
         if keep_paths:
             rec.update(ex)
