@@ -116,6 +116,11 @@ enum {
   PDD_CV_NETWORK = 1,        /* grad v of the 2-64-64-1 tanh network at every step */
   PDD_CV_GRAD_LUT = 2        /* grad v baked into a float32 table, bilinear read */
 };
+enum {
+  PDD_INTERP_HAT = 0,        /* linear (hat) weights on the two nearest lattice points (footnote 8) */
+  PDD_INTERP_RBF_IMQ = 1     /* cardinal functions of the inverse multiquadric on the side's whole
+                                stencil (eqs. 1-5, 21) */
+};
 enum { PDD_DIAG_WIDTH = 8 };   /* per knot: sum K, N, exits E/N/W/S, sum s, sum s^2 */
 enum { PDD_DUMP_WIDTH = 8 };   /* per dumped path: K, x_K, y_K, Y_K, Z_K, Xi_K, knot, path */
 enum { PDD_MLP_WIDTH = 64, PDD_MLP_PARAMS = 4417 };
@@ -148,6 +153,9 @@ typedef struct pdd_run {
   const double* u_ref;             /* device, length n, nullable: knot values used in
                                       the per-path score diagnostics (sum s, sum s^2) */
   double* dump;                    /* device, n * dump_paths * PDD_DUMP_WIDTH, when dump_paths > 0 */
+  int32_t interp;                  /* PDD_INTERP_HAT (0) | PDD_INTERP_RBF_IMQ: interface-side interpolation */
+  double rbf_c;                    /* RBF_IMQ: shape parameter c > 0 of phi_c(r) = 1 / sqrt(r^2 + c^2),
+                                      in domain units (pdd_rbf_shape picks it by condition number) */
 } pdd_run;
 
 /* ---- context ------------------------------------------------------------- */
@@ -202,9 +210,16 @@ pdd_status pdd_knot_xy(const pdd_partition* part, const pdd_knots* knots, double
 /* Monte Carlo assembly of G (CSR) and b: for every knot k, N_k paths of the
  * diffusion (9) start at x_k and are integrated by Euler-Maruyama until they
  * first leave the knot's patch (eq. 15); the exit point is projected onto the
- * closest tripped side line and linearly interpolated onto that line's knot
- * lattice (eq. 21 with footnote 8's linear scheme).  Row k: G_kk = 1,
+ * closest tripped side line and interpolated onto that line's knot lattice
+ * (eq. 21): linearly (footnote 8's scheme, run->interp = PDD_INTERP_HAT) or
+ * with the inverse-multiquadric cardinal functions of the side's whole
+ * extended stencil (eqs. 1-5, run->interp = PDD_INTERP_RBF_IMQ; float64
+ * evaluation in both precision modes, as the interpolation matrix is
+ * ill-conditioned by design).  Row k: G_kk = 1,
  * G_kj = -mean(Y_K w_j), b_k = mean(Z_K + Xi_K + Y_K * boundary data reached).
+ * The RBF mode takes no u_ref and no network control variate
+ * (PDD_EUNSUPPORTED); its results equal the per-path definition up to
+ * rounding amplified by the condition number of the interpolation matrix.
  * Random numbers: Philox4x32-10, counter = (draw j, path p, knot k, instance),
  * draw j feeding steps 2j and 2j+1 through Box-Muller.
  * Outputs (device): row_ptr int32[n+1], col_idx int32[nnz], val double[nnz],
@@ -236,7 +251,7 @@ typedef struct pdd_instance {
  * lengths share the machine.  Every instance's result equals what
  * pdd_assemble gives it alone, up to float64 summation order.  Restrictions:
  * all instances share precision, exit rule, coefficient family (POISSON,
- * VARCOEF or AMPLITUDE) and seed; no u_ref or dump.  A control variate is
+ * VARCOEF or AMPLITUDE) and seed; no u_ref, dump or RBF interpolation.  A control variate is
  * allowed when every instance names the same one (same mode and the same
  * table or parameter pointers) and the instances share the domain; the
  * network mode is float32 only here.  Instances are told apart in the random
@@ -303,7 +318,8 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
  * (nullable) the Monte Carlo standard error of each value.  n_pts = 0 does
  * nothing (xy and u may then be NULL).
  * run: seed, instance (< 2^31), precision, exit_rule, n_paths (paths per
- * point), h; cv, n_paths_per_knot and dump must be unset.  Path p of point i
+ * point), h; cv, n_paths_per_knot and dump must be unset and interp must be
+ * PDD_INTERP_HAT (else PDD_EUNSUPPORTED).  Path p of point i
  * draws from the Philox counter (draw, p, i, instance + 2^31), disjoint from
  * the knot streams of assemblies with instance < 2^31. */
 pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
@@ -321,7 +337,8 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
  * u_knots (device double[n], e.g. pdd_solve of a warm-up assembly) on
  * interface sides and the boundary datum g on the domain boundary.  With
  * run->cv in gradient-table mode, xi (eq. 37) is drawn alongside and taken
- * at the GM exit (run->cv NULL: xi = 0; the network mode is not accepted).
+ * at the GM exit (run->cv NULL: xi = 0; the network mode and RBF
+ * interpolation are not accepted).
  * Path p of knot k draws from the Philox counter (draw, p, k, run->instance)
  * with key run->seed; run->exit_rule, n_paths_per_knot and dump are not used.
  * stats: device double[n * PDD_CAL_WIDTH], the per-knot sums listed at
@@ -342,6 +359,16 @@ pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_parti
  * h, paths: outputs of n entries; bias, var, rho2 nullable. */
 pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths, double h0, double eps, int32_t n_job,
                                 double* h, int32_t* paths, double* bias, double* var, double* rho2);
+
+/* Shape parameter of the inverse multiquadric (Sec. 5.1 picks it so that the
+ * interpolation matrix has a spectral condition number of about 1e10), host
+ * only: the c at which the matrix Phi_ij = phi_c(|i - j| spacing) of n_nodes
+ * equispaced points reaches condition number target_cond, found by bisection
+ * on log c in [1e-3, 1e3] spacing to a relative width of 1e-12 (eigenvalues
+ * by cyclic Jacobi).  PDD_EINVAL for n_nodes < 2 or > 256, spacing <= 0,
+ * target_cond outside (1, 1e14] (beyond, float64 cannot resolve it) or
+ * outside the range reached in that interval. */
+pdd_status pdd_rbf_shape(int32_t n_nodes, double spacing, double target_cond, double* c);
 
 /* ---- control-variate network (eqs. 11, 37-38) ---------------------------- */
 
@@ -385,7 +412,8 @@ pdd_status pdd_mlp_bake_grad_lut(pdd_ctx* ctx, const float* params, const pdd_pa
  * (Z_K + Y_K u(exit) - Z_n) / Y_n, u at the exit interpolated from u0 (device,
  * the solved knot values) or the boundary datum.  Outputs (device, slot
  * (k paths_per_knot + p) points_per_path + n): xy[2 slots], target[slots];
- * slots past a path's exit get a NaN target.  run.cv must be NULL. */
+ * slots past a path's exit get a NaN target.  run.cv must be NULL and
+ * run.interp PDD_INTERP_HAT (else PDD_EUNSUPPORTED). */
 pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
                                 const pdd_knots* knots, const pdd_run* run, const double* u0, int32_t paths_per_knot,
                                 int32_t points_per_path, float* xy, float* target);

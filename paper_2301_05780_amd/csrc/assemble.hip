@@ -184,7 +184,7 @@ struct GeoView {
   int L;
 };
 
-template <int KIND, bool F64, int CV, bool BATCH>
+template <int KIND, bool F64, int CV, bool BATCH, bool RBF = false>
 __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   using R = typename std::conditional<F64, double, float>::type;
   constexpr bool CVON = CV != PDD_CV_NONE;
@@ -364,6 +364,44 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           {
 #pragma clang fp contract(off)
             bp = bp + r.Y * gv;
+          }
+        } else if constexpr (RBF) {
+          // interface side, RBF cardinal interpolation: Y phi_c(|z - z_q|)
+          // into the slot of every stencil point q (the weights Phi^{-1} phi
+          // are applied once per row, after the sums).  float64 throughout:
+          // the interpolation matrix is ill-conditioned by design.  The
+          // stencil's boundary lattice points (q = 0, q = L) take their
+          // cardinal weight H_q(z) = (Phi^{-1} phi(z))_q times g into b here,
+          // so the per-path score stays whole.
+          const int clo = d.clo[o], chi = d.chi[o];
+          const int S = chi - clo + 1;
+          const double da = vert ? G.dy : G.dx;
+          const double a0 = vert ? (double)G.y0 : (double)G.x0;
+          const double t = fmin(fmax(((double)along - a0) / da, (double)clo), (double)chi);
+          const double* Mi = P.rbf_inv + (vert ? P.rbf_half : 0) + rbf_block_offset(S);
+          const double* Ml = Mi + (size_t)(S - 1) * S;
+          double* row = wrows + (size_t)row_of(rb, W) * RL + o * SL;
+          const double Yd = (double)r.Y;
+          const bool b0 = clo == 0, bL = chi == G.L;
+          double h0 = 0.0, hL = 0.0;
+          for (int i = 0; i < S; ++i) {
+            const double rr = (t - (double)(clo + i)) * da;
+            const double ph = 1.0 / sqrt(fma(rr, rr, P.rbf_c2));
+            lds_add(row + i, Yd * ph);
+            if (b0) h0 = fma(Mi[i], ph, h0);
+            if (bL) hL = fma(Ml[i], ph, hL);
+          }
+          for (int e = 0; e < 2; ++e) {
+            if (!(e ? bL : b0)) continue;
+            const int q = e ? chi : clo;
+            const R qc = vert ? G.y0 + (R)q * (R)G.dy : G.x0 + (R)q * (R)G.dx;
+            const R gv = vert ? g_at<KIND>(lpos, qc) : g_at<KIND>(qc, lpos);
+            R c;
+            {
+#pragma clang fp contract(off)
+              c = r.Y * (R)(e ? hL : h0);
+              bp = bp + c * gv;
+            }
           }
         } else {
           // interface side: hat weights on the line lattice, clamped to the stencil range
@@ -661,6 +699,12 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
 // VGPRs, i.e. 6 waves per SIMD (measured 4-12 % faster than the uncapped 5
 // waves; with the gradient-table control variate the extra spills cost more
 // than the occupancy gains)
+// RBF cardinal interpolation at the exits (single launches)
+template <int KIND, bool F64, int CV>
+__global__ __launch_bounds__(256) void k_assemble_rbf(AsmParams P) {
+  assemble_body<KIND, F64, CV, false, true>(P);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_assemble_w6(AsmParams P) {
   assemble_body<KIND, false, PDD_CV_NONE, false>(P);
@@ -684,7 +728,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
   if (F.ticket_counter && blockIdx.x == 0 && threadIdx.x < 8) F.ticket_counter[threadIdx.x] = 0u;
   if (k >= F.n) return;
   const int RL = F.row_len, SL = F.slot_len;
-  double* row = fsum + (size_t)(threadIdx.x >> 6) * RL;
+  double* row = fsum + (size_t)(threadIdx.x >> 6) * (F.rbf_inv ? 2 * RL : RL);
   const int tb = F.ticket_begin[k], te = F.ticket_begin[k + 1];
   // the knot's partial rows summed slot by slot in ticket order (coalesced reads)
   for (int i = lane; i < RL; i += 64) {
@@ -697,6 +741,25 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
   __builtin_amdgcn_wave_barrier();
   const KnotDesc d = F.desc[k];
   const double N = (double)F.n_paths[k];
+  // RBF: the slots of side o hold sums of Y phi_c(|z - z_q|); its weights
+  // are Phi^{-1} times them (Phi^{-1} symmetric: lane i reads column i)
+  const double* src = row;
+  if (F.rbf_inv) {
+    double* wv = row + RL;
+    for (int o = 0; o < 4; ++o) {
+      if ((d.bmask >> o) & 1) continue;
+      const int S = d.chi[o] - d.clo[o] + 1;
+      const double* Mi = F.rbf_inv + ((o == 0 || o == 2) ? F.rbf_half : 0) + rbf_block_offset(S);
+      for (int i = lane; i < S; i += 64) {
+        double acc = 0.0;
+        for (int j = 0; j < S; ++j) acc = fma(Mi[(size_t)j * S + i], row[o * SL + j], acc);
+        wv[o * SL + i] = acc;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    src = wv;
+  }
   for (int pos = F.row_ptr[k] + lane; pos < F.row_ptr[k + 1]; pos += 64) {
     const int col = F.col_idx[pos];
     if (col == (int)k) { F.val[pos] = 1.0; continue; }
@@ -707,7 +770,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
       const bool vert = (o == 0 || o == 2);
       const int on = vert ? cx : cy, q = vert ? cy : cx;
       if (on != d.at[o] || q < d.clo[o] || q > d.chi[o]) continue;
-      sv += row[o * SL + (q - d.clo[o])];
+      sv += src[o * SL + (q - d.clo[o])];
     }
     F.val[pos] = -sv / N;
   }
@@ -793,6 +856,36 @@ const void* pick(int kind, int cv) {
   }
 }
 
+template <bool F64, int CV>
+const void* pick_rbf_kind(int kind) {
+  switch (kind) {
+    case PDD_COEF_POISSON: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_POISSON, F64, CV>);
+    case PDD_COEF_VARCOEF: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_VARCOEF, F64, CV>);
+    case PDD_COEF_AMPLITUDE: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_AMPLITUDE, F64, CV>);
+    case PDD_COEF_LUT: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_LUT, F64, CV>);
+    default: break;
+  }
+  if constexpr (CV == PDD_CV_NONE) {
+    if (kind == PDD_COEF_CONSTSOL) return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_CONSTSOL, F64, CV>);
+    if (kind == PDD_COEF_EXITTIME) return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_EXITTIME, F64, CV>);
+  }
+  return nullptr;
+}
+
+// RBF interpolation: no control variate or the gradient table
+template <bool F64>
+const void* pick_rbf(int kind, int cv) {
+  switch (cv) {
+    case PDD_CV_NONE: return pick_rbf_kind<F64, PDD_CV_NONE>(kind);
+    case PDD_CV_GRAD_LUT: return pick_rbf_kind<F64, PDD_CV_GRAD_LUT>(kind);
+    default: return nullptr;
+  }
+}
+
+const void* rbf_kernel(int precision, int kind, int cv) {
+  return precision == PDD_FP64_SAME_STREAM ? pick_rbf<true>(kind, cv) : pick_rbf<false>(kind, cv);
+}
+
 const void* assemble_kernel(int precision, int kind, int cv, bool batch) {
   if (batch) return precision == PDD_FP64_SAME_STREAM ? pick_batch<true>(kind, cv) : pick_batch<false>(kind, cv);
   return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind, cv) : pick<false>(kind, cv);
@@ -829,11 +922,29 @@ hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int bloc
   return hipLaunchKernel(f, dim3(grid), dim3(block), args, lds_bytes, stream);
 }
 
+hipError_t assemble_occupancy_rbf(int precision, int kind, int cv_mode, int block, size_t lds_bytes,
+                                  int* blocks_per_cu) {
+  const void* f = rbf_kernel(precision, kind, cv_mode);
+  if (!f) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
+}
+
+hipError_t launch_assemble_rbf(const AsmParams& p, int precision, int grid, int block, size_t lds_bytes,
+                               hipStream_t stream) {
+  const void* f = rbf_kernel(precision, p.coef.kind, p.cv_mode);
+  if (!f || !p.rbf_inv || p.insts) return hipErrorInvalidValue;
+  AsmParams arg = p;
+  void* args[] = {&arg};
+  return hipLaunchKernel(f, dim3(grid), dim3(block), args, lds_bytes, stream);
+}
+
 hipError_t launch_finalize(const FinalizeParams& p, hipStream_t stream) {
-  // one summed row per wave in LDS (at most 160 KiB per workgroup)
-  const int block = (size_t)4 * p.row_len * sizeof(double) <= 163840 ? 256 : 64;
+  // one summed row per wave in LDS (and its RBF weights beside it), at most
+  // 160 KiB per workgroup
+  const size_t per_wave = (size_t)(p.rbf_inv ? 2 : 1) * p.row_len * sizeof(double);
+  const int block = 4 * per_wave <= 163840 ? 256 : 64;
   const int64_t grid = (p.n + block / 64 - 1) / (block / 64);
-  const size_t lds = (size_t)(block / 64) * p.row_len * sizeof(double);
+  const size_t lds = (size_t)(block / 64) * per_wave;
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_finalize),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -55,6 +55,8 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
       return bad(ctx, PDD_EINVAL, "pdd_assemble_batch: instances must share precision, exit rule, family and seed");
     if (q.run.u_ref || q.run.dump_paths)
       return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: no u_ref or dump in batches");
+    if (q.run.interp != PDD_INTERP_HAT)
+      return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: batches use the hat interpolation");
     // a control variate is shared: the same mode and table or network for
     // every instance, on one domain (the gradient table spans it)
     const int qcv = q.run.cv ? q.run.cv->mode : PDD_CV_NONE;
@@ -290,7 +292,7 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
 
   for (int32_t i = 0; i < n; ++i) {
     const GeoCache& g = *bc->geos[i];
-    FinalizeParams F;
+    FinalizeParams F{};
     F.partial = P.partial + (size_t)bc->ticket_off[i] * row_len;
     F.ticket_begin = bc->ticket_begin[i]->as<int32_t>();
     F.desc = P.desc + bc->knot_off[i];

@@ -14,6 +14,7 @@
 #include "kernels.h"
 #include "mlp.h"
 #include "plan.h"
+#include "rbf.h"
 
 using namespace pdd;
 
@@ -282,6 +283,8 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
     return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: run.n_paths_per_knot must be NULL and run.dump_paths 0");
   if (run->instance >= 0x80000000u)
     return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: run.instance must be below 2^31");
+  if (run->interp != PDD_INTERP_HAT)
+    return fail(ctx, PDD_EUNSUPPORTED, "pdd_eval_subdomain: boundary values use the hat interpolation (run.interp 0)");
   if (n_pts > INT32_MAX) return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: at most 2^31 - 1 points");
   pdd_status st = validate_run(ctx, *coeffs, *run);
   if (st != PDD_OK) return st;
@@ -297,6 +300,8 @@ pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_parti
   if (run->n_paths < 1 || run->n_paths > INT32_MAX) return fail(ctx, PDD_EINVAL, "pdd_calibrate: need 1 <= n_paths < 2^31");
   if (run->cv && run->cv->mode == PDD_CV_NETWORK)
     return fail(ctx, PDD_EINVAL, "pdd_calibrate: xi is drawn with the gradient table (run.cv mode GRAD_LUT) or not at all");
+  if (run->interp != PDD_INTERP_HAT)
+    return fail(ctx, PDD_EUNSUPPORTED, "pdd_calibrate: u0 is interpolated with the hat weights (run.interp 0)");
   pdd_run r = *run;
   r.exit_rule = PDD_EXIT_GM;
   r.n_paths_per_knot = nullptr;
@@ -342,6 +347,12 @@ pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths,
     if (var) var[i] = vphi;
     if (rho2) rho2[i] = r2;
   }
+  return PDD_OK;
+}
+
+pdd_status pdd_rbf_shape(int32_t n_nodes, double spacing, double target_cond, double* c) {
+  const pdd_status st = rbf_shape(n_nodes, spacing, target_cond, c);
+  if (st != PDD_OK) return fail(nullptr, st, "pdd_rbf_shape: need 2 <= n_nodes <= 256, spacing > 0 and 1 < target_cond <= 1e14 in reach");
   return PDD_OK;
 }
 
@@ -402,6 +413,8 @@ pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pd
     return fail(ctx, PDD_EINVAL, "pdd_collect_training: bad arguments");
   if (run->cv && run->cv->mode != PDD_CV_NONE)
     return fail(ctx, PDD_EINVAL, "pdd_collect_training: collect from plain paths (run.cv must be NULL)");
+  if (run->interp != PDD_INTERP_HAT)
+    return fail(ctx, PDD_EUNSUPPORTED, "pdd_collect_training: targets use the hat interpolation (run.interp 0)");
   pdd_status st = validate_run(ctx, *coeffs, *run);
   if (st != PDD_OK) return st;
   hipError_t e = hipSetDevice(ctx->device);

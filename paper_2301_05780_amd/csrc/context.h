@@ -89,6 +89,16 @@ struct AssembleJob {
 
 }  // namespace pdd
 
+namespace pdd {
+// Inverses of the RBF stencil matrices for one (slot length, spacing, c).
+struct RbfCache {
+  int32_t slot_len = 0;
+  double dx = 0, dy = 0, c = 0;
+  int64_t half = 0;
+  DeviceBuffer tab;
+};
+}  // namespace pdd
+
 struct pdd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -98,6 +108,7 @@ struct pdd_ctx {
   std::vector<std::unique_ptr<pdd::GeoCache>> geo;
   std::unique_ptr<pdd::TicketCache> tickets;
   std::unique_ptr<pdd::BatchCache> batch;
+  std::unique_ptr<pdd::RbfCache> rbf;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool capturing = false;

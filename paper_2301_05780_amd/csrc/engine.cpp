@@ -8,6 +8,7 @@
 
 #include "context.h"
 #include "plan.h"
+#include "rbf.h"
 
 namespace pdd {
 
@@ -36,6 +37,14 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
     return bad(ctx, PDD_EINVAL, "run.n_paths: need 1 <= n_paths <= 2^31 - 1");
   if (r.dump_paths < 0 || (r.dump_paths > 0 && !r.dump))
     return bad(ctx, PDD_EINVAL, "run.dump_paths: need dump_paths >= 0 and a dump buffer when > 0");
+  if (r.interp != PDD_INTERP_HAT && r.interp != PDD_INTERP_RBF_IMQ)
+    return bad(ctx, PDD_EINVAL, "run.interp: unknown interpolation");
+  if (r.interp == PDD_INTERP_RBF_IMQ) {
+    if (!(r.rbf_c > 0.0) || !std::isfinite(r.rbf_c)) return bad(ctx, PDD_EINVAL, "run.rbf_c: need a finite shape parameter > 0");
+    if (r.u_ref) return bad(ctx, PDD_EUNSUPPORTED, "run.u_ref: not available with RBF interpolation");
+    if (r.cv && r.cv->mode == PDD_CV_NETWORK)
+      return bad(ctx, PDD_EUNSUPPORTED, "run.cv: RBF interpolation takes no control variate or the gradient table");
+  }
   if (r.cv) {
     const pdd_cv& cv = *r.cv;
     if (cv.mode < PDD_CV_NONE || cv.mode > PDD_CV_GRAD_LUT) return bad(ctx, PDD_EINVAL, "run.cv.mode: unknown mode");
@@ -113,6 +122,35 @@ void fill_asm_params(const GeoCache& gcr, const pdd_coeffs& co, const pdd_run& r
   }
 }
 
+// The inverse table of the RBF stencil matrices for this geometry and shape
+// parameter (built on the host and uploaded once per combination).
+pdd_status prepare_rbf(pdd_ctx* ctx, const Geometry& g, const pdd_run& run, AsmParams& P, bool capturing) {
+  RbfCache* rc = ctx->rbf.get();
+  if (!rc || rc->slot_len != g.slot_len || rc->dx != g.dx || rc->dy != g.dy || rc->c != run.rbf_c) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: RBF table not cached; run the same call once before capturing");
+    auto fresh = std::make_unique<RbfCache>();
+    fresh->slot_len = g.slot_len;
+    fresh->dx = g.dx;
+    fresh->dy = g.dy;
+    fresh->c = run.rbf_c;
+    std::vector<double> tab;
+    if (!rbf_inverse_table(g.slot_len, g.dx, g.dy, run.rbf_c, tab, fresh->half))
+      return bad(ctx, PDD_EINVAL, "run.rbf_c: a stencil's interpolation matrix is not positive definite in float64 "
+                                  "(shape parameter too large for the stencil)");
+    hipError_t e;
+    if ((e = fresh->tab.reserve(tab.size() * sizeof(double))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(rbf table)");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(fresh->tab.ptr, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return check_hip(ctx, e, "upload rbf table");
+    ctx->rbf = std::move(fresh);
+    rc = ctx->rbf.get();
+  }
+  P.rbf_inv = rc->tab.as<double>();
+  P.rbf_half = rc->half;
+  P.rbf_c2 = run.rbf_c * run.rbf_c;
+  return PDD_OK;
+}
+
 pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
@@ -154,7 +192,9 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;
-  e = assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, false, block, lds, &per_cu);
+  const bool rbf = run.interp == PDD_INTERP_RBF_IMQ;
+  e = rbf ? assemble_occupancy_rbf(run.precision, job.coeffs.kind, cv_mode, block, lds, &per_cu)
+          : assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, false, block, lds, &per_cu);
   if (e != hipSuccess) return check_hip(ctx, e, "occupancy query");
   per_cu = std::max(per_cu, 1);
   int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
@@ -255,6 +295,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.ticket_counter = nullptr;
   if ((st = prepare_lut_bound(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
   if ((st = prepare_lut_cells(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
+  if (rbf && (st = prepare_rbf(ctx, g, run, P, capturing)) != PDD_OK) return st;
   if (ctx->schedule == PDD_SCHEDULE_DYNAMIC) {
     if (!ctx->ticket_counter.ptr) {
       if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: counter not allocated; run once before capturing");
@@ -275,14 +316,15 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     t1 = ctx->ev_pool[2 * ctx->ev_used + 1];
     if ((e = hipEventRecord(t0, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
   }
-  e = launch_assemble(P, run.precision, (int)grid, block, lds, ctx->stream);
+  e = rbf ? launch_assemble_rbf(P, run.precision, (int)grid, block, lds, ctx->stream)
+          : launch_assemble(P, run.precision, (int)grid, block, lds, ctx->stream);
   if (e != hipSuccess) return check_hip(ctx, e, "launch assemble");
   if (t1) {
     if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
     ctx->ev_used += 1;
   }
 
-  FinalizeParams F;
+  FinalizeParams F{};
   F.partial = P.partial;
   F.ticket_begin = tc->ticket_begin.as<int32_t>();
   F.desc = P.desc;
@@ -297,6 +339,8 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   F.b = job.b;
   F.diag = job.diag;
   F.ticket_counter = P.ticket_counter;
+  F.rbf_inv = P.rbf_inv;
+  F.rbf_half = P.rbf_half;
   e = launch_finalize(F, ctx->stream);
   if (e != hipSuccess) return check_hip(ctx, e, "launch finalize");
   ctx->last_grid = (int)grid;

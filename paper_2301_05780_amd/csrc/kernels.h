@@ -9,6 +9,11 @@
 
 namespace pdd {
 
+// Offset of the S x S block in one orientation's half of the RBF inverse
+// table: blocks for S = 1, 2, ... are stored back to back, so S starts at
+// 1^2 + ... + (S-1)^2.
+__host__ __device__ inline int64_t rbf_block_offset(int64_t S) { return (S - 1) * S * (2 * S - 1) / 6; }
+
 // Per-knot descriptor read by the assembly kernels (one per unknown).
 struct KnotDesc {
   double sx, sy;          // start point x_k
@@ -90,6 +95,12 @@ struct AsmParams {
   const float* cv_params;     // network parameters (float32, PDD_MLP_PARAMS)
   const float* cv_lut;        // grad v table [n][n][2]
   float cv_lut_sx, cv_lut_sy; // (n-1)/(x1-x0), (n-1)/(y1-y0)
+  // RBF interpolation (kernels built for it only): inverses of the stencil
+  // interpolation matrices, S x S row-major at rbf_inv[vert * rbf_half +
+  // rbf_block_offset(S)] (vert: sides on lines x = const, spacing dy)
+  const double* rbf_inv;
+  int64_t rbf_half;
+  double rbf_c2;              // c^2
 };
 
 // Extras stored after the 4 slot_len G slots of a partial row.
@@ -109,11 +120,21 @@ struct FinalizeParams {
   double* b;
   double* diag;                  // nullable
   uint32_t* ticket_counter;      // 8 counters reset to zero for the next assembly (nullable)
+  // RBF interpolation (nullable: hat weights): the slots of an interface side
+  // hold sums of Y phi_c(|z - z_q|); the weights are Phi^{-1} times them
+  const double* rbf_inv;
+  int64_t rbf_half;
 };
 
 // Launchers (defined in assemble.hip).  Return hipSuccess or the launch error.
 hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block,
                            size_t lds_bytes, hipStream_t stream);
+// RBF interpolation: the same launch with the kernels built for it (single
+// launches; control variate none or gradient table)
+hipError_t launch_assemble_rbf(const AsmParams& p, int precision, int grid, int block, size_t lds_bytes,
+                               hipStream_t stream);
+hipError_t assemble_occupancy_rbf(int precision, int kind, int cv_mode, int block, size_t lds_bytes,
+                                  int* blocks_per_cu);
 hipError_t launch_finalize(const FinalizeParams& p, hipStream_t stream);
 // Training-pair collection (collect.hip).
 hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot, int32_t points_per_path,

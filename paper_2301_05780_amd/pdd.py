@@ -22,6 +22,7 @@ DIAG_WIDTH = 8
 DUMP_WIDTH = 8
 MLP_PARAMS = 4417
 CAL_WIDTH = 8
+INTERP = {"hat": 0, "rbf": 1}
 
 
 class PddError(RuntimeError):
@@ -66,7 +67,7 @@ class Run(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32), ("precision", C.c_int32),
                 ("exit_rule", C.c_int32), ("dump_paths", C.c_int32), ("n_paths", C.c_int64),
                 ("n_paths_per_knot", C.c_void_p), ("h", C.c_double), ("cv", C.c_void_p),
-                ("u_ref", C.c_void_p), ("dump", C.c_void_p)]
+                ("u_ref", C.c_void_p), ("dump", C.c_void_p), ("interp", C.c_int32), ("rbf_c", C.c_double)]
 
 
 class Instance(C.Structure):
@@ -101,6 +102,7 @@ def lib():
             "pdd_set_refill": [vp, i32],
             "pdd_calibrate": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots), C.POINTER(Run), vp, vp],
             "pdd_calibration_plan": [i64, vp, i64, f64, f64, i32, vp, vp, vp, vp, vp],
+            "pdd_rbf_shape": [i32, f64, f64, C.POINTER(f64)],
             "pdd_plan_tickets": [C.POINTER(Partition), C.POINTER(Knots), vp, i32, i32, i32, C.POINTER(i64), vp, vp,
                                  vp],
             "pdd_get_refill": [vp, C.POINTER(i32)],
@@ -201,6 +203,23 @@ def calibration_plan(stats, n_paths, h0, eps, n_job):
                                       h.ctypes.data, paths.ctypes.data, bias.ctypes.data, var.ctypes.data,
                                       rho2.ctypes.data))
     return dict(h=h, n_paths=paths, bias=bias, var=var, rho2=rho2)
+
+
+def rbf_shape(n_nodes, spacing, target_cond=1e10):
+    """Shape parameter c of the inverse multiquadric at which the
+    interpolation matrix of n_nodes equispaced points reaches target_cond
+    (host)."""
+    c = C.c_double()
+    _check(lib().pdd_rbf_shape(int(n_nodes), float(spacing), float(target_cond), C.byref(c)))
+    return c.value
+
+
+def _set_interp(run, w):
+    """Interpolation fields of a Run from workload keys ``interp`` ("hat" or
+    "rbf") and ``rbf_c``."""
+    run.interp = INTERP[w.get("interp", "hat")]
+    run.rbf_c = float(w.get("rbf_c", 0.0))
+    return run
 
 
 def knot_xy(w):
@@ -304,6 +323,7 @@ class Context:
     def _instance(self, w, out, precision=None, lut=None, cvp=None):
         run = Run(int(w["seed"]) & (2 ** 64 - 1), int(w.get("instance", 0)), PRECISION[precision or w["precision"]],
                   EXIT[w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), cvp, None, None)
+        _set_interp(run, w)
         return Instance(self.coeffs_of(w, lut), partition_of(w), knots_of(w), run,
                         _ptr(out["row_ptr"]), _ptr(out["col_idx"]), _ptr(out["val"]), _ptr(out["b"]),
                         _ptr(out["diag"]))
@@ -388,6 +408,7 @@ class Context:
         t = self.torch.empty(slots, dtype=self.torch.float32, device=self.device)
         run = Run(int(w["seed"] if seed is None else seed), int(w.get("instance", 0)), PRECISION["fp32"],
                   EXIT[exit_rule or w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), None, None, None)
+        _set_interp(run, w)
         co = self.coeffs_of(w, lut)
         part, kn = partition_of(w), knots_of(w)
         self.check(lib().pdd_collect_training(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
@@ -406,6 +427,7 @@ class Context:
                   PRECISION[precision or w["precision"]], EXIT["gm"], 0, int(n_paths), None,
                   float(w["h"] if h is None else h),
                   C.cast(C.pointer(cvs), C.c_void_p) if cvs is not None else None, None, None)
+        _set_interp(run, w)
         co = self.coeffs_of(w, lut)
         part, kn = partition_of(w), knots_of(w)
         self.check(lib().pdd_calibrate(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
@@ -424,6 +446,7 @@ class Context:
                   int(w.get("instance", 0) if instance is None else instance),
                   PRECISION[precision or w["precision"]], EXIT[exit_rule or w["exit_rule"]], 0, int(n_paths),
                   None, float(w["h"] if h is None else h), None, None, None)
+        _set_interp(run, w)
         co = self.coeffs_of(w, lut)
         part, kn = partition_of(w), knots_of(w)
         self.check(lib().pdd_eval_subdomain(self.h, C.byref(co), C.byref(part), C.byref(kn), _ptr(u_knots), int(P),
@@ -467,6 +490,7 @@ class Context:
                   int(dump_paths), int(w["n_paths"]), _ptr(npk), float(w["h"]),
                   C.cast(C.pointer(cvs), C.c_void_p) if cvs is not None else None,
                   _ptr(u_ref), _ptr(out.get("dump")) if dump_paths else None)
+        _set_interp(run, w)
         co = self.coeffs_of(w, lut)
         part, kn = partition_of(w), knots_of(w)
         self.check(lib().pdd_assemble(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),

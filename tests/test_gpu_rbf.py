@@ -1,0 +1,186 @@
+"""GPU parity of the RBF cardinal interpolation (eqs. 1-5, 21) through the C
+ABI against the CPU oracle.
+
+The kernels sum Y phi_c(|z - z_q|) over a row's paths and apply Phi^{-1}
+once per row side; the oracle solves Phi H = phi(z) per path.  The two agree
+up to rounding amplified by the condition number kappa of the stencil's
+interpolation matrix: each cardinal weight carries an error of at most about
+S kappa u (S stencil points, u = 2^-53), so the bars are
+
+  * float64 same-stream: every G and b entry within (1e-12 + S kappa u) of
+    the row's mean absolute per-path contribution; step counts and exit-side
+    counts exact (the paths are those of the hat assembly);
+  * float32 production: within 3 Monte Carlo standard errors plus the
+    float32 rounding floor of the hat tests.
+"""
+import numpy as np
+import pytest
+
+from paper_2301_05780_amd import pdd, workloads
+from oracle import mlp as omlp
+from oracle.geometry import Geometry
+from oracle.coeffs import Coefficients
+from oracle.assemble import assemble as oracle_assemble, to_csr
+from oracle.rbf import shape_for_condition, condition
+from parity import fetch, assert_within_se
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+def _geom(w):
+    return Geometry(w["domain"], w["H"], w["m"], w["ext"])
+
+
+def _with_shape(w, kappa):
+    """w with RBF interpolation, c chosen (by the oracle) so that the longest
+    stencil's matrix has condition number kappa."""
+    S = w["m"] + 2 * w["ext"] + 1
+    g = _geom(w)
+    S = min(S, g.L + 1)
+    c = shape_for_condition(S, g.dx, kappa)
+    return dict(w, interp="rbf", rbf_c=c), S, condition(np.arange(S) * g.dx, c)
+
+
+def _oracle(w, cv=None, lut=None):
+    g = _geom(w)
+    co = Coefficients(w["kind"], w.get("param", ()), lut=lut, lut_n=w.get("lut_n", 0), domain=w["domain"])
+    out = oracle_assemble(g, co, w["n_paths"], w["h"], w["seed"], instance=w.get("instance", 0),
+                          exit_rule=w["exit_rule"], cv=cv, interp=("rbf", w["rbf_c"]))
+    return g, to_csr(g, out["rows"])
+
+
+def _assert_rbf_same_stream(got, g, ref, S, kappa):
+    assert np.array_equal(got["row_ptr"], g.row_ptr) and np.array_equal(got["col_idx"], g.col_idx)
+    row_of = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    tol = (1e-12 + S * kappa * U) * ref["mass"]
+    dv = np.abs(got["val"] - ref["val"])
+    db = np.abs(got["b"] - ref["b"])
+    print(f"RBF same-stream: kappa {kappa:.2e}, worst G {np.max(dv / tol[row_of]):.3g} x bar, "
+          f"worst b {np.max(db / tol):.3g} x bar", flush=True)
+    assert np.all(dv <= tol[row_of]) and np.all(db <= tol)
+    assert np.array_equal(got["diag"][:, :6], ref["diag"][:, :6])
+    scale = np.max(np.abs(ref["diag"][:, 6:]))
+    assert np.allclose(got["diag"][:, 6:], ref["diag"][:, 6:], rtol=0, atol=(1e-11 + S * kappa * U) * scale)
+
+
+@pytest.mark.parametrize("rule,kappa", [("gm", 1e6), ("naive", 1e6), ("gm", 1e10)])
+def test_poisson_small_fp64_same_stream(ctx, rule, kappa):
+    w, S, k = _with_shape(workloads.poisson_small(rule), kappa)
+    g, ref = _oracle(w)
+    got = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    _assert_rbf_same_stream(got, g, ref, S, k)
+
+
+@pytest.mark.parametrize("kind,param", [("varcoef", ()), ("amplitude", (0.6,)), ("constsol", ())])
+def test_families_fp64_same_stream(ctx, kind, param):
+    w = dict(kind=kind, param=param, domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=200, h=1e-3,
+             seed=3, precision="fp64", exit_rule="gm")
+    w, S, k = _with_shape(w, 1e8)
+    g, ref = _oracle(w)
+    got = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    _assert_rbf_same_stream(got, g, ref, S, k)
+
+
+def test_stencil_reaching_both_boundary_ends(ctx):
+    """ext = m on two subdomains: side stencils span the whole line, both
+    boundary lattice points inside one stencil."""
+    w = dict(workloads.poisson_small("gm"), ext=8, n_paths=300, kind="varcoef")
+    w, S, k = _with_shape(w, 1e6)
+    g, ref = _oracle(w)
+    assert any(g.side(kk, o)["clo"] == 0 and g.side(kk, o)["chi"] == g.L and not g.side(kk, o)["boundary"]
+               for kk in range(g.n) for o in "ENWS")
+    got = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    _assert_rbf_same_stream(got, g, ref, S, k)
+
+
+def test_grad_table_cv_fp64_same_stream(ctx):
+    w = dict(workloads.poisson_small("gm"), n_paths=200, kind="varcoef", H=3, m=6, ext=3, h=2e-3)
+    w, S, k = _with_shape(w, 1e6)
+    n = 65
+    xs = np.arange(n) / (n - 1)
+    X, Y = np.meshgrid(xs, xs)
+    rng = np.random.default_rng(7)
+    th = (workloads.mlp_init(2) + rng.normal(0, 0.05, workloads.MLP_PARAMS)).astype(np.float32).astype(np.float64)
+    table = omlp.grad_input(th, np.stack([X.ravel(), Y.ravel()], axis=1)).reshape(n, n, 2).astype(np.float32)
+    spec = pdd.CVSpec("grad_lut", table=torch.from_numpy(table).cuda())
+    g, ref = _oracle(w, cv=omlp.GradLutCV(table, w["domain"]))
+    got = fetch(ctx.assemble(w, cv=spec), g)
+    ctx.sync()
+    _assert_rbf_same_stream(got, g, ref, S, k)
+
+
+@pytest.mark.parametrize("kappa", [1e6, 1e10])
+def test_varcoef_fp32_production_within_se(ctx, kappa):
+    w = dict(kind="varcoef", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=400, h=1e-3,
+             seed=1, precision="fp32", exit_rule="gm")
+    w, S, k = _with_shape(w, kappa)
+    g, ref = _oracle(w)
+    got = fetch(ctx.assemble(w), g)
+    ctx.sync()
+    assert_within_se(got, g, ref, nse=3.0, floor=1e-6 + S * k * U)
+
+
+def test_table_family_fp32_within_se(ctx):
+    tab = workloads.varied_lut(65)
+    w = dict(kind="lut", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=8, ext=4, n_paths=300, h=1e-3,
+             seed=2, precision="fp32", exit_rule="gm", lut_n=65)
+    w, S, k = _with_shape(w, 1e8)
+    g, ref = _oracle(w, lut=tab)
+    got = fetch(ctx.assemble(w, lut=torch.from_numpy(tab).cuda()), g)
+    ctx.sync()
+    assert_within_se(got, g, ref, nse=3.0, floor=1e-6 + S * k * U)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_same_paths_as_the_hat_assembly(ctx, precision):
+    """The interpolation acts after the exit: step totals and exit sides are
+    those of the hat assembly, bit for bit."""
+    w = dict(workloads.poisson_small("gm"), kind="amplitude", param=(0.3,), precision=precision, n_paths=500)
+    wr, _, _ = _with_shape(w, 1e8)
+    hat = ctx.assemble(w)["diag"].cpu().numpy().reshape(-1, pdd.DIAG_WIDTH)
+    rbf = ctx.assemble(wr)["diag"].cpu().numpy().reshape(-1, pdd.DIAG_WIDTH)
+    ctx.sync()
+    assert np.array_equal(hat[:, :6], rbf[:, :6])
+
+
+def test_rbf_arguments_and_unsupported_combinations(ctx):
+    w = workloads.poisson_small()
+    for bad in (dict(interp="rbf", rbf_c=0.0), dict(interp="rbf", rbf_c=-1.0), dict(interp="rbf", rbf_c=float("nan")),
+                dict(interp="rbf", rbf_c=1e3)):          # c = 1e3: matrices singular in float64
+        with pytest.raises(pdd.PddError) as e:
+            ctx.assemble(dict(w, **bad))
+        assert e.value.status == pdd.EINVAL
+    wr = dict(w, interp="rbf", rbf_c=0.1)
+    n = pdd.pattern(w)[0]
+    with pytest.raises(pdd.PddError) as e:
+        ctx.assemble(wr, u_ref=torch.zeros(n, dtype=torch.float64, device="cuda"))
+    assert e.value.status == pdd.EUNSUPPORTED
+    spec = pdd.CVSpec("network", params=torch.from_numpy(workloads.mlp_init(0).astype(np.float32)).cuda())
+    with pytest.raises(pdd.PddError) as e:
+        ctx.assemble(dict(wr, precision="fp32"), cv=spec)
+    assert e.value.status == pdd.EUNSUPPORTED
+    with pytest.raises(pdd.PddError) as e:
+        ctx.assemble_batch([wr, dict(wr, instance=1)])
+    assert e.value.status == pdd.EUNSUPPORTED
+    with pytest.raises(pdd.PddError) as e:
+        ctx.calibrate(wr, torch.zeros(n, dtype=torch.float64, device="cuda"), 16)
+    assert e.value.status == pdd.EUNSUPPORTED
+    # the context stays usable
+    out = ctx.assemble(wr)
+    ctx.sync()
+    assert np.all(np.isfinite(out["b"].cpu().numpy()))
