@@ -316,6 +316,42 @@ def phases(ctx, w, n0, eps, n_job, table=None):
     }
 
 
+def rbf_view(ctx, w, steps=5, target_cond=1e10):
+    """The paper's own interpolation on workload w beside the hat weights:
+    inverse-multiquadric cardinal functions on the extended side stencils
+    (Sec. 2.1), the shape parameter set so that the longest stencil's
+    interpolation matrix has condition number target_cond (Sec. 5.1).  Same
+    paths (same seed) for both; reports the assembly kernel's time, its
+    path-steps/s and the interface errors against u* of one solve each.
+    Default launch shape for both (no autotuning)."""
+    import numpy as np
+    from paper_2301_05780_amd import pdd
+    from oracle.coeffs import Coefficients     # the manufactured solution only
+    L = w["H"] * w["m"]
+    S = min(w["m"] + 2 * w["ext"] + 1, L + 1)
+    c = pdd.rbf_shape(S, (w["domain"][1] - w["domain"][0]) / L, target_cond)
+    xy = pdd.knot_xy(w)
+    ue = Coefficients(w["kind"], w.get("param", ())).exact(xy[:, 0], xy[:, 1])
+    res = {"stencil_points": S, "rbf_c": c, "condition_number": target_cond}
+    for name, ww in (("hat", w), ("rbf", dict(w, interp="rbf", rbf_c=c))):
+        out = ctx.assemble(ww)
+        ctx.sync()
+        ctx.set_timing(True)
+        for _ in range(steps):
+            ctx.assemble(ww, out=out)
+        ctx.sync()
+        ms, n = ctx.kernel_ms()
+        ctx.set_timing(False)
+        kms = ms / max(n, 1)
+        path_steps = float(out["diag"].view(-1, 8)[:, 0].sum().item())
+        u, _, _ = ctx.solve(out["row_ptr"], out["col_idx"], out["val"][:out["nnz"]], out["b"])
+        err = np.abs(u.cpu().numpy() - ue)
+        res[name] = {"kernel_ms": kms, "path_steps_per_s": path_steps / kms * 1e3,
+                     "rmse": float(np.sqrt(np.mean(err ** 2))), "max_error": float(err.max())}
+    res["kernel_time_ratio_rbf_to_hat"] = res["rbf"]["kernel_ms"] / res["hat"]["kernel_ms"]
+    return res
+
+
 # ---- runs ---------------------------------------------------------------------
 def tuned_single(ctx, w, lut=None, tune=True):
     """Assemble once (allocating the outputs and the context's caches), then,
@@ -432,6 +468,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv-compare", action="store_true")
+    ap.add_argument("--no-rbf", action="store_true", help="skip the RBF-interpolation view of the varcoef line")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the launch-shape autotuner before timing (on by default)")
@@ -518,6 +555,8 @@ def main():
                                          (10000, 5000, 2500, 1250, 625, 313)),
             }
             rec["phases"] = phases(ctx, workloads.varcoef("gm"), 1000, 0.01, 100, _TABLES.get("varcoef"))
+            if not args.no_rbf:
+                rec["rbf_interpolation"] = rbf_view(ctx, w)
         ctx.close()
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)

@@ -103,6 +103,19 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// 1 / sqrt(x) for x >= c^2 > 0 in float64: the hardware estimate refined by
+// two Newton steps for the reciprocal square root,
+// y <- y + y (1 - x y^2) / 2, each of which squares the relative error.
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
@@ -386,7 +399,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           double h0 = 0.0, hL = 0.0;
           for (int i = 0; i < S; ++i) {
             const double rr = (t - (double)(clo + i)) * da;
-            const double ph = 1.0 / sqrt(fma(rr, rr, P.rbf_c2));
+            const double ph = rsqrt_f64(fma(rr, rr, P.rbf_c2));
             lds_add(row + i, Yd * ph);
             if (b0) h0 = fma(Mi[i], ph, h0);
             if (bL) hL = fma(Ml[i], ph, hL);

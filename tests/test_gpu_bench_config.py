@@ -70,6 +70,33 @@ def test_varcoef_in_the_timed_configuration(ctx):
         ctx.set_spare_rows(-1)
 
 
+def test_varcoef_rbf_at_full_size(ctx):
+    """The RBF view of the benchmark: full varcoef size, default launch shape,
+    c at condition number 1e10 for the 33-point stencils; sampled rows
+    against the oracle's per-path cardinal weights within 3 standard errors
+    (plus S kappa u of the row mass for the conditioning)."""
+    w = workloads.varcoef()
+    c = pdd.rbf_shape(33, 1 / 128, 1e10)
+    wr = dict(w, interp="rbf", rbf_c=c)
+    out = ctx.assemble(wr)
+    ctx.sync()
+    got = _host(out)
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    assert np.array_equal(got["row_ptr"], g.row_ptr) and np.array_equal(got["col_idx"], g.col_idx)
+    assert np.all(np.isfinite(got["val"])) and np.all(np.isfinite(got["b"]))
+    n = g.n
+    knots = np.concatenate([[0, n - 1], np.random.default_rng(6).choice(n, 2, replace=False)])
+    ref = oracle_assemble(g, Coefficients("varcoef", ()), w["n_paths"], w["h"], w["seed"], exit_rule=w["exit_rule"],
+                          knots=knots, interp=("rbf", c))["rows"]
+    for k in knots:
+        r = ref[k]
+        a, e = g.row_ptr[k], g.row_ptr[k + 1]
+        floor = 1e-6 + 33 * 1e10 * 2.0 ** -53 * r["mass"]
+        assert np.all(np.abs(got["val"][a:e] - r["val"]) <= 3 * r["se_val"] + floor), k
+        assert abs(got["b"][k] - r["b"]) <= 3 * r["se_b"] + floor, k
+        assert abs(got["diag"][k, 0] / r["diag"][0] - 1.0) < 2e-3, k
+
+
 def test_large_lut_in_the_timed_configuration(ctx):
     w = workloads.large_lut()
     tab = workloads.poisson_lut(w["lut_n"])
