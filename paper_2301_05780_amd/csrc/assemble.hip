@@ -116,6 +116,36 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   return y;
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// One DPP step of a float64 wave reduction: each lane adds the value of
+// the lane the control selects (0 where the source lies outside the row or
+// the row is masked off).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+  return v + __hiloint2double(hi, lo);
+}
+
+// Sum of v over the 64 lanes, returned to every lane: shifts by 1, 2, 4
+// and 8 within each row of 16 lanes leave the row's sum in its lane 15; the
+// row broadcasts of lanes 15 and 31 then carry the four row sums into lane
+// 63, which is read out.  A fixed order, no LDS traffic.
+__device__ __forceinline__ double wave_total_dpp(double v) {
+  v = dpp_add_f64<0x111, 0xf>(v);    // row_shr:1
+  v = dpp_add_f64<0x112, 0xf>(v);    // row_shr:2
+  v = dpp_add_f64<0x114, 0xf>(v);    // row_shr:4
+  v = dpp_add_f64<0x118, 0xf>(v);    // row_shr:8
+  v = dpp_add_f64<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+  v = dpp_add_f64<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+  return readlane_f64(v, 63);
+}
+
 __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
@@ -344,6 +374,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       const bool valid = i < qn;
       int rb = 0, o = 0;
       double vb = 0.0, vs = 0.0, vk = 0.0;
+      int rkey = -1;                 // RBF: 4 buffer + side of an interface exit (-1: none)
+      double rt = 0.0, rY = 0.0;     // RBF: lattice coordinate of the exit point, Y
       if (valid) {
         ExitRec<R> r = Q[i];
         const uint32_t meta = Qm[i];
@@ -379,43 +411,14 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
             bp = bp + r.Y * gv;
           }
         } else if constexpr (RBF) {
-          // interface side, RBF cardinal interpolation: Y phi_c(|z - z_q|)
-          // into the slot of every stencil point q (the weights Phi^{-1} phi
-          // are applied once per row, after the sums).  float64 throughout:
-          // the interpolation matrix is ill-conditioned by design.  The
-          // stencil's boundary lattice points (q = 0, q = L) take their
-          // cardinal weight H_q(z) = (Phi^{-1} phi(z))_q times g into b here,
-          // so the per-path score stays whole.
-          const int clo = d.clo[o], chi = d.chi[o];
-          const int S = chi - clo + 1;
-          const double da = vert ? G.dy : G.dx;
+          // interface side, RBF: the exit's lattice coordinate on the line,
+          // clamped to the stencil; its contributions are summed below, one
+          // group of exits sharing a row side at a time
           const double a0 = vert ? (double)G.y0 : (double)G.x0;
-          const double t = fmin(fmax(((double)along - a0) / da, (double)clo), (double)chi);
-          const double* Mi = P.rbf_inv + (vert ? P.rbf_half : 0) + rbf_block_offset(S);
-          const double* Ml = Mi + (size_t)(S - 1) * S;
-          double* row = wrows + (size_t)row_of(rb, W) * RL + o * SL;
-          const double Yd = (double)r.Y;
-          const bool b0 = clo == 0, bL = chi == G.L;
-          double h0 = 0.0, hL = 0.0;
-          for (int i = 0; i < S; ++i) {
-            const double rr = (t - (double)(clo + i)) * da;
-            const double ph = rsqrt_f64(fma(rr, rr, P.rbf_c2));
-            lds_add(row + i, Yd * ph);
-            if (b0) h0 = fma(Mi[i], ph, h0);
-            if (bL) hL = fma(Ml[i], ph, hL);
-          }
-          for (int e = 0; e < 2; ++e) {
-            if (!(e ? bL : b0)) continue;
-            const int q = e ? chi : clo;
-            const R qc = vert ? G.y0 + (R)q * (R)G.dy : G.x0 + (R)q * (R)G.dx;
-            const R gv = vert ? g_at<KIND>(lpos, qc) : g_at<KIND>(qc, lpos);
-            R c;
-            {
-#pragma clang fp contract(off)
-              c = r.Y * (R)(e ? hL : h0);
-              bp = bp + c * gv;
-            }
-          }
+          const double da = vert ? G.dy : G.dx;
+          rt = fmin(fmax(((double)along - a0) / da, (double)d.clo[o]), (double)d.chi[o]);
+          rY = (double)r.Y;
+          rkey = 4 * rb + o;
         } else {
           // interface side: hat weights on the line lattice, clamped to the stencil range
           const int clo = d.clo[o], chi = d.chi[o];
@@ -456,6 +459,93 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         vb = (double)bp;
         vs = vb + (double)uref;
         vk = (double)(meta & 0xFFFFFFu);
+      }
+      if constexpr (RBF) {
+        // RBF cardinal interpolation, one group of exits with the same row
+        // and side at a time, lanes across the side's stencil points: lane q
+        // sums Y phi_c(|z - z_q|) over the group's exits and adds the sum to
+        // the row's slot once (the weights Phi^{-1} phi are applied at the
+        // row flush).  float64 throughout: the interpolation matrix is
+        // ill-conditioned by design.  The stencil's boundary lattice points
+        // (q = 0, q = L) take each exit's cardinal weight H_q(z) =
+        // (Phi^{-1} phi(z))_q, a sum across the lanes, times g into b.
+        constexpr int RU = 2;          // exits per pass of the group loop
+        double hb = 0.0;               // this lane's exit: sum over the boundary points q of H_q(z) g(z_q)
+        uint64_t todo = __ballot(rkey >= 0);
+        while (todo) {
+          const int key = __builtin_amdgcn_readlane(rkey, __builtin_ctzll(todo));
+          const uint64_t grp = __ballot(rkey == key);
+          todo &= ~grp;
+          const int gb = key >> 2, go = key & 3;
+          const WB& W = B[gb];
+          const KnotDesc& d = W.d;
+          const GeoView<R> Gg = geo(W);
+          const bool vert = (go == 0 || go == 2);
+          const int clo = d.clo[go], chi = d.chi[go], S = chi - clo + 1;
+          const double da = vert ? Gg.dy : Gg.dx;
+          const bool b0 = clo == 0, bL = chi == Gg.L;
+          const double* Mi = P.rbf_inv + (vert ? P.rbf_half : 0) + rbf_block_offset(S);
+          double* row = wrows + (size_t)row_of(gb, W) * RL + go * SL;
+          // g at the stencil's boundary points (q = 0, q = L)
+          const R lpos = (R)d.line[go];
+          auto g_end = [&](int q) __attribute__((always_inline)) -> double {
+            const R qc = vert ? Gg.y0 + (R)q * (R)Gg.dy : Gg.x0 + (R)q * (R)Gg.dx;
+            return (double)(vert ? g_at<KIND>(lpos, qc) : g_at<KIND>(qc, lpos));
+          };
+          const double g0 = b0 ? g_end(clo) : 0.0, gL = bL ? g_end(chi) : 0.0;
+          for (int c0 = 0; c0 < S; c0 += 64) {
+            const int si = c0 + lane;
+            const bool in = si < S;
+            const double q = (double)(clo + si);
+            // rows 0 and S-1 of Phi^{-1} weighted by the boundary data
+            double wb = 0.0;
+            if (b0 && in) wb = Mi[si] * g0;
+            if (bL && in) wb = fma(Mi[(size_t)(S - 1) * S + si], gL, wb);
+            double acc = 0.0;
+            uint64_t m = grp;
+            // two exits per pass (independent chains; a missing one takes
+            // Y = 0 and the first one's coordinate), added in exit order
+            while (m) {
+              int e[RU];
+              bool has[RU];
+              e[0] = __builtin_ctzll(m);
+              has[0] = true;
+              m &= m - 1;
+#pragma unroll
+              for (int u = 1; u < RU; ++u) {
+                has[u] = m != 0;
+                e[u] = has[u] ? __builtin_ctzll(m) : e[0];
+                m &= m - 1;
+              }
+              double ph[RU];
+#pragma unroll
+              for (int u = 0; u < RU; ++u) {
+                const double rr = (readlane_f64(rt, e[u]) - q) * da;
+                ph[u] = rsqrt_f64(fma(rr, rr, P.rbf_c2));
+              }
+#pragma unroll
+              for (int u = 0; u < RU; ++u) acc = fma(has[u] ? readlane_f64(rY, e[u]) : 0.0, ph[u], acc);
+              if (b0 || bL) {
+                double t[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) t[u] = wave_total_dpp(wb * ph[u]);
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                  if (has[u] && lane == e[u]) hb += t[u];
+                }
+              }
+            }
+            if (in) lds_add(row + si, acc);
+          }
+        }
+        if (rkey >= 0) {
+          // Y times the boundary points' cardinal weights and data, into b
+          {
+#pragma clang fp contract(off)
+            vb = vb + rY * hb;
+          }
+          vs = vb;
+        }
       }
       // row extras: b, sum s, sum s^2 and sum K through LDS atomics (the LDS
       // pipe serialises the same-address lanes; no VALU reduction needed),
