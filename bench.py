@@ -352,6 +352,71 @@ def rbf_view(ctx, w, steps=5, target_cond=1e10):
     return res
 
 
+def sec5_experiment(ctx, seed=0):
+    """The paper's numerical experiment (Sec. 5, eqs. 42-43) on one GPU, its
+    three phases as in Sec. 4.3: Phase I, the warm-up assembly with N0 = 1000
+    paths per knot at h0 = 0.08 (RBF interpolation, float32 paths) and its
+    solve; Phase II, the calibration with N0' = 1000 mixed GM/EM paths per
+    knot scored with the warm-up solution (u0 interpolated with hat weights,
+    no control variate: rho^2 = 0); Phase III, the production assembly with
+    the per-knot path counts of eq. 41 and the smallest h_i of eq. 40.
+    Reports each phase's kernel time and path-steps and the interface errors
+    against u* (the paper prints Phase I RMSE 0.016, max 0.074 and Phase III
+    RMSE 0.0044, max 0.0224)."""
+    import numpy as np
+    import torch
+    from paper_2301_05780_amd import pdd, workloads
+    from oracle.coeffs import Coefficients     # the manufactured solution only
+    w = workloads.sec5()
+    L = w["H"] * w["m"]
+    S = min(w["m"] * 2 + 2 * w["ext"] + 1, L + 1)
+    dx = (w["domain"][1] - w["domain"][0]) / L
+    w = dict(w, rbf_c=pdd.rbf_shape(S, dx, w["rbf_condition"]), seed=seed)
+    xy = pdd.knot_xy(w)
+    ue = Coefficients("eq43").exact(xy[:, 0], xy[:, 1])
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        r = fn()
+        e1.record(ctx.stream)
+        e1.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    def errors(out):
+        u, it, rr = ctx.solve(out["row_ptr"], out["col_idx"], out["val"][:out["nnz"]], out["b"])
+        err = np.abs(u.cpu().numpy() - ue)
+        return u, {"rmse": float(np.sqrt(np.mean(err ** 2))), "max_error": float(err.max()),
+                   "fraction_within_eps": float(np.mean(err < w["eps"])), "solver_iterations": it}
+
+    ctx.assemble(w)                                    # caches (stencil inverses, tickets)
+    out1, ms1 = timed(lambda: ctx.assemble(w))
+    steps1 = float(out1["diag"].view(-1, 8)[:, 0].sum().item())
+    u0, e1 = errors(out1)
+    wh = dict(w, interp="hat")
+    stats, ms2 = timed(lambda: ctx.calibrate(wh, u0, w["n_paths"], seed=seed + 1))
+    st = stats.cpu().numpy()
+    pl = pdd.calibration_plan(st, w["n_paths"], w["h"], w["eps"], w["n_job"])
+    h3 = float(pl["h"].min())
+    w3 = dict(w, h=h3, seed=seed + 2)
+    ctx.assemble(w3, n_paths_per_knot=pl["n_paths"])   # caches for the new path counts
+    out3, ms3 = timed(lambda: ctx.assemble(w3, n_paths_per_knot=pl["n_paths"]))
+    steps3 = float(out3["diag"].view(-1, 8)[:, 0].sum().item())
+    _, e3 = errors(out3)
+    return {
+        "workload": ("Lap u = f on [-100,100]^2, u* of eq. 43, 10x10 subdomains, 63 lattice intervals per "
+                     f"subdomain side, stencils widened by {w['ext']}, {len(ue)} knots, RBF c = {w['rbf_c']:.4g} "
+                     f"(condition number {w['rbf_condition']:.0e} at {S} points)"),
+        "phase1": dict(e1, n_paths=w["n_paths"], h=w["h"], gpu_ms=ms1, path_steps=steps1,
+                       path_steps_per_s=steps1 / ms1 * 1e3),
+        "phase2": {"gpu_ms": ms2, "path_steps": float(st[:, 7].sum()), "mean_bias_bound": float(pl["bias"].mean()),
+                   "knots_with_h_below_h0": int(np.sum(pl["h"] < w["h"])), "h_min": h3,
+                   "paths_total": int(pl["n_paths"].sum()), "paths_median": float(np.median(pl["n_paths"]))},
+        "phase3": dict(e3, h=h3, gpu_ms=ms3, path_steps=steps3, path_steps_per_s=steps3 / ms3 * 1e3),
+        "paper": {"phase1": {"rmse": 0.016, "max_error": 0.074}, "phase3": {"rmse": 0.0044, "max_error": 0.0224}},
+    }
+
+
 # ---- runs ---------------------------------------------------------------------
 def tuned_single(ctx, w, lut=None, tune=True):
     """Assemble once (allocating the outputs and the context's caches), then,
@@ -557,6 +622,7 @@ def main():
             rec["phases"] = phases(ctx, workloads.varcoef("gm"), 1000, 0.01, 100, _TABLES.get("varcoef"))
             if not args.no_rbf:
                 rec["rbf_interpolation"] = rbf_view(ctx, w)
+                rec["sec5_experiment"] = sec5_experiment(ctx)
         ctx.close()
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)

@@ -65,14 +65,17 @@ typedef struct pdd_ctx pdd_ctx;
  *              the shift; the exact shift uses a_nn at the projection.
  *   CONSTSOL   sigma, d, c of VARCOEF, f = c, g = 1 (u = 1 is the solution)
  *   EXITTIME   sigma = sqrt(2) I, d = 0, c = 0, f = -1, g = 0 (u = mean exit
- *              time, eq. 26) */
+ *              time, eq. 26)
+ *   EQ43       the Poisson problem of the Sec. 5 experiment (eq. 42): sigma =
+ *              sqrt(2) I, d = 0, c = 0, u* of eq. 43, f = Lap u*, g = u* */
 enum {
   PDD_COEF_POISSON = 0,
   PDD_COEF_VARCOEF = 1,
   PDD_COEF_AMPLITUDE = 2,
   PDD_COEF_LUT = 3,
   PDD_COEF_CONSTSOL = 4,
-  PDD_COEF_EXITTIME = 5
+  PDD_COEF_EXITTIME = 5,
+  PDD_COEF_EQ43 = 6
 };
 enum { PDD_LUT_STRIDE = 8 };
 

@@ -18,6 +18,8 @@ Families (all on the unit square in the workloads that use them):
   constsol   sigma, d, c of varcoef, f = c, g = 1, so that u = 1 solves (6)
   exittime   sigma = sqrt(2) I, d = 0, c = 0, f = -1, g = 0: u is the mean exit
              time of eq. (26)
+  eq43       the Poisson problem of the Sec. 5 experiment (eq. 42, Lap u = f):
+             sigma = sqrt(2) I, d = 0, c = 0, u* of eq. 43, f = Lap u*, g = u*
 
 f = L u* is written out by hand for each manufactured family; the tests check
 it against finite differences of u* through the operator of (6).
@@ -34,6 +36,41 @@ def _u_poisson(x, y):
     return np.sin(PI * x) * np.sin(PI * y) + x * x * y
 
 
+def _u_eq43(x, y):
+    """Eq. 43: 3 + sin(sqrt(1 + x^2/100 + y^2/50))/3 + tanh(sin(3x/25 + y/20) + sin(x/20 - 3y/25))/3."""
+    r = np.sqrt(1.0 + x * x / 100.0 + y * y / 50.0)
+    s = np.sin(3.0 * x / 25.0 + y / 20.0) + np.sin(x / 20.0 - 3.0 * y / 25.0)
+    return 3.0 + np.sin(r) / 3.0 + np.tanh(s) / 3.0
+
+
+def _grad_eq43(x, y):
+    r = np.sqrt(1.0 + x * x / 100.0 + y * y / 50.0)
+    a, b = 3.0 * x / 25.0 + y / 20.0, x / 20.0 - 3.0 * y / 25.0
+    sech2 = 1.0 - np.tanh(np.sin(a) + np.sin(b)) ** 2
+    ux = np.cos(r) * x / (100.0 * r) + sech2 * (3.0 / 25.0 * np.cos(a) + np.cos(b) / 20.0)
+    uy = np.cos(r) * y / (50.0 * r) + sech2 * (np.cos(a) / 20.0 - 3.0 / 25.0 * np.cos(b))
+    return ux / 3.0, uy / 3.0
+
+
+def _lap_eq43(x, y):
+    """Laplacian of eq. 43, differentiated by hand term by term."""
+    r = np.sqrt(1.0 + x * x / 100.0 + y * y / 50.0)
+    rx, ry = x / (100.0 * r), y / (50.0 * r)
+    # d2 r/dx2 + d2 r/dy2
+    rxx = 1.0 / (100.0 * r) - x * x / (100.0 ** 2 * r ** 3)
+    ryy = 1.0 / (50.0 * r) - y * y / (50.0 ** 2 * r ** 3)
+    lap_sin_r = np.cos(r) * (rxx + ryy) - np.sin(r) * (rx * rx + ry * ry)
+    a, b = 3.0 * x / 25.0 + y / 20.0, x / 20.0 - 3.0 * y / 25.0
+    s = np.sin(a) + np.sin(b)
+    sx = 3.0 / 25.0 * np.cos(a) + np.cos(b) / 20.0
+    sy = np.cos(a) / 20.0 - 3.0 / 25.0 * np.cos(b)
+    sxx = -(3.0 / 25.0) ** 2 * np.sin(a) - (1.0 / 20.0) ** 2 * np.sin(b)
+    syy = -(1.0 / 20.0) ** 2 * np.sin(a) - (3.0 / 25.0) ** 2 * np.sin(b)
+    t = np.tanh(s)
+    lap_tanh_s = (1.0 - t * t) * (sxx + syy) - 2.0 * t * (1.0 - t * t) * (sx * sx + sy * sy)
+    return (lap_sin_r + lap_tanh_s) / 3.0
+
+
 class Coefficients:
     """Pointwise coefficients of one BVP instance, float64 in and out."""
 
@@ -45,7 +82,7 @@ class Coefficients:
             tab = np.asarray(lut, dtype=np.float32).reshape(lut_n, lut_n, LUT_STRIDE)
             self.lut = tab.astype(np.float64)        # float32 table promoted to float64
             self.lut_n = int(lut_n)
-        elif kind not in ("poisson", "varcoef", "amplitude", "constsol", "exittime"):
+        elif kind not in ("poisson", "varcoef", "amplitude", "constsol", "exittime", "eq43"):
             raise ValueError(kind)
 
     # --- bilinear read of the node-centred table ---------------------------
@@ -67,7 +104,7 @@ class Coefficients:
     def sigma(self, x, y):
         """Symmetric diffusion matrix entries (sxx, sxy, syy)."""
         z = np.zeros_like(x)
-        if self.kind in ("poisson", "exittime"):
+        if self.kind in ("poisson", "exittime", "eq43"):
             s = np.full_like(x, np.sqrt(2.0))
             return s, z, s.copy()
         if self.kind in ("varcoef", "constsol"):
@@ -115,6 +152,8 @@ class Coefficients:
             return -(1.0 + x * x)
         if k == "exittime":
             return np.full_like(x, -1.0)
+        if k == "eq43":
+            return _lap_eq43(x, y)
         return self._lut(x, y)[..., 6]
 
     def boundary(self, x, y):
@@ -133,6 +172,8 @@ class Coefficients:
             return np.exp(x) * np.cos(2 * y)
         if self.kind == "constsol":
             return np.ones_like(x)
+        if self.kind == "eq43":
+            return _u_eq43(x, y)
         return None
 
     def grad_exact(self, x, y):
@@ -142,6 +183,8 @@ class Coefficients:
                     PI * np.sin(PI * x) * np.cos(PI * y) + x * x)
         if self.kind == "varcoef":
             return np.exp(x) * np.cos(2 * y), -2 * np.exp(x) * np.sin(2 * y)
+        if self.kind == "eq43":
+            return _grad_eq43(x, y)
         return np.zeros_like(x), np.zeros_like(x)
 
     def normal_diffusion(self, x, y, line):

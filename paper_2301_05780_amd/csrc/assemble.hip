@@ -940,6 +940,7 @@ const void* pick_kind(int kind) {
     case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64, CV>();
     case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64, CV>();
     case PDD_COEF_LUT: return kernel_ptr<PDD_COEF_LUT, F64, CV>();
+    case PDD_COEF_EQ43: return kernel_ptr<PDD_COEF_EQ43, F64, CV>();
     default: break;
   }
   if constexpr (CV == PDD_CV_NONE) {
@@ -966,6 +967,7 @@ const void* pick_rbf_kind(int kind) {
     case PDD_COEF_VARCOEF: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_VARCOEF, F64, CV>);
     case PDD_COEF_AMPLITUDE: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_AMPLITUDE, F64, CV>);
     case PDD_COEF_LUT: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_LUT, F64, CV>);
+    case PDD_COEF_EQ43: return reinterpret_cast<const void*>(&k_assemble_rbf<PDD_COEF_EQ43, F64, CV>);
     default: break;
   }
   if constexpr (CV == PDD_CV_NONE) {

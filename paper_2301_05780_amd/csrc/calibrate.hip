@@ -185,6 +185,7 @@ hipError_t launch_prec(const CalArgs& C, bool cv, hipStream_t stream) {
     case PDD_COEF_AMPLITUDE: return launch_kind<PDD_COEF_AMPLITUDE, F64>(C, cv, stream);
     case PDD_COEF_LUT: return launch_kind<PDD_COEF_LUT, F64>(C, cv, stream);
     case PDD_COEF_CONSTSOL: return launch_kind<PDD_COEF_CONSTSOL, F64>(C, cv, stream);
+    case PDD_COEF_EQ43: return launch_kind<PDD_COEF_EQ43, F64>(C, cv, stream);
     default: return launch_kind<PDD_COEF_EXITTIME, F64>(C, cv, stream);
   }
 }

@@ -138,6 +138,7 @@ hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot,
     case PDD_COEF_AMPLITUDE: hipLaunchKernelGGL(k_collect<PDD_COEF_AMPLITUDE>, dim3(grid), dim3(BLK), 0, stream, C); break;
     case PDD_COEF_LUT: hipLaunchKernelGGL(k_collect<PDD_COEF_LUT>, dim3(grid), dim3(BLK), 0, stream, C); break;
     case PDD_COEF_CONSTSOL: hipLaunchKernelGGL(k_collect<PDD_COEF_CONSTSOL>, dim3(grid), dim3(BLK), 0, stream, C); break;
+    case PDD_COEF_EQ43: hipLaunchKernelGGL(k_collect<PDD_COEF_EQ43>, dim3(grid), dim3(BLK), 0, stream, C); break;
     default: hipLaunchKernelGGL(k_collect<PDD_COEF_EXITTIME>, dim3(grid), dim3(BLK), 0, stream, C); break;
   }
   return hipGetLastError();

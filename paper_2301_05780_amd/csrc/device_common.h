@@ -150,6 +150,38 @@ __device__ __forceinline__ void lut_fetch(const CoefParams& cp, float x, float y
   o.f = bl(a1.z, b1.z, c1.z, d1.z);
 }
 
+// The manufactured solution of the Sec. 5 experiment (eq. 43),
+//   u = 3 + sin(r) / 3 + tanh(s) / 3,  r = sqrt(1 + x^2/100 + y^2/50),
+//   s = sin(3x/25 + y/20) + sin(x/20 - 3y/25),
+// and its Laplacian, the source of eq. 42: with T = tanh s,
+//   Lap sin(r) = cos(r) Lap r - sin(r) |grad r|^2,
+//   Lap r = 1/(100 r) + 1/(50 r) - (x/100)^2/r^3 - (y/50)^2/r^3,
+//   Lap tanh(s) = (1 - T^2) (Lap s - 2 T |grad s|^2),  Lap s = -(9/625 + 1/400) s.
+template <typename R>
+__device__ __forceinline__ R eq43_u(R x, R y) {
+#pragma clang fp contract(off)
+  const R r = sqrt((R)1 + x * x / (R)100 + y * y / (R)50);
+  const R s = sin((R)3 * x / (R)25 + y / (R)20) + sin(x / (R)20 - (R)3 * y / (R)25);
+  return (R)3 + sin(r) / (R)3 + tanh(s) / (R)3;
+}
+
+template <typename R>
+__device__ __forceinline__ R eq43_laplacian(R x, R y) {
+#pragma clang fp contract(off)
+  const R r = sqrt((R)1 + x * x / (R)100 + y * y / (R)50);
+  const R rx = x / ((R)100 * r), ry = y / ((R)50 * r);
+  const R lap_r = (R)1 / ((R)100 * r) + (R)1 / ((R)50 * r) - (rx * rx + ry * ry) / r;
+  const R lap_a = cos(r) * lap_r - sin(r) * (rx * rx + ry * ry);
+  const R al = (R)3 * x / (R)25 + y / (R)20, be = x / (R)20 - (R)3 * y / (R)25;
+  const R sa = sin(al), sb = sin(be), ca = cos(al), cb = cos(be);
+  const R s = sa + sb;
+  const R sx = (R)3 / (R)25 * ca + cb / (R)20, sy = ca / (R)20 - (R)3 / (R)25 * cb;
+  const R lap_s = -((R)9 / (R)625 + (R)1 / (R)400) * s;
+  const R T = tanh(s);
+  const R lap_b = ((R)1 - T * T) * (lap_s - (R)2 * T * (sx * sx + sy * sy));
+  return (lap_a + lap_b) / (R)3;
+}
+
 // Coefficients at (x, y).  float64 versions mirror the CPU definition's
 // expression order; float32 versions use the transcendental units.
 template <int KIND>
@@ -178,6 +210,10 @@ __device__ __forceinline__ void coef_at(const CoefParams& cp, double x, double y
     } else {
       o.f = -(1.0 + x * x);
     }
+  } else if constexpr (KIND == PDD_COEF_EQ43) {
+    o.sxx = sqrt(2.0); o.sxy = 0.0; o.syy = sqrt(2.0);
+    o.dx = 0.0; o.dy = 0.0; o.c = 0.0;
+    o.f = eq43_laplacian(x, y);
   } else if constexpr (KIND == PDD_COEF_AMPLITUDE) {
     const double a = cp.a;
     const double s2px = sin(2.0 * kPi * x), c2py = cos(2.0 * kPi * y);
@@ -219,6 +255,10 @@ __device__ __forceinline__ void coef_at(const CoefParams& cp, float x, float y, 
     } else {
       o.f = -(1.0f + x * x);
     }
+  } else if constexpr (KIND == PDD_COEF_EQ43) {
+    o.sxx = 1.41421356237f; o.sxy = 0.0f; o.syy = 1.41421356237f;
+    o.dx = 0.0f; o.dy = 0.0f; o.c = 0.0f;
+    o.f = eq43_laplacian(x, y);
   } else if constexpr (KIND == PDD_COEF_AMPLITUDE) {
     const float a = (float)cp.a;
     const float s2px = sin_rev(x), c2py = cos_rev(y);
@@ -238,14 +278,16 @@ __device__ __forceinline__ void coef_at(const CoefParams& cp, float x, float y, 
 template <int KIND>
 __device__ __forceinline__ double g_at(double x, double y) {
 #pragma clang fp contract(off)
-  if constexpr (KIND == PDD_COEF_VARCOEF) return exp(x) * cos(2.0 * y);
+  if constexpr (KIND == PDD_COEF_EQ43) return eq43_u(x, y);
+  else if constexpr (KIND == PDD_COEF_VARCOEF) return exp(x) * cos(2.0 * y);
   else if constexpr (KIND == PDD_COEF_CONSTSOL) return 1.0;
   else if constexpr (KIND == PDD_COEF_EXITTIME) return 0.0;
   else return sin(kPi * x) * sin(kPi * y) + x * x * y;
 }
 template <int KIND>
 __device__ __forceinline__ float g_at(float x, float y) {
-  if constexpr (KIND == PDD_COEF_VARCOEF) return fexp(x) * cos_rev(y * 0.3183098861837907f);
+  if constexpr (KIND == PDD_COEF_EQ43) return eq43_u(x, y);
+  else if constexpr (KIND == PDD_COEF_VARCOEF) return fexp(x) * cos_rev(y * 0.3183098861837907f);
   else if constexpr (KIND == PDD_COEF_CONSTSOL) return 1.0f;
   else if constexpr (KIND == PDD_COEF_EXITTIME) return 0.0f;
   else return sin_rev(0.5f * x) * sin_rev(0.5f * y) + x * x * y;

@@ -22,7 +22,7 @@ pdd_status bad(pdd_ctx* ctx, pdd_status st, const char* msg) {
 }  // namespace
 
 pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
-  if (c.kind < PDD_COEF_POISSON || c.kind > PDD_COEF_EXITTIME)
+  if (c.kind < PDD_COEF_POISSON || c.kind > PDD_COEF_EQ43)
     return bad(ctx, PDD_EINVAL, "coeffs.kind: unknown coefficient family");
   if (c.kind == PDD_COEF_AMPLITUDE && !(c.param[0] >= 0.0 && c.param[0] < 1.0))
     return bad(ctx, PDD_EINVAL, "coeffs.param[0]: amplitude must lie in [0, 1)");
@@ -52,7 +52,7 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
     if (cv.mode == PDD_CV_GRAD_LUT && (!cv.grad_lut || cv.lut_n < 2 || cv.lut_n > 65536))
       return bad(ctx, PDD_EINVAL, "run.cv: grad-table mode needs a table and 2 <= lut_n <= 65536");
     if (cv.mode != PDD_CV_NONE && (c.kind == PDD_COEF_CONSTSOL || c.kind == PDD_COEF_EXITTIME))
-      return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variates are built for the poisson, varcoef, amplitude and LUT families");
+      return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variates are built for the poisson, varcoef, amplitude, LUT and eq43 families");
   }
   return PDD_OK;
 }

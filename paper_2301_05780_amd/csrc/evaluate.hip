@@ -187,6 +187,7 @@ hipError_t launch_kind(const EvalArgs& A, unsigned grid, hipStream_t stream) {
     case PDD_COEF_AMPLITUDE: hipLaunchKernelGGL((k_eval<PDD_COEF_AMPLITUDE, F64>), dim3(grid), dim3(BLK), 0, stream, A); break;
     case PDD_COEF_LUT: hipLaunchKernelGGL((k_eval<PDD_COEF_LUT, F64>), dim3(grid), dim3(BLK), 0, stream, A); break;
     case PDD_COEF_CONSTSOL: hipLaunchKernelGGL((k_eval<PDD_COEF_CONSTSOL, F64>), dim3(grid), dim3(BLK), 0, stream, A); break;
+    case PDD_COEF_EQ43: hipLaunchKernelGGL((k_eval<PDD_COEF_EQ43, F64>), dim3(grid), dim3(BLK), 0, stream, A); break;
     default: hipLaunchKernelGGL((k_eval<PDD_COEF_EXITTIME, F64>), dim3(grid), dim3(BLK), 0, stream, A); break;
   }
   return hipGetLastError();

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EUNSUPPORTED = range(6)
-KIND = {"poisson": 0, "varcoef": 1, "amplitude": 2, "lut": 3, "constsol": 4, "exittime": 5}
+KIND = {"poisson": 0, "varcoef": 1, "amplitude": 2, "lut": 3, "constsol": 4, "exittime": 5, "eq43": 6}
 PRECISION = {"fp64": 0, "fp32": 1}
 EXIT = {"naive": 0, "gm": 1}
 CV_MODE = {"none": 0, "network": 1, "grad_lut": 2}

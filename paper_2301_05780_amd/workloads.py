@@ -49,6 +49,19 @@ def large_lut(exit_rule="gm"):
                 exit_rule=exit_rule, lut_n=4096)
 
 
+def sec5(exit_rule="gm"):
+    """The numerical experiment of Sec. 5 at one-GPU scale: Lap u = f on
+    [-100, 100]^2 with the solution of eq. 43, 10 x 10 subdomains, 64 knots
+    per interface counted with the two crossings (63 lattice intervals per
+    subdomain side), side stencils widened by half a segment (32 lattice
+    units) each way, RBF interpolation with the shape parameter at condition
+    number 1e10 for the longest stencil; Phase I with h0 = 0.08 and
+    N0 = 1000, target precision eps = 0.01, N_job = 200."""
+    return dict(name="sec5", kind="eq43", param=(), domain=(-100.0, 100.0, -100.0, 100.0),
+                H=10, m=63, ext=32, n_paths=1000, h=0.08, seed=0, precision="fp32",
+                exit_rule=exit_rule, interp="rbf", rbf_condition=1e10, eps=0.01, n_job=200)
+
+
 def batched(seed=0, n_instances=64):
     """Instance draws of the batched workload (NumPy PCG64, ``seed``)."""
     rng = np.random.Generator(np.random.PCG64(seed))

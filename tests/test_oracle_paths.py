@@ -44,6 +44,25 @@ def test_source_is_operator_of_exact_solution(kind, param):
     assert np.allclose(c.source(x, y), Lu, rtol=1e-5, atol=1e-5)
 
 
+def test_eq43_source_and_gradient_by_finite_differences():
+    """The Sec. 5 problem: f = Lap u* (eq. 42) and grad u* by central
+    differences of eq. 43 over the domain [-100, 100]^2."""
+    c = Coefficients("eq43")
+    rng = np.random.default_rng(6)
+    x, y = rng.uniform(-100, 100, 200), rng.uniform(-100, 100, 200)
+    e = 1e-2
+    u = c.exact
+    lap = (u(x + e, y) + u(x - e, y) + u(x, y + e) + u(x, y - e) - 4 * u(x, y)) / e ** 2
+    assert np.allclose(c.source(x, y), lap, rtol=0, atol=2e-7)
+    gx, gy = c.grad_exact(x, y)
+    assert np.allclose(gx, (u(x + e, y) - u(x - e, y)) / (2 * e), atol=2e-7)
+    assert np.allclose(gy, (u(x, y + e) - u(x, y - e)) / (2 * e), atol=2e-7)
+    # the generator of sigma = sqrt(2) I is the Laplacian: eq. 42 as written
+    sxx, sxy, syy = c.sigma(x, y)
+    assert np.allclose(0.5 * sxx * sxx, 1.0) and np.all(sxy == 0) and np.allclose(0.5 * syy * syy, 1.0)
+    assert np.all(c.boundary(x, y) == u(x, y)) and np.all((u(x, y) > 2.3) & (u(x, y) < 3.7))
+
+
 def test_mean_exit_time_series_and_gm_order():
     """h E[K] -> E[tau] of eq. (26).  With the exit-time family, b_k = h E[K]
     exactly (f = -1, g = 0).  Gobet-Menozzi (first order) sits within 3 SE
