@@ -159,6 +159,9 @@ typedef struct pdd_run {
   int32_t interp;                  /* PDD_INTERP_HAT (0) | PDD_INTERP_RBF_IMQ: interface-side interpolation */
   double rbf_c;                    /* RBF_IMQ: shape parameter c > 0 of phi_c(r) = 1 / sqrt(r^2 + c^2),
                                       in domain units (pdd_rbf_shape picks it by condition number) */
+  const double* h_per_knot;        /* host, length n, nullable: per-knot time steps h_i (eq. 40), each
+                                      finite and > 0, used for knot i's paths instead of h (pdd_assemble
+                                      only; PDD_EUNSUPPORTED elsewhere) */
 } pdd_run;
 
 /* ---- context ------------------------------------------------------------- */

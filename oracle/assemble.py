@@ -299,17 +299,19 @@ def assemble(geom, coef, n_paths, h, seed, instance=0, exit_rule="gm", cv=None,
              u_ref=None, knots=None, keep_paths=False, interp=None):
     """Assemble the rows of G and entries of b for the given knots (all by default).
 
-    n_paths: int, or per-knot array of length geom.n.  interp: None for the
-    hat weights, ("rbf", c) for the inverse-multiquadric cardinal weights.
+    n_paths: int, or per-knot array of length geom.n; h likewise (the knot's
+    own time step h_i of eq. 40).  interp: None for the hat weights,
+    ("rbf", c) for the inverse-multiquadric cardinal weights.
     Returns dict(rows={k: knot_row(...)}, and the per-path records if keep_paths).
     """
     if exit_rule not in ("naive", "gm"):
         raise ValueError(exit_rule)
     ks = range(geom.n) if knots is None else [int(k) for k in knots]
     npk = np.broadcast_to(np.asarray(n_paths, dtype=np.int64), (geom.n,))
+    hk = np.broadcast_to(np.asarray(h, dtype=np.float64), (geom.n,))
     rows, paths = {}, {}
     for k in ks:
-        rec = integrate_knot(geom, coef, k, npk[k], h, seed, instance, exit_rule, cv)
+        rec = integrate_knot(geom, coef, k, npk[k], float(hk[k]), seed, instance, exit_rule, cv)
         ex = exit_points(geom, coef, k, rec, interp)
         rows[k] = knot_row(geom, coef, k, rec, ex, u_ref)
         if keep_paths:

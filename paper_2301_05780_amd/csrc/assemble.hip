@@ -227,7 +227,7 @@ struct GeoView {
   int L;
 };
 
-template <int KIND, bool F64, int CV, bool BATCH, bool RBF = false>
+template <int KIND, bool F64, int CV, bool BATCH, bool RBF = false, bool HK = false>
 __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   using R = typename std::conditional<F64, double, float>::type;
   constexpr bool CVON = CV != PDD_CV_NONE;
@@ -598,9 +598,18 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     double* row = wrows + (size_t)prow * RL;
     for (int i = lane; i < RL; i += 64) row[i] = 0.0;
     wave_sync();
+    // the ticket's time step: the instance's, the knot's own (h_i of
+    // eq. 40), or the launch's
+    double hk = P.h, sqk = P.sqrt_h;
+    if constexpr (HK) {
+      if (P.h_knot) {
+        hk = P.h_knot[T.knot];
+        sqk = sqrt(hk);
+      }
+    }
     if (lane < 4) {
       CoefParams cp = P.coef;
-      double sqh = P.sqrt_h;
+      double sqh = sqk;
       if constexpr (BATCH) { cp.a = W.I.a; sqh = W.I.sqrt_h; }
       W.ebox[lane] = exit_threshold<KIND, R>(cp, P.exit_rule, sqh, W.d, lane);
     }
@@ -618,6 +627,9 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       u.h = to_uniform((R)W.I.h);
       u.sq = to_uniform((R)W.I.sqrt_h);
       u.a = to_uniform((R)W.I.a);
+    } else if constexpr (HK) {
+      u.h = to_uniform((R)hk);
+      u.sq = to_uniform((R)sqk);
     }
     if (b) { tk1 = (int)t; nx1 = T.p0; en1 = T.p1; u1 = u; }
     else { tk0 = (int)t; nx0 = T.p0; en0 = T.p1; u0 = u; }
@@ -680,11 +692,11 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         ehy = cur ? u1.e1 : u0.e1;
         elx = cur ? u1.e2 : u0.e2;
         ely = cur ? u1.e3 : u0.e3;
-        if constexpr (BATCH) {
+        if constexpr (BATCH || HK) {
           lh = cur ? u1.h : u0.h;
           lsq = cur ? u1.sq : u0.sq;
-          la = cur ? u1.a : u0.a;
         }
+        if constexpr (BATCH) la = cur ? u1.a : u0.a;
         active = true;
         buf = cur;
       }
@@ -793,9 +805,10 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   }
 }
 
+// single launches take per-knot time steps when P.h_knot is set
 template <int KIND, bool F64, int CV, bool BATCH>
 __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
-  assemble_body<KIND, F64, CV, BATCH>(P);
+  assemble_body<KIND, F64, CV, BATCH, false, !BATCH>(P);
 }
 
 // float32 closed-form families without a control variate: capped at 80
@@ -805,7 +818,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmParams P) {
 // RBF cardinal interpolation at the exits (single launches)
 template <int KIND, bool F64, int CV>
 __global__ __launch_bounds__(256) void k_assemble_rbf(AsmParams P) {
-  assemble_body<KIND, F64, CV, false, true>(P);
+  assemble_body<KIND, F64, CV, false, true, true>(P);
 }
 
 template <int KIND>
@@ -899,14 +912,15 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeParams F) {
   }
 }
 
+// hk: per-knot time steps (the capped kernels take the launch's h only)
 template <int KIND, bool F64, int CV, bool BATCH = false>
-const void* kernel_ptr() {
-  if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND != PDD_COEF_LUT)
-    return reinterpret_cast<const void*>(&k_assemble_w6<KIND>);
-  else if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND == PDD_COEF_LUT)
-    return reinterpret_cast<const void*>(&k_assemble_w4<KIND>);
-  else
-    return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
+const void* kernel_ptr(bool hk = false) {
+  if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND != PDD_COEF_LUT) {
+    if (!hk) return reinterpret_cast<const void*>(&k_assemble_w6<KIND>);
+  } else if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND == PDD_COEF_LUT) {
+    if (!hk) return reinterpret_cast<const void*>(&k_assemble_w4<KIND>);
+  }
+  return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
 }
 
 template <bool F64, int CV>
@@ -934,28 +948,28 @@ const void* pick_batch(int kind, int cv) {
 }
 
 template <bool F64, int CV>
-const void* pick_kind(int kind) {
+const void* pick_kind(int kind, bool hk) {
   switch (kind) {
-    case PDD_COEF_POISSON: return kernel_ptr<PDD_COEF_POISSON, F64, CV>();
-    case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64, CV>();
-    case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64, CV>();
-    case PDD_COEF_LUT: return kernel_ptr<PDD_COEF_LUT, F64, CV>();
-    case PDD_COEF_EQ43: return kernel_ptr<PDD_COEF_EQ43, F64, CV>();
+    case PDD_COEF_POISSON: return kernel_ptr<PDD_COEF_POISSON, F64, CV>(hk);
+    case PDD_COEF_VARCOEF: return kernel_ptr<PDD_COEF_VARCOEF, F64, CV>(hk);
+    case PDD_COEF_AMPLITUDE: return kernel_ptr<PDD_COEF_AMPLITUDE, F64, CV>(hk);
+    case PDD_COEF_LUT: return kernel_ptr<PDD_COEF_LUT, F64, CV>(hk);
+    case PDD_COEF_EQ43: return kernel_ptr<PDD_COEF_EQ43, F64, CV>(hk);
     default: break;
   }
   if constexpr (CV == PDD_CV_NONE) {
-    if (kind == PDD_COEF_CONSTSOL) return kernel_ptr<PDD_COEF_CONSTSOL, F64, CV>();
-    if (kind == PDD_COEF_EXITTIME) return kernel_ptr<PDD_COEF_EXITTIME, F64, CV>();
+    if (kind == PDD_COEF_CONSTSOL) return kernel_ptr<PDD_COEF_CONSTSOL, F64, CV>(hk);
+    if (kind == PDD_COEF_EXITTIME) return kernel_ptr<PDD_COEF_EXITTIME, F64, CV>(hk);
   }
   return nullptr;
 }
 
 template <bool F64>
-const void* pick(int kind, int cv) {
+const void* pick(int kind, int cv, bool hk) {
   switch (cv) {
-    case PDD_CV_NONE: return pick_kind<F64, PDD_CV_NONE>(kind);
-    case PDD_CV_NETWORK: return pick_kind<F64, PDD_CV_NETWORK>(kind);
-    case PDD_CV_GRAD_LUT: return pick_kind<F64, PDD_CV_GRAD_LUT>(kind);
+    case PDD_CV_NONE: return pick_kind<F64, PDD_CV_NONE>(kind, hk);
+    case PDD_CV_NETWORK: return pick_kind<F64, PDD_CV_NETWORK>(kind, hk);
+    case PDD_CV_GRAD_LUT: return pick_kind<F64, PDD_CV_GRAD_LUT>(kind, hk);
     default: return nullptr;
   }
 }
@@ -991,9 +1005,9 @@ const void* rbf_kernel(int precision, int kind, int cv) {
   return precision == PDD_FP64_SAME_STREAM ? pick_rbf<true>(kind, cv) : pick_rbf<false>(kind, cv);
 }
 
-const void* assemble_kernel(int precision, int kind, int cv, bool batch) {
+const void* assemble_kernel(int precision, int kind, int cv, bool batch, bool hk = false) {
   if (batch) return precision == PDD_FP64_SAME_STREAM ? pick_batch<true>(kind, cv) : pick_batch<false>(kind, cv);
-  return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind, cv) : pick<false>(kind, cv);
+  return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind, cv, hk) : pick<false>(kind, cv, hk);
 }
 
 }  // namespace
@@ -1012,15 +1026,15 @@ size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int c
 }
 
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
-                              int* blocks_per_cu) {
-  const void* f = assemble_kernel(precision, kind, cv_mode, batch);
+                              int* blocks_per_cu, bool per_knot_h) {
+  const void* f = assemble_kernel(precision, kind, cv_mode, batch, per_knot_h);
   if (!f) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block, size_t lds_bytes,
                            hipStream_t stream) {
-  const void* f = assemble_kernel(precision, p.coef.kind, p.cv_mode, p.insts != nullptr);
+  const void* f = assemble_kernel(precision, p.coef.kind, p.cv_mode, p.insts != nullptr, p.h_knot != nullptr);
   if (!f) return hipErrorInvalidValue;
   AsmParams arg = p;
   void* args[] = {&arg};

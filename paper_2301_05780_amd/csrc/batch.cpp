@@ -57,6 +57,8 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
       return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: no u_ref or dump in batches");
     if (q.run.interp != PDD_INTERP_HAT)
       return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: batches use the hat interpolation");
+    if (q.run.h_per_knot)
+      return bad(ctx, PDD_EUNSUPPORTED, "pdd_assemble_batch: one time step per instance (run.h_per_knot unset)");
     // a control variate is shared: the same mode and table or network for
     // every instance, on one domain (the gradient table spans it)
     const int qcv = q.run.cv ? q.run.cv->mode : PDD_CV_NONE;

@@ -285,6 +285,7 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
     return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: run.instance must be below 2^31");
   if (run->interp != PDD_INTERP_HAT)
     return fail(ctx, PDD_EUNSUPPORTED, "pdd_eval_subdomain: boundary values use the hat interpolation (run.interp 0)");
+  if (run->h_per_knot) return fail(ctx, PDD_EUNSUPPORTED, "pdd_eval_subdomain: run.h_per_knot must be NULL");
   if (n_pts > INT32_MAX) return fail(ctx, PDD_EINVAL, "pdd_eval_subdomain: at most 2^31 - 1 points");
   pdd_status st = validate_run(ctx, *coeffs, *run);
   if (st != PDD_OK) return st;
@@ -302,6 +303,7 @@ pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_parti
     return fail(ctx, PDD_EINVAL, "pdd_calibrate: xi is drawn with the gradient table (run.cv mode GRAD_LUT) or not at all");
   if (run->interp != PDD_INTERP_HAT)
     return fail(ctx, PDD_EUNSUPPORTED, "pdd_calibrate: u0 is interpolated with the hat weights (run.interp 0)");
+  if (run->h_per_knot) return fail(ctx, PDD_EUNSUPPORTED, "pdd_calibrate: one time step h0 (run.h_per_knot NULL)");
   pdd_run r = *run;
   r.exit_rule = PDD_EXIT_GM;
   r.n_paths_per_knot = nullptr;
@@ -415,6 +417,7 @@ pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pd
     return fail(ctx, PDD_EINVAL, "pdd_collect_training: collect from plain paths (run.cv must be NULL)");
   if (run->interp != PDD_INTERP_HAT)
     return fail(ctx, PDD_EUNSUPPORTED, "pdd_collect_training: targets use the hat interpolation (run.interp 0)");
+  if (run->h_per_knot) return fail(ctx, PDD_EUNSUPPORTED, "pdd_collect_training: run.h_per_knot must be NULL");
   pdd_status st = validate_run(ctx, *coeffs, *run);
   if (st != PDD_OK) return st;
   hipError_t e = hipSetDevice(ctx->device);

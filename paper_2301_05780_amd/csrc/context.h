@@ -40,6 +40,8 @@ struct GeoCache {
 struct TicketCache {
   const GeoCache* geo = nullptr;
   std::vector<int32_t> npk;       // paths per knot
+  std::vector<double> hk;         // per-knot time steps (empty: the launch's h)
+  DeviceBuffer h_knot;            // device copy of hk
   int32_t per_ticket = 0;
   uint32_t inst = 0;
   bool spatial = false;           // spatial order (tabulated coefficients) instead of longest-first

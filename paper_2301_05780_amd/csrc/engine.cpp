@@ -171,6 +171,13 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     npk[k] = (int32_t)v;
     total += v;
   }
+  // per-knot time steps (eq. 40)
+  std::vector<double> hk;
+  if (run.h_per_knot) {
+    hk.assign(run.h_per_knot, run.h_per_knot + g.n);
+    for (double v : hk)
+      if (!(v > 0.0) || !std::isfinite(v)) return bad(ctx, PDD_EINVAL, "run.h_per_knot: entries must be finite and > 0");
+  }
   if (run.u_ref) {
     if (!gc->lattice.ptr && capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: lattice table not cached before capture");
     st = get_lattice(ctx, gc);
@@ -194,7 +201,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   int per_cu = 0;
   const bool rbf = run.interp == PDD_INTERP_RBF_IMQ;
   e = rbf ? assemble_occupancy_rbf(run.precision, job.coeffs.kind, cv_mode, block, lds, &per_cu)
-          : assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, false, block, lds, &per_cu);
+          : assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, false, block, lds, &per_cu, !hk.empty());
   if (e != hipSuccess) return check_hip(ctx, e, "occupancy query");
   per_cu = std::max(per_cu, 1);
   int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
@@ -216,7 +223,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   // tickets (cached while geometry, path counts, ticket size and order repeat)
   TicketCache* tc = ctx->tickets.get();
   if (!tc || tc->geo != gc || tc->per_ticket != per_ticket || tc->npk != npk || tc->inst != run.instance ||
-      tc->spatial != spatial) {
+      tc->spatial != spatial || tc->hk != hk) {
     if (capturing) return bad(ctx, PDD_EINVAL, "pdd_assemble: tables not cached; run the same call once before capturing");
     auto fresh = std::make_unique<TicketCache>();
     fresh->geo = gc;
@@ -225,7 +232,10 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     fresh->inst = run.instance;
     TicketPlan plan;
     std::string err;
-    if ((st = plan_tickets(g, npk, per_ticket, spatial, run.instance, plan, err)) != PDD_OK) return bad(ctx, st, err.c_str());
+    fresh->hk = hk;
+    if ((st = plan_tickets(g, npk, per_ticket, spatial, run.instance, plan, err, hk.empty() ? nullptr : hk.data())) !=
+        PDD_OK)
+      return bad(ctx, st, err.c_str());
     const std::vector<Ticket>& tk = plan.tickets;
     const std::vector<int32_t>& tb = plan.begin;
     const std::vector<int32_t>& order = plan.order;
@@ -242,6 +252,11 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     if ((e = hipMemcpy(fresh->order.ptr, order.data(), order.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload order");
     if ((e = hipMemcpy(fresh->ticket_begin.ptr, tb.data(), tb.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload ticket_begin");
     if ((e = hipMemcpy(fresh->n_paths.ptr, npk.data(), npk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return check_hip(ctx, e, "upload n_paths");
+    if (!hk.empty()) {
+      if ((e = fresh->h_knot.reserve(hk.size() * sizeof(double))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(h_knot)");
+      if ((e = hipMemcpy(fresh->h_knot.ptr, hk.data(), hk.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return check_hip(ctx, e, "upload h_knot");
+    }
     ctx->tickets = std::move(fresh);
     tc = ctx->tickets.get();
   }
@@ -283,6 +298,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   fill_asm_params(*gc, job.coeffs, run, P);
   P.tickets = tc->tickets.as<Ticket>();
   P.order = tc->order.as<int32_t>();
+  P.h_knot = hk.empty() ? nullptr : tc->h_knot.as<double>();
   P.n_tickets = (int32_t)tc->n_tickets;
   P.xcd_begin = split_xcd ? tc->xcd_begin.as<int32_t>() : nullptr;
   P.refill_min = ctx->refill_min;

@@ -101,6 +101,9 @@ struct AsmParams {
   const double* rbf_inv;
   int64_t rbf_half;
   double rbf_c2;              // c^2
+  // per-knot time steps h_i (eq. 40), device, nullable: the launch's h
+  // (single launches of the generic and RBF kernels)
+  const double* h_knot;
 };
 
 // Extras stored after the 4 slot_len G slots of a partial row.
@@ -155,6 +158,6 @@ hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipS
 size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch, int pool_rows);
 // Kernel attribute query for occupancy-based grid sizing.
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
-                              int* blocks_per_cu);
+                              int* blocks_per_cu, bool per_knot_h = false);
 
 }  // namespace pdd

@@ -21,7 +21,7 @@ uint32_t spread_bits(uint32_t v) {
 }  // namespace
 
 pdd_status plan_tickets(const Geometry& g, const std::vector<int32_t>& npk, int64_t per_ticket, bool spatial,
-                        uint32_t instance, TicketPlan& out, std::string& err) {
+                        uint32_t instance, TicketPlan& out, std::string& err, const double* h_knot) {
   if (per_ticket < 1) {
     err = "plan_tickets: paths per ticket must be >= 1";
     return PDD_EINVAL;
@@ -40,7 +40,10 @@ pdd_status plan_tickets(const Geometry& g, const std::vector<int32_t>& npk, int6
       return PDD_EINVAL;
     }
     const int64_t c = (N + per_ticket - 1) / per_ticket;
-    const double area = (double)(g.box[4 * k + 1] - g.box[4 * k + 0]) * (double)(g.box[4 * k + 3] - g.box[4 * k + 2]);
+    // expected steps per path: the mean exit time (which scales with the
+    // patch area, eq. 26) over the knot's time step
+    double area = (double)(g.box[4 * k + 1] - g.box[4 * k + 0]) * (double)(g.box[4 * k + 3] - g.box[4 * k + 2]);
+    if (h_knot) area /= h_knot[k];
     for (int64_t i = 0; i < c; ++i) {
       Ticket t;
       t.knot = (int32_t)k;

@@ -23,9 +23,11 @@ struct TicketPlan {
 // contiguous ranges.  The claim order is, with `spatial`, the tickets sorted
 // by the Morton (Z) index of their knot's subdomain (stable: knot order and
 // path ranges within), else longest expected first (expected cost = patch
-// area x paths, the mean exit time scaling with the area, eq. 26; stable).
+// area x paths, the mean exit time scaling with the area, eq. 26, divided
+// by the knot's time step when per-knot steps h_knot (host, nullable) are
+// given; stable).
 pdd_status plan_tickets(const Geometry& g, const std::vector<int32_t>& npk, int64_t per_ticket, bool spatial,
-                        uint32_t instance, TicketPlan& out, std::string& err);
+                        uint32_t instance, TicketPlan& out, std::string& err, const double* h_knot = nullptr);
 
 // Split of a spatial order over the XCDs for a grid of `grid` workgroups
 // (grid >= 8; workgroup b runs on XCD b mod 8): XCD x, which holds

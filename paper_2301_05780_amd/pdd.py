@@ -67,7 +67,8 @@ class Run(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32), ("precision", C.c_int32),
                 ("exit_rule", C.c_int32), ("dump_paths", C.c_int32), ("n_paths", C.c_int64),
                 ("n_paths_per_knot", C.c_void_p), ("h", C.c_double), ("cv", C.c_void_p),
-                ("u_ref", C.c_void_p), ("dump", C.c_void_p), ("interp", C.c_int32), ("rbf_c", C.c_double)]
+                ("u_ref", C.c_void_p), ("dump", C.c_void_p), ("interp", C.c_int32), ("rbf_c", C.c_double),
+                ("h_per_knot", C.c_void_p)]
 
 
 class Instance(C.Structure):
@@ -461,10 +462,11 @@ class Context:
 
     def assemble(self, w, out=None, lut=None, n_paths_per_knot=None, u_ref=None,
                  dump_paths=0, precision=None, exit_rule=None, seed=None, instance=None,
-                 cv=None):
+                 cv=None, h_per_knot=None):
         """Assemble G (CSR) and b of workload w.  Returns dict of device tensors
         row_ptr, col_idx, val, b, diag (and dump if requested).  ``out`` may hold
-        preallocated tensors of the same names to write into."""
+        preallocated tensors of the same names to write into; ``h_per_knot``
+        (host array of n) gives each knot its own time step."""
         torch = self.torch
         n, nnz, _, _ = pattern(w) if out is None else (out["n"], out["nnz"], None, None)
         dev = self.device
@@ -491,10 +493,14 @@ class Context:
                   C.cast(C.pointer(cvs), C.c_void_p) if cvs is not None else None,
                   _ptr(u_ref), _ptr(out.get("dump")) if dump_paths else None)
         _set_interp(run, w)
+        hk = None
+        if h_per_knot is not None:
+            hk = np.ascontiguousarray(h_per_knot, dtype=np.float64)
+            run.h_per_knot = hk.ctypes.data
         co = self.coeffs_of(w, lut)
         part, kn = partition_of(w), knots_of(w)
         self.check(lib().pdd_assemble(self.h, C.byref(co), C.byref(part), C.byref(kn), C.byref(run),
                                       _ptr(out["row_ptr"]), _ptr(out["col_idx"]), _ptr(out["val"]),
                                       _ptr(out["b"]), _ptr(out["diag"])))
-        self._keep = (npk, cvs)
+        self._keep = (npk, cvs, hk)
         return out
