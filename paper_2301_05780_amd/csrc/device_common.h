@@ -182,6 +182,27 @@ __device__ __forceinline__ R eq43_laplacian(R x, R y) {
   return (lap_a + lap_b) / (R)3;
 }
 
+// float32 form of the same Laplacian on the transcendental units: angles in
+// revolutions, 1/r from the reciprocal square root, tanh from exp2, and
+// multiplications by reciprocal constants instead of divisions.
+__device__ __forceinline__ float eq43_laplacian(float x, float y) {
+  constexpr float inv2pi = 0.15915494309189535f;
+  const float q = 1.0f + x * x * 0.01f + y * y * 0.02f;
+  const float ir = __builtin_amdgcn_rsqf(q), r = q * ir;
+  const float rx = x * 0.01f * ir, ry = y * 0.02f * ir;
+  const float g2 = rx * rx + ry * ry;
+  const float lap_r = (0.03f - g2) * ir;
+  const float lap_a = cos_rev(r * inv2pi) * lap_r - sin_rev(r * inv2pi) * g2;
+  const float al = (0.12f * x + 0.05f * y) * inv2pi, be = (0.05f * x - 0.12f * y) * inv2pi;
+  const float sa = sin_rev(al), sb = sin_rev(be), ca = cos_rev(al), cb = cos_rev(be);
+  const float s = sa + sb;
+  const float sx = 0.12f * ca + 0.05f * cb, sy = 0.05f * ca - 0.12f * cb;
+  // tanh s = 1 - 2 / (e^{2s} + 1), e^{2s} = 2^{2s log2 e}; |s| <= 2 keeps it finite
+  const float T = 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(s * 2.8853900817779268f) + 1.0f);
+  const float lap_b = (1.0f - T * T) * (-0.0169f * s - 2.0f * T * (sx * sx + sy * sy));
+  return (lap_a + lap_b) * 0.3333333333333333f;
+}
+
 // Coefficients at (x, y).  float64 versions mirror the CPU definition's
 // expression order; float32 versions use the transcendental units.
 template <int KIND>
