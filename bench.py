@@ -271,7 +271,7 @@ def phases(ctx, w, n0, eps, n_job, table=None):
     assembly with n0 paths per knot and its solve; the Phase II calibration
     (n0 mixed GM/EM paths per knot, the control variate drawn alongside with
     the gradient table); and the Phase III production run with the per-knot
-    path counts of eq. 41 (and the smallest h_i of eq. 40), the control
+    path counts of eq. 41 and the per-knot time steps of eq. 40, the control
     variate on.  Reports the calibration kernel's time and path-steps/s, the
     plan and the final interface errors against u*."""
     import numpy as np
@@ -299,7 +299,7 @@ def phases(ctx, w, n0, eps, n_job, table=None):
     st = stats.cpu().numpy()
     pl = pdd.calibration_plan(st, n0, w["h"], eps, n_job)
     h3 = float(pl["h"].min())
-    out = ctx.assemble(dict(w, h=h3), seed=10, cv=spec, n_paths_per_knot=pl["n_paths"])
+    out = ctx.assemble(w, seed=10, cv=spec, n_paths_per_knot=pl["n_paths"], h_per_knot=pl["h"])
     err = np.abs(solve(out).cpu().numpy() - ue)
     steps = float(st[:, 7].sum())
     return {
@@ -312,7 +312,7 @@ def phases(ctx, w, n0, eps, n_job, table=None):
                         "paths_total": int(pl["n_paths"].sum()), "paths_median": float(np.median(pl["n_paths"]))},
         "production": {"rmse": float(np.sqrt(np.mean(err ** 2))), "max_error": float(err.max()),
                        "fraction_within_eps": float(np.mean(err < eps)),
-                       "paths": int(pl["n_paths"].sum()), "h": h3},
+                       "paths": int(pl["n_paths"].sum()), "h_min": h3, "h_median": float(np.median(pl["h"]))},
     }
 
 
