@@ -372,12 +372,29 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   if (n_inst < 1 || !inst || reps < 1 || !best_ms) return bad(ctx, PDD_EINVAL, "pdd_autotune: bad arguments");
   // signature of the workload: instance geometries, path counts and options
   std::string sig;
-  char buf[256];
+  char buf[384];
+  // FNV-1a over a host array (per-knot path counts or steps)
+  auto fnv = [](const void* p, size_t bytes) -> unsigned long long {
+    unsigned long long hsh = 1469598103934665603ull;
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < bytes; ++i) hsh = (hsh ^ c[i]) * 1099511628211ull;
+    return hsh;
+  };
   for (int32_t i = 0; i < n_inst; ++i) {
     const pdd_instance& q = inst[i];
-    snprintf(buf, sizeof(buf), "%d:%d:%d:%d:%d:%.17g:%lld:%d:%d:%.17g:%.17g:%.17g:%.17g:%.17g;", q.coeffs.kind,
-             q.coeffs.lut_n, q.part.H, q.knots.m, q.knots.ext, q.run.h, (long long)q.run.n_paths, q.run.precision,
-             q.run.exit_rule, q.coeffs.param[0], q.part.x0, q.part.x1, q.part.y0, q.part.y1);
+    unsigned long long hn = 0, hh = 0;
+    if (q.run.n_paths_per_knot || q.run.h_per_knot) {
+      GeoCache* gc = nullptr;
+      if (get_geometry(ctx, q.part, q.knots, &gc) == PDD_OK) {
+        const size_t n = (size_t)gc->g.n;
+        if (q.run.n_paths_per_knot) hn = fnv(q.run.n_paths_per_knot, n * sizeof(int32_t));
+        if (q.run.h_per_knot) hh = fnv(q.run.h_per_knot, n * sizeof(double));
+      }
+    }
+    snprintf(buf, sizeof(buf), "%d:%d:%d:%d:%d:%.17g:%lld:%d:%d:%.17g:%.17g:%.17g:%.17g:%.17g:%d:%d:%.17g:%llx:%llx;",
+             q.coeffs.kind, q.coeffs.lut_n, q.part.H, q.knots.m, q.knots.ext, q.run.h, (long long)q.run.n_paths,
+             q.run.precision, q.run.exit_rule, q.coeffs.param[0], q.part.x0, q.part.x1, q.part.y0, q.part.y1,
+             q.run.cv ? q.run.cv->mode : PDD_CV_NONE, q.run.interp, q.run.rbf_c, hn, hh);
     sig += buf;
   }
   auto run_once = [&]() -> pdd_status {

@@ -321,25 +321,35 @@ class Context:
                     b=torch.empty(n, dtype=torch.float64, device=dev),
                     diag=torch.empty(n * DIAG_WIDTH, dtype=torch.float64, device=dev))
 
-    def _instance(self, w, out, precision=None, lut=None, cvp=None):
+    def _instance(self, w, out, precision=None, lut=None, cvp=None, npk=None, hk=None):
         run = Run(int(w["seed"]) & (2 ** 64 - 1), int(w.get("instance", 0)), PRECISION[precision or w["precision"]],
                   EXIT[w["exit_rule"]], 0, int(w["n_paths"]), None, float(w["h"]), cvp, None, None)
         _set_interp(run, w)
+        if npk is not None:
+            run.n_paths_per_knot = npk.ctypes.data
+        if hk is not None:
+            run.h_per_knot = hk.ctypes.data
         return Instance(self.coeffs_of(w, lut), partition_of(w), knots_of(w), run,
                         _ptr(out["row_ptr"]), _ptr(out["col_idx"]), _ptr(out["val"]), _ptr(out["b"]),
                         _ptr(out["diag"]))
 
-    def batch_arrays(self, ws, outs=None, precision=None, lut=None, cv=None):
+    def batch_arrays(self, ws, outs=None, precision=None, lut=None, cv=None, n_paths_per_knot=None,
+                     h_per_knot=None):
         """Instance array (and outputs) for pdd_assemble_batch / pdd_autotune;
         ``lut`` is the table of tabulated-coefficient workloads (single
-        instance); ``cv`` a CVSpec shared by every instance."""
+        instance); ``cv`` a CVSpec shared by every instance; per-knot path
+        counts and steps (host arrays) for a single instance, which
+        pdd_autotune then tunes as pdd_assemble runs it."""
         outs = outs or [self._outputs(w) for w in ws]
         cvp = None
         if cv is not None:
             cvs = cv if isinstance(cv, CV) else cv.struct()
             self._keep_cv = cvs                       # the instances point at it
             cvp = C.cast(C.pointer(cvs), C.c_void_p)
-        arr = (Instance * len(ws))(*[self._instance(w, o, precision, lut, cvp) for w, o in zip(ws, outs)])
+        npk = None if n_paths_per_knot is None else np.ascontiguousarray(n_paths_per_knot, dtype=np.int32)
+        hk = None if h_per_knot is None else np.ascontiguousarray(h_per_knot, dtype=np.float64)
+        self._keep_arrays = (npk, hk)
+        arr = (Instance * len(ws))(*[self._instance(w, o, precision, lut, cvp, npk, hk) for w, o in zip(ws, outs)])
         return arr, outs
 
     def assemble_batch(self, ws, outs=None, precision=None, arr=None, cv=None):
