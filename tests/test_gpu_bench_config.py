@@ -97,6 +97,41 @@ def test_varcoef_rbf_at_full_size(ctx):
         assert abs(got["diag"][k, 0] / r["diag"][0] - 1.0) < 2e-3, k
 
 
+def test_sec5_phase1_in_the_timed_configuration(ctx):
+    """The Sec. 5 experiment's Phase I at full size (11,241 knots, 191-point
+    RBF stencils, h0 = 0.08) in the autotuned shape the benchmark times:
+    sampled rows against the oracle within 3 standard errors plus the
+    conditioning floor."""
+    w = workloads.sec5()
+    c = pdd.rbf_shape(191, 200.0 / 630, w["rbf_condition"])
+    w = dict(w, rbf_c=c)
+    arr, outs = ctx.batch_arrays([w])
+    try:
+        ctx.autotune(arr, reps=1)
+        shape = ctx.last_launch()
+        out = ctx.assemble(w, out=outs[0])
+        ctx.sync()
+        assert ctx.last_launch() == shape
+        got = _host(out)
+        g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+        assert np.array_equal(got["row_ptr"], g.row_ptr) and np.array_equal(got["col_idx"], g.col_idx)
+        assert np.all(np.isfinite(got["val"])) and np.all(np.isfinite(got["b"]))
+        knots = np.random.default_rng(8).choice(g.n, 2, replace=False)
+        ref = oracle_assemble(g, Coefficients("eq43"), w["n_paths"], w["h"], w["seed"], exit_rule=w["exit_rule"],
+                              knots=knots, interp=("rbf", c))["rows"]
+        for k in knots:
+            r = ref[k]
+            a, e = g.row_ptr[k], g.row_ptr[k + 1]
+            floor = 1e-6 + 191 * w["rbf_condition"] * 2.0 ** -53 * r["mass"]
+            assert np.all(np.abs(got["val"][a:e] - r["val"]) <= 3 * r["se_val"] + floor), k
+            assert abs(got["b"][k] - r["b"]) <= 3 * r["se_b"] + floor, k
+            assert abs(got["diag"][k, 0] / r["diag"][0] - 1.0) < 5e-3, k
+    finally:
+        ctx.set_launch(0, 0, 0)
+        ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
+
+
 def test_large_lut_in_the_timed_configuration(ctx):
     w = workloads.large_lut()
     tab = workloads.poisson_lut(w["lut_n"])
