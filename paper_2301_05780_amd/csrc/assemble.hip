@@ -103,17 +103,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// 1 / sqrt(x) for x >= c^2 > 0 in float64: the hardware estimate refined by
-// two Newton steps for the reciprocal square root,
-// y <- y + y (1 - x y^2) / 2, each of which squares the relative error.
+// 1 / sqrt(x) for x >= c^2 > 0 in float64: the hardware estimate (relative
+// error about 2^-23) refined by one Halley step for the reciprocal square
+// root, y <- y (1 + e/2 + 3 e^2/8) with e = 1 - x y^2, which cubes the
+// relative error (below the float64 rounding of the final step).
 __device__ __forceinline__ double rsqrt_f64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-  }
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -375,7 +372,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       int rb = 0, o = 0;
       double vb = 0.0, vs = 0.0, vk = 0.0;
       int rkey = -1;                 // RBF: 4 buffer + side of an interface exit (-1: none)
-      double rt = 0.0, rY = 0.0;     // RBF: lattice coordinate of the exit point, Y
+      double rtd = 0.0, rY = 0.0;    // RBF: exit point along the line (domain units from its origin), Y
       if (valid) {
         ExitRec<R> r = Q[i];
         const uint32_t meta = Qm[i];
@@ -416,7 +413,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           // group of exits sharing a row side at a time
           const double a0 = vert ? (double)G.y0 : (double)G.x0;
           const double da = vert ? G.dy : G.dx;
-          rt = fmin(fmax(((double)along - a0) / da, (double)d.clo[o]), (double)d.chi[o]);
+          const double t = fmin(fmax(((double)along - a0) / da, (double)d.clo[o]), (double)d.chi[o]);
+          rtd = t * da;
           rY = (double)r.Y;
           rkey = 4 * rb + o;
         } else {
@@ -496,7 +494,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           for (int c0 = 0; c0 < S; c0 += 64) {
             const int si = c0 + lane;
             const bool in = si < S;
-            const double q = (double)(clo + si);
+            const double qd = (double)(clo + si) * da;     // the stencil point, in domain units from the line's origin
             // rows 0 and S-1 of Phi^{-1} weighted by the boundary data
             double wb = 0.0;
             if (b0 && in) wb = Mi[si] * g0;
@@ -520,7 +518,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
               double ph[RU];
 #pragma unroll
               for (int u = 0; u < RU; ++u) {
-                const double rr = (readlane_f64(rt, e[u]) - q) * da;
+                const double rr = readlane_f64(rtd, e[u]) - qd;
                 ph[u] = rsqrt_f64(fma(rr, rr, P.rbf_c2));
               }
 #pragma unroll
