@@ -15,6 +15,7 @@
 //   sum phi_GM xi, sum K_GM, sum K_EM.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -36,6 +37,7 @@ struct CalArgs {
   const double* u0;                  // warm-up knot values
   uint32_t inst;                     // fourth Philox counter word
   double* rec;                       // REC doubles per path
+  unsigned long long* counter;       // next path id (zeroed before the launch)
 };
 
 // u0 at the exit point resolved from the flagged sides `fl` (bit o: side o)
@@ -74,27 +76,67 @@ __device__ R exit_value(const AsmParams& P, const KnotDesc& d, const double* u0,
   return val;
 }
 
+// Persistent: each wave takes path ids from a device counter, a batch for
+// its idle lanes at a time (once at least REFILL lanes are idle, or all of
+// them), so a lane whose path ended starts the next one instead of waiting
+// for the longest path of its wave.  A path's arithmetic is independent of
+// which lane runs it, so the records do not depend on the schedule.
+constexpr int REFILL = 16;
+
 template <int KIND, bool F64, bool CVON>
 __global__ __launch_bounds__(BLK) void k_calibrate(CalArgs C) {
   using R = typename std::conditional<F64, double, float>::type;
   const AsmParams& P = C.P;
-  const int64_t gid = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  if (gid >= C.n * C.n_paths) return;
-  const int64_t k = gid / C.n_paths;
-  const uint32_t p = (uint32_t)(gid % C.n_paths);
-  const KnotDesc d = P.desc[k];
-  R egm[4], env[4];
-  for (int o = 0; o < 4; ++o) {
-    egm[o] = exit_threshold<KIND, R>(P.coef, PDD_EXIT_GM, P.sqrt_h, d, o);
-    env[o] = exit_threshold<KIND, R>(P.coef, PDD_EXIT_NAIVE, P.sqrt_h, d, o);
-  }
+  const int lane = threadIdx.x & 63;
+  const int64_t total = C.n * C.n_paths;
   const R h = (R)P.h, sq = (R)P.sqrt_h;
-  R x = (R)d.sx, y = (R)d.sy, Y = 1, Z = 0, Xi = 0;
+  bool active = false, exhausted = false;
+  int64_t gid = 0, k = 0;
+  uint32_t p = 0;
+  R egm[4], env[4];
+  const double* line = nullptr;      // the knot's side lines (global; read by the table family's GM test)
+  R x = 0, y = 0, Y = 0, Z = 0, Xi = 0;
   R phi_gm = 0, xi_gm = 0, phi_em = 0;
   uint32_t K = 0, K_gm = 0, j = 0;
-  bool gm_done = false, done = false;
-  while (!done) {
+  bool gm_done = false;
+  while (true) {
+    // ---- refill idle lanes with the next path ids -----------------------
+    const uint64_t idle = __ballot(!active);
+    const int n_idle = __popcll(idle);
+    if (!exhausted && idle != 0 && (n_idle >= REFILL || idle == ~0ull)) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(C.counter, (unsigned long long)n_idle);
+      base = ((unsigned long long)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+             (unsigned)__builtin_amdgcn_readfirstlane((int)(base & 0xffffffffull));
+      if ((int64_t)(base + n_idle) >= total) exhausted = true;
+      if (!active) {
+        const int64_t g = (int64_t)base + __popcll(idle & ((1ull << lane) - 1ull));
+        if (g < total) {
+          gid = g;
+          k = g / C.n_paths;
+          p = (uint32_t)(g % C.n_paths);
+          const KnotDesc d = P.desc[k];
+          for (int o = 0; o < 4; ++o) {
+            egm[o] = exit_threshold<KIND, R>(P.coef, PDD_EXIT_GM, P.sqrt_h, d, o);
+            env[o] = exit_threshold<KIND, R>(P.coef, PDD_EXIT_NAIVE, P.sqrt_h, d, o);
+          }
+          line = P.desc[k].line;
+          x = (R)d.sx; y = (R)d.sy; Y = 1; Z = 0; Xi = 0;
+          phi_gm = 0; xi_gm = 0; phi_em = 0;
+          K = 0; K_gm = 0; j = 0;
+          gm_done = false;
+          active = true;
+        }
+      }
+    }
+    if (__ballot(active) == 0) {
+      if (exhausted) break;
+      continue;
+    }
+    if (!active) continue;
+    // ---- one draw, up to two steps --------------------------------------
     const U4 r = philox10(j, p, (uint32_t)k, C.inst, P.key0, P.key1);
+    bool done = false;
     for (int half = 0; half < 2 && !done; ++half) {
       R z0, z1;
       if constexpr (F64) box_muller(uniform64(half ? r.c : r.a), uniform64(half ? r.d : r.b), z0, z1);
@@ -104,22 +146,25 @@ __global__ __launch_bounds__(BLK) void k_calibrate(CalArgs C) {
       em_step<KIND, R, CVON>(P.coef, h, sq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
       ++K;
       if (!gm_done) {
-        const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_GM, sq, d.line, egm, x, y);
+        const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_GM, sq, line, egm, x, y);
         if (fl) {
+          const KnotDesc d = P.desc[k];
           phi_gm = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, fl);
           xi_gm = Xi;
           K_gm = K;
           gm_done = true;
         }
       }
-      const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_NAIVE, sq, d.line, env, x, y);
+      const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_NAIVE, sq, line, env, x, y);
       if (fl) {
+        const KnotDesc d = P.desc[k];
         phi_em = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, fl);
         done = true;
       }
     }
     ++j;
     if (!done && 2 * j >= (1u << 24) - 2) {      // step cap: every side flagged
+      const KnotDesc d = P.desc[k];
       if (!gm_done) {
         phi_gm = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, 15u);
         xi_gm = Xi;
@@ -128,13 +173,20 @@ __global__ __launch_bounds__(BLK) void k_calibrate(CalArgs C) {
       phi_em = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, 15u);
       done = true;
     }
+    if (done) {
+      double* out = C.rec + gid * REC;
+      out[0] = (double)phi_em - (double)phi_gm;
+      out[1] = (double)phi_gm;
+      out[2] = (double)xi_gm;
+      out[3] = (double)K_gm;
+      out[4] = (double)K;
+      active = false;
+    }
   }
-  double* out = C.rec + gid * REC;
-  out[0] = (double)phi_em - (double)phi_gm;
-  out[1] = (double)phi_gm;
-  out[2] = (double)xi_gm;
-  out[3] = (double)K_gm;
-  out[4] = (double)K;
+}
+
+__global__ void k_zero_counter(unsigned long long* c) {
+  if (threadIdx.x == 0) *c = 0ull;
 }
 
 // Per-knot sums of the path records: one wave per knot, lane l takes paths
@@ -170,8 +222,9 @@ __global__ __launch_bounds__(BLK) void k_calibrate_sum(const double* __restrict_
 
 template <int KIND, bool F64>
 hipError_t launch_kind(const CalArgs& C, bool cv, hipStream_t stream) {
+  // persistent grid: enough workgroups to fill the device, fewer for small runs
   const int64_t threads = C.n * C.n_paths;
-  const unsigned grid = (unsigned)((threads + BLK - 1) / BLK);
+  const unsigned grid = (unsigned)std::min<int64_t>((threads + BLK - 1) / BLK, 2048);
   if (cv) hipLaunchKernelGGL((k_calibrate<KIND, F64, true>), dim3(grid), dim3(BLK), 0, stream, C);
   else hipLaunchKernelGGL((k_calibrate<KIND, F64, false>), dim3(grid), dim3(BLK), 0, stream, C);
   return hipGetLastError();
@@ -192,7 +245,10 @@ hipError_t launch_prec(const CalArgs& C, bool cv, hipStream_t stream) {
 
 }  // namespace
 
-size_t calibrate_scratch_bytes(int64_t n, int32_t n_paths) { return (size_t)n * n_paths * REC * sizeof(double); }
+// the path records, then the path counter (256-byte aligned)
+size_t calibrate_scratch_bytes(int64_t n, int32_t n_paths) {
+  return ((size_t)n * n_paths * REC * sizeof(double) + 255) / 256 * 256 + 256;
+}
 
 hipError_t launch_calibrate(const AsmParams& P, int precision, int64_t n, int32_t n_paths, uint32_t inst,
                             const double* u0, double* rec, double* stats, hipStream_t stream) {
@@ -203,6 +259,9 @@ hipError_t launch_calibrate(const AsmParams& P, int precision, int64_t n, int32_
   C.u0 = u0;
   C.inst = inst;
   C.rec = rec;
+  C.counter = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(rec) +
+                                                    ((size_t)n * n_paths * REC * sizeof(double) + 255) / 256 * 256);
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, C.counter);
   const bool cv = P.cv_mode == PDD_CV_GRAD_LUT;
   hipError_t e = precision == PDD_FP64_SAME_STREAM ? launch_prec<true>(C, cv, stream) : launch_prec<false>(C, cv, stream);
   if (e != hipSuccess) return e;

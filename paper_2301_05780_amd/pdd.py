@@ -6,6 +6,7 @@ ABI and raises ``PddError`` on any non-OK status.  There is no fallback:
 if libpdd.so is missing the import of the library fails loudly.
 """
 import ctypes as C
+import functools
 import os
 
 import numpy as np
@@ -161,7 +162,15 @@ def knots_of(w):
 
 
 def pattern(w):
-    """(n, nnz, row_ptr, col_idx) of the workload's system, computed on the host."""
+    """(n, nnz, row_ptr, col_idx) of the workload's system, computed on the host
+    (cached per discretisation; the arrays are shared, read them only)."""
+    d = tuple(float(v) for v in w["domain"])
+    return _pattern(d, int(w["H"]), int(w["m"]), int(w["ext"]))
+
+
+@functools.lru_cache(maxsize=8)
+def _pattern(domain, H, m, ext):
+    w = dict(domain=domain, H=H, m=m, ext=ext)
     part, kn = partition_of(w), knots_of(w)
     n, nnz = C.c_int64(), C.c_int64()
     _check(lib().pdd_pattern(C.byref(part), C.byref(kn), C.byref(n), C.byref(nnz), None, None))
@@ -169,6 +178,8 @@ def pattern(w):
     ci = np.empty(max(nnz.value, 1), dtype=np.int32)
     _check(lib().pdd_pattern(C.byref(part), C.byref(kn), C.byref(n), C.byref(nnz),
                              rp.ctypes.data, ci.ctypes.data))
+    rp.setflags(write=False)
+    ci.setflags(write=False)
     return n.value, nnz.value, rp, ci[:nnz.value]
 
 
