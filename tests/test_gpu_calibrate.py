@@ -105,3 +105,23 @@ def test_calibrate_argument_validation(ctx):
     with pytest.raises(pdd.PddError) as e:
         ctx.calibrate(w, u, 10, cv=pdd.CVSpec("network", params=params))
     assert e.value.status == pdd.EINVAL
+
+
+@pytest.mark.parametrize("n_paths", [1, 3, 65])
+def test_persistent_claims_cover_every_path(ctx, n_paths):
+    """Path counts that leave the last claims partly empty (1, 3 and 65 paths
+    per knot): float64 sums equal the oracle's, the step totals exactly, so
+    every path ran once."""
+    w = dict(kind="eq43", param=(), domain=(-100.0, 100.0, -100.0, 100.0), H=3, m=4, ext=2, n_paths=n_paths,
+             h=2.0, seed=17, precision="fp64", exit_rule="gm")
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    c = Coefficients("eq43")
+    u0 = _u0(g, c, np.random.default_rng(5))
+    got = ctx.calibrate(w, torch.from_numpy(u0).cuda(), n_paths).cpu().numpy()
+    ctx.sync()
+    ref = oracle_calibrate(g, c, u0, n_paths, w["h"], w["seed"])
+    for k in range(g.n):
+        r = ref[k]
+        scale = n_paths * (1.0 + abs(r[1]) / n_paths) ** 2
+        assert np.all(np.abs(got[k, :6] - r[:6]) <= 1e-11 * scale), k
+        assert np.array_equal(got[k, 6:], r[6:]), k
