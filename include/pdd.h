@@ -343,13 +343,14 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
  * u_knots (device double[n], e.g. pdd_solve of a warm-up assembly) on
  * interface sides and the boundary datum g on the domain boundary.  With
  * run->cv in gradient-table mode, xi (eq. 37) is drawn alongside and taken
- * at the GM exit (run->cv NULL: xi = 0; the network mode and RBF
- * interpolation are not accepted).
+ * at the GM exit (run->cv NULL: xi = 0).  The network mode, RBF
+ * interpolation and h_per_knot are not accepted (PDD_EINVAL,
+ * PDD_EUNSUPPORTED).
  * Path p of knot k draws from the Philox counter (draw, p, k, run->instance)
  * with key run->seed; run->exit_rule, n_paths_per_knot and dump are not used.
  * stats: device double[n * PDD_CAL_WIDTH], the per-knot sums listed at
  * PDD_CAL_WIDTH, each summed over the knot's paths in a fixed order.  Needs
- * n * n_paths * 40 bytes of scratch (at most 16 GiB). */
+ * n * n_paths * 40 bytes (plus 512) of scratch, at most 16 GiB. */
 pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part, const pdd_knots* knots,
                          const pdd_run* run, const double* u_knots, double* stats);
 

@@ -1,10 +1,12 @@
 // Phase II calibration (Sec. 4.1-4.2, eqs. 32-39): mixed Gobet-Menozzi /
 // Euler-Maruyama trajectories scored with the warm-up solution.
 //
-// One thread per path (knot k, path p < N0'), the assembly's random stream,
-// step and exit rules.  A path runs until it leaves the closed patch (the
-// naive exit); on the way, the first step whose iterate is not strictly
-// inside the Gobet-Menozzi-shrunk patch is its GM exit.  Each exit is
+// One lane per path (knot k, path p < N0'), the assembly's random stream,
+// step and exit rules; waves are persistent and claim path ids from a
+// device counter as their lanes fall idle.  A path runs until it leaves the
+// closed patch (the naive exit); on the way, the first step whose iterate
+// is not strictly inside the Gobet-Menozzi-shrunk patch is its GM exit.
+// Each exit is
 // resolved as in the assembly (side choice, projection, hat weights) and
 // scored with u0: phi = Z_K + Y_K u0(P_K), u0 interpolated from the warm-up
 // knot values on interface sides and the boundary datum g on the domain
