@@ -24,6 +24,9 @@ and the control variate xi = Xi at the GM exit (eq. 37).  Per knot:
     paths          N_i = 9 V_i (1 - rho_i^2) / eps^2, rounded to the closest
                    multiple k N_job, k >= 1                               (41)
 
+With interp=("rbf", c) the exit values of u0 use the cardinal functions of
+the side's stencil, as the assembly's interpolation (eq. 21).
+
 Readings: eq. 41 is read as 2 eps / 3 = 2 sqrt(V (1 - rho^2) / N_i); the
 variance is the population variance of the N0 scores; rho^2 = 0 when either
 variance is 0; h_i = h0 when the mean difference is 0.
@@ -105,18 +108,24 @@ def mixed_paths(coef, box, start, word2, instance, n_paths, h, seed, cv=None):
     return gm, em
 
 
-def path_scores(geom, coef, k, rec, u0):
+def path_scores(geom, coef, k, rec, u0, interp=None):
     """phi = Z_K + Y_K u0(P_K) per path, with P_K the resolved exit point of
     ``rec`` (exit_points) and u0 the interpolated knot values u0[j] on
-    interface sides (g at boundary lattice points), g on boundary sides."""
-    ex = exit_points(geom, coef, k, rec)
+    interface sides (g at boundary lattice points), g on boundary sides.
+    interp: None for the hat weights, ("rbf", c) for the cardinal functions
+    of the side's stencil (the assembly's interpolation, eq. 21)."""
+    ex = exit_points(geom, coef, k, rec, interp)
     uex = np.where(ex["boundary"], ex["g_side"], 0.0)
     for p in np.nonzero(~ex["boundary"])[0]:
         side = int(ex["side"][p])
         s = geom.side(k, ("E", "N", "W", "S")[side])
-        q0 = int(ex["q0"][p])
+        if interp is not None:
+            pairs = ex["contribs"][p]
+        else:
+            q0 = int(ex["q0"][p])
+            pairs = ((q0, ex["w0"][p]), (q0 + 1, ex["w1"][p]))
         val = 0.0
-        for q, w in ((q0, ex["w0"][p]), (q0 + 1, ex["w1"][p])):
+        for q, w in pairs:
             j = _lattice_target(geom, k, side, q)
             if j < 0:
                 if s["line"] == "x":
@@ -130,20 +139,20 @@ def path_scores(geom, coef, k, rec, u0):
     return rec["Z"] + rec["Y"] * uex
 
 
-def calibrate_knot(geom, coef, k, u0, n_paths, h, seed, instance=0, cv=None):
+def calibrate_knot(geom, coef, k, u0, n_paths, h, seed, instance=0, cv=None, interp=None):
     """STATS_WIDTH sums of knot k from n_paths mixed trajectories."""
     gm, em = mixed_paths(coef, geom.box[k], (geom.x[k], geom.y[k]), k, instance, n_paths, h, seed, cv)
-    phi_gm = path_scores(geom, coef, k, gm, u0)
-    phi_em = path_scores(geom, coef, k, em, u0)
+    phi_gm = path_scores(geom, coef, k, gm, u0, interp)
+    phi_em = path_scores(geom, coef, k, em, u0, interp)
     xi = gm["Xi"]
     return np.array([np.sum(phi_em - phi_gm), np.sum(phi_gm), np.sum(phi_gm * phi_gm), np.sum(xi),
                      np.sum(xi * xi), np.sum(phi_gm * xi), float(gm["K"].sum()), float(em["K"].sum())])
 
 
-def calibrate(geom, coef, u0, n_paths, h, seed, instance=0, cv=None, knots=None):
+def calibrate(geom, coef, u0, n_paths, h, seed, instance=0, cv=None, knots=None, interp=None):
     """Per-knot STATS_WIDTH sums (rows in knot order; only ``knots`` if given)."""
     ks = range(geom.n) if knots is None else knots
-    return {int(k): calibrate_knot(geom, coef, int(k), u0, n_paths, h, seed, instance, cv) for k in ks}
+    return {int(k): calibrate_knot(geom, coef, int(k), u0, n_paths, h, seed, instance, cv, interp) for k in ks}
 
 
 def plan(stats, n_paths, h0, eps, n_job):

@@ -76,3 +76,39 @@ def test_plan_formulas_on_a_hand_example():
     s2 = s.copy()
     s2[0] = 0.02 * N
     assert np.isclose(plan(s2[None, :], N, 1e-3, 0.01, 100)["h"][0], 2e-3 * 0.01 / 0.06)
+
+
+def test_rbf_scores_by_an_independent_interpolant():
+    """With the RBF interpolation, each exit's u0 value equals scipy's
+    inverse-multiquadric interpolant of the side's stencil values (knot
+    values, g at the boundary lattice points) at the clamped exit point."""
+    from scipy.interpolate import RBFInterpolator
+    g, c = _small(), Coefficients("varcoef")
+    u0 = c.exact(g.x, g.y) + np.random.default_rng(4).normal(0.0, 0.01, g.n)
+    cc = 1.5 * g.dx
+    for k in (1, g.n // 2):
+        gm, em = mixed_paths(c, g.box[k], (g.x[k], g.y[k]), k, 0, 60, 2e-3, 9)
+        phi = path_scores(g, c, k, em, u0, ("rbf", cc))
+        ex = exit_points(g, c, k, em)
+        for p in range(60):
+            o = int(ex["side"][p])
+            s = g.side(k, "ENWS"[o])
+            if s["boundary"]:
+                assert phi[p] == em["Z"][p] + em["Y"][p] * ex["g_side"][p]
+                continue
+            vert = s["line"] == "x"
+            along = em["y"][p] if vert else em["x"][p]
+            a0, da = (g.y0, g.dy) if vert else (g.x0, g.dx)
+            t = min(max((along - a0) / da, s["clo"]), s["chi"])
+            qs = np.arange(s["clo"], s["chi"] + 1)
+            vals = []
+            for q in qs:
+                if q == 0 or q == g.L:
+                    px, py = (g.lattice_x(s["at"]), g.lattice_y(q)) if vert else (g.lattice_x(q), g.lattice_y(s["at"]))
+                    vals.append(c.boundary(np.array([px]), np.array([py]))[0])
+                else:
+                    vals.append(u0[g.index[s["at"], q] if vert else g.index[q, s["at"]]])
+            ip = RBFInterpolator((qs * da)[:, None], np.array(vals), kernel="inverse_multiquadric",
+                                 epsilon=1.0 / cc, degree=-1)
+            ref = em["Z"][p] + em["Y"][p] * ip(np.array([[t * da]]))[0]
+            assert abs(phi[p] - ref) < 1e-9, (k, p)
