@@ -343,9 +343,11 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
  * u_knots (device double[n], e.g. pdd_solve of a warm-up assembly) on
  * interface sides and the boundary datum g on the domain boundary.  With
  * run->cv in gradient-table mode, xi (eq. 37) is drawn alongside and taken
- * at the GM exit (run->cv NULL: xi = 0).  The network mode, RBF
- * interpolation and h_per_knot are not accepted (PDD_EINVAL,
- * PDD_EUNSUPPORTED).
+ * at the GM exit (run->cv NULL: xi = 0).  With run->interp =
+ * PDD_INTERP_RBF_IMQ, u0 at an interface exit is the RBF interpolant of the
+ * side's stencil values (as pdd_assemble interpolates; float64, n * 4 *
+ * stencil-length doubles of extra scratch).  The network mode and
+ * h_per_knot are not accepted (PDD_EINVAL, PDD_EUNSUPPORTED).
  * Path p of knot k draws from the Philox counter (draw, p, k, run->instance)
  * with key run->seed; run->exit_rule, n_paths_per_knot and dump are not used.
  * stats: device double[n * PDD_CAL_WIDTH], the per-knot sums listed at

@@ -103,16 +103,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// 1 / sqrt(x) for x >= c^2 > 0 in float64: the hardware estimate (relative
-// error about 2^-23) refined by one Halley step for the reciprocal square
-// root, y <- y (1 + e/2 + 3 e^2/8) with e = 1 - x y^2, which cubes the
-// relative error (below the float64 rounding of the final step).
-__device__ __forceinline__ double rsqrt_f64(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double e = fma(-x * y, y, 1.0);
-  return fma(y * e, fma(0.375, e, 0.5), y);
-}
-
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);

@@ -40,11 +40,17 @@ struct CalArgs {
   uint32_t inst;                     // fourth Philox counter word
   double* rec;                       // REC doubles per path
   unsigned long long* counter;       // next path id (zeroed before the launch)
+  // RBF interpolation of u0 (nullable: hat weights): per knot and side the
+  // coefficients alpha = Phi^{-1} v of the interpolant of the stencil values
+  // v (knot values, g at boundary lattice points), slot_len per side
+  const double* alpha;
+  int32_t slot_len;
 };
 
 // u0 at the exit point resolved from the flagged sides `fl` (bit o: side o)
 template <int KIND, typename R, bool F64>
-__device__ R exit_value(const AsmParams& P, const KnotDesc& d, const double* u0, R x, R y, uint32_t fl) {
+__device__ R exit_value(const AsmParams& P, const KnotDesc& d, const double* u0, const double* alpha, int SL, R x,
+                        R y, uint32_t fl) {
   const bool fE = fl & 1u, fN = (fl >> 1) & 1u, fW = (fl >> 2) & 1u, fS = (fl >> 3) & 1u;
   const int o = choose_side<R>(x, y, fE, fN, fW, fS, d.line);
   const bool vert = (o == 0 || o == 2);
@@ -54,6 +60,21 @@ __device__ R exit_value(const AsmParams& P, const KnotDesc& d, const double* u0,
     const R a0 = vert ? (R)P.y0 : (R)P.x0, a1 = vert ? (R)P.y1 : (R)P.x1;
     const R pa = fmin(fmax(along, a0), a1);
     return vert ? g_at<KIND>(lpos, pa) : g_at<KIND>(pa, lpos);
+  }
+  if (alpha) {
+    // RBF: u0(z) = sum_i alpha_i phi_c(|z - z_i|) over the side's stencil,
+    // z the exit point clamped to the stencil, in float64
+    const double da = vert ? P.dy : P.dx;
+    const double a0 = vert ? P.y0 : P.x0;
+    const int clo = d.clo[o], S = d.chi[o] - clo + 1;
+    const double zd = fmin(fmax(((double)along - a0) / da, (double)clo), (double)d.chi[o]) * da;
+    const double* a = alpha + ((size_t)d.knot * 4 + o) * SL;
+    double acc = 0.0;
+    for (int i = 0; i < S; ++i) {
+      const double rr = zd - (double)(clo + i) * da;
+      acc = fma(a[i], rsqrt_f64(fma(rr, rr, P.rbf_c2)), acc);
+    }
+    return (R)acc;
   }
   int q0;
   R w;
@@ -84,6 +105,7 @@ __device__ R exit_value(const AsmParams& P, const KnotDesc& d, const double* u0,
 // for the longest path of its wave.  A path's arithmetic is independent of
 // which lane runs it, so the records do not depend on the schedule.
 constexpr int REFILL = 16;
+constexpr int EXIT_BATCH = 16;       // waiting exits that trigger their evaluation
 
 template <int KIND, bool F64, bool CVON>
 __global__ __launch_bounds__(BLK) void k_calibrate(CalArgs C) {
@@ -101,6 +123,11 @@ __global__ __launch_bounds__(BLK) void k_calibrate(CalArgs C) {
   R phi_gm = 0, xi_gm = 0, phi_em = 0;
   uint32_t K = 0, K_gm = 0, j = 0;
   bool gm_done = false;
+  // exits waiting for their u0 value: the GM exit's state, and the naive
+  // exit (the path's final state, the lane stepping no further)
+  bool pgm = false, pem = false;
+  R gmx = 0, gmy = 0, gmY = 0, gmZ = 0;
+  uint32_t gmfl = 0, emfl = 0;
   while (true) {
     // ---- refill idle lanes with the next path ids -----------------------
     const uint64_t idle = __ballot(!active);
@@ -135,55 +162,130 @@ __global__ __launch_bounds__(BLK) void k_calibrate(CalArgs C) {
       if (exhausted) break;
       continue;
     }
-    if (!active) continue;
-    // ---- one draw, up to two steps --------------------------------------
-    const U4 r = philox10(j, p, (uint32_t)k, C.inst, P.key0, P.key1);
-    bool done = false;
-    for (int half = 0; half < 2 && !done; ++half) {
-      R z0, z1;
-      if constexpr (F64) box_muller(uniform64(half ? r.c : r.a), uniform64(half ? r.d : r.b), z0, z1);
-      else box_muller(uniform32(half ? r.c : r.a), uniform32(half ? r.d : r.b), z0, z1);
-      R gx = 0, gy = 0;
-      if constexpr (CVON) grad_lut(P, x, y, gx, gy);
-      em_step<KIND, R, CVON>(P.coef, h, sq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
-      ++K;
-      if (!gm_done) {
-        const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_GM, sq, line, egm, x, y);
+    // ---- one draw, up to two steps (lanes whose path has not ended) ------
+    if (active && !pem) {
+      const U4 r = philox10(j, p, (uint32_t)k, C.inst, P.key0, P.key1);
+      for (int half = 0; half < 2 && !pem; ++half) {
+        R z0, z1;
+        if constexpr (F64) box_muller(uniform64(half ? r.c : r.a), uniform64(half ? r.d : r.b), z0, z1);
+        else box_muller(uniform32(half ? r.c : r.a), uniform32(half ? r.d : r.b), z0, z1);
+        R gx = 0, gy = 0;
+        if constexpr (CVON) grad_lut(P, x, y, gx, gy);
+        em_step<KIND, R, CVON>(P.coef, h, sq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+        ++K;
+        if (!gm_done) {
+          const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_GM, sq, line, egm, x, y);
+          if (fl) {
+            gmx = x; gmy = y; gmY = Y; gmZ = Z; gmfl = fl;
+            xi_gm = Xi;
+            K_gm = K;
+            gm_done = true;
+            pgm = true;
+          }
+        }
+        const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_NAIVE, sq, line, env, x, y);
         if (fl) {
-          const KnotDesc d = P.desc[k];
-          phi_gm = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, fl);
+          emfl = fl;
+          pem = true;
+        }
+      }
+      ++j;
+      if (!pem && 2 * j >= (1u << 24) - 2) {      // step cap: every side flagged
+        if (!gm_done) {
+          gmx = x; gmy = y; gmY = Y; gmZ = Z; gmfl = 15u;
           xi_gm = Xi;
           K_gm = K;
           gm_done = true;
+          pgm = true;
         }
+        emfl = 15u;
+        pem = true;
       }
-      const uint32_t fl = exit_sides<KIND, R>(P.coef, PDD_EXIT_NAIVE, sq, line, env, x, y);
-      if (fl) {
+    }
+    // ---- exit values, for the waiting exits together -----------------------
+    // u0 at an exit (a loop over the stencil with RBF weights) runs once
+    // enough lanes wait for it, or when no lane can step any more, so that
+    // the wave does not take that loop for every single exit.
+    const uint64_t waiting = __ballot(pgm || pem);
+    if (waiting != 0 && (__popcll(waiting) >= EXIT_BATCH || __ballot(active && !pem) == 0)) {
+      if (pgm) {
         const KnotDesc d = P.desc[k];
-        phi_em = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, fl);
-        done = true;
+        phi_gm = gmZ + gmY * exit_value<KIND, R, F64>(P, d, C.u0, C.alpha, C.slot_len, gmx, gmy, gmfl);
+        pgm = false;
+      }
+      if (pem) {
+        const KnotDesc d = P.desc[k];
+        phi_em = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, C.alpha, C.slot_len, x, y, emfl);
+        double* out = C.rec + gid * REC;
+        out[0] = (double)phi_em - (double)phi_gm;
+        out[1] = (double)phi_gm;
+        out[2] = (double)xi_gm;
+        out[3] = (double)K_gm;
+        out[4] = (double)K;
+        pem = false;
+        active = false;
       }
     }
-    ++j;
-    if (!done && 2 * j >= (1u << 24) - 2) {      // step cap: every side flagged
-      const KnotDesc d = P.desc[k];
-      if (!gm_done) {
-        phi_gm = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, 15u);
-        xi_gm = Xi;
-        K_gm = K;
-      }
-      phi_em = Z + Y * exit_value<KIND, R, F64>(P, d, C.u0, x, y, 15u);
-      done = true;
+  }
+}
+
+// The RBF coefficients of u0 on every interface side: one wave per (knot,
+// side); the stencil values in LDS, then alpha_i = sum_j (Phi^{-1})_ji v_j
+// (Phi^{-1} symmetric: lane i reads column i).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_calib_alpha(AsmParams P, int64_t n, int32_t SL, const double* u0,
+                                                     double* alpha) {
+  extern __shared__ double vs[];
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= 4 * n) return;
+  const int64_t k = w >> 2;
+  const int o = (int)(w & 3);
+  const KnotDesc& d = P.desc[k];
+  if ((d.bmask >> o) & 1) return;
+  double* v = vs + (size_t)(threadIdx.x >> 6) * SL;
+  const bool vert = (o == 0 || o == 2);
+  const int clo = d.clo[o], S = d.chi[o] - clo + 1;
+  for (int i = lane; i < S; i += 64) {
+    const int q = clo + i;
+    if (q == 0 || q == P.L) {
+      const double qc = vert ? P.y0 + (double)q * P.dy : P.x0 + (double)q * P.dx;
+      v[i] = vert ? g_at<KIND>(d.line[o], qc) : g_at<KIND>(qc, d.line[o]);
+    } else {
+      const int lx = vert ? d.at[o] : q, ly = vert ? q : d.at[o];
+      v[i] = u0[P.lattice[(size_t)ly * (P.L + 1) + lx]];
     }
-    if (done) {
-      double* out = C.rec + gid * REC;
-      out[0] = (double)phi_em - (double)phi_gm;
-      out[1] = (double)phi_gm;
-      out[2] = (double)xi_gm;
-      out[3] = (double)K_gm;
-      out[4] = (double)K;
-      active = false;
-    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const double* Mi = P.rbf_inv + (vert ? P.rbf_half : 0) + rbf_block_offset(S);
+  for (int i = lane; i < S; i += 64) {
+    double acc = 0.0;
+    for (int j = 0; j < S; ++j) acc = fma(Mi[(size_t)j * S + i], v[j], acc);
+    alpha[(size_t)w * SL + i] = acc;
+  }
+}
+
+template <int KIND>
+hipError_t launch_alpha_kind(const AsmParams& P, int64_t n, int32_t SL, const double* u0, double* alpha,
+                             hipStream_t stream) {
+  const int64_t waves = 4 * n;
+  const unsigned grid = (unsigned)((waves + 3) / 4);
+  const size_t lds = (size_t)4 * SL * sizeof(double);
+  hipLaunchKernelGGL((k_calib_alpha<KIND>), dim3(grid), dim3(256), lds, stream, P, n, SL, u0, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_alpha(const AsmParams& P, int64_t n, int32_t SL, const double* u0, double* alpha,
+                        hipStream_t stream) {
+  switch (P.coef.kind) {
+    case PDD_COEF_POISSON: return launch_alpha_kind<PDD_COEF_POISSON>(P, n, SL, u0, alpha, stream);
+    case PDD_COEF_VARCOEF: return launch_alpha_kind<PDD_COEF_VARCOEF>(P, n, SL, u0, alpha, stream);
+    case PDD_COEF_AMPLITUDE: return launch_alpha_kind<PDD_COEF_AMPLITUDE>(P, n, SL, u0, alpha, stream);
+    case PDD_COEF_LUT: return launch_alpha_kind<PDD_COEF_LUT>(P, n, SL, u0, alpha, stream);
+    case PDD_COEF_CONSTSOL: return launch_alpha_kind<PDD_COEF_CONSTSOL>(P, n, SL, u0, alpha, stream);
+    case PDD_COEF_EQ43: return launch_alpha_kind<PDD_COEF_EQ43>(P, n, SL, u0, alpha, stream);
+    default: return launch_alpha_kind<PDD_COEF_EXITTIME>(P, n, SL, u0, alpha, stream);
   }
 }
 
@@ -253,8 +355,15 @@ size_t calibrate_scratch_bytes(int64_t n, int32_t n_paths) {
 }
 
 hipError_t launch_calibrate(const AsmParams& P, int precision, int64_t n, int32_t n_paths, uint32_t inst,
-                            const double* u0, double* rec, double* stats, hipStream_t stream) {
+                            const double* u0, double* rec, double* stats, hipStream_t stream, double* alpha,
+                            int32_t slot_len) {
   CalArgs C;
+  C.alpha = alpha;
+  C.slot_len = slot_len;
+  if (alpha) {
+    const hipError_t e = launch_alpha(P, n, slot_len, u0, alpha, stream);
+    if (e != hipSuccess) return e;
+  }
   C.P = P;
   C.n = n;
   C.n_paths = n_paths;

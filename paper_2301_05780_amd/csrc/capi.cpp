@@ -301,8 +301,6 @@ pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_parti
   if (run->n_paths < 1 || run->n_paths > INT32_MAX) return fail(ctx, PDD_EINVAL, "pdd_calibrate: need 1 <= n_paths < 2^31");
   if (run->cv && run->cv->mode == PDD_CV_NETWORK)
     return fail(ctx, PDD_EINVAL, "pdd_calibrate: xi is drawn with the gradient table (run.cv mode GRAD_LUT) or not at all");
-  if (run->interp != PDD_INTERP_HAT)
-    return fail(ctx, PDD_EUNSUPPORTED, "pdd_calibrate: u0 is interpolated with the hat weights (run.interp 0)");
   if (run->h_per_knot) return fail(ctx, PDD_EUNSUPPORTED, "pdd_calibrate: one time step h0 (run.h_per_knot NULL)");
   pdd_run r = *run;
   r.exit_rule = PDD_EXIT_GM;
@@ -322,8 +320,16 @@ pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_parti
   AsmParams P;
   fill_asm_params(*gc, *coeffs, r, P);
   if ((st = prepare_lut_bound(ctx, *coeffs, r, P, false)) != PDD_OK) return st;
+  double* alpha = nullptr;
+  if (r.interp == PDD_INTERP_RBF_IMQ) {
+    // the stencil inverses, and scratch for the per-side RBF coefficients of u0
+    if ((st = prepare_rbf(ctx, gc->g, r, P, false)) != PDD_OK) return st;
+    const size_t abytes = (size_t)gc->g.n * 4 * gc->g.slot_len * sizeof(double);
+    if ((e = ctx->calib_alpha.reserve(abytes)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(rbf coefficients)");
+    alpha = ctx->calib_alpha.as<double>();
+  }
   e = launch_calibrate(P, r.precision, gc->g.n, (int32_t)r.n_paths, r.instance, u_knots, ctx->calib_scratch.as<double>(),
-                       stats, ctx->stream);
+                       stats, ctx->stream, alpha, gc->g.slot_len);
   return check_hip(ctx, e, "launch calibrate");
 }
 

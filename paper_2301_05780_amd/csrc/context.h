@@ -117,7 +117,7 @@ struct pdd_ctx {
   std::vector<pdd::TuneEntry> tune_cache;
   pdd::DeviceBuffer partial;
   pdd::DeviceBuffer solve_scratch, solve_flag;
-  pdd::DeviceBuffer collect_scratch, mlp_scratch, calib_scratch;
+  pdd::DeviceBuffer collect_scratch, mlp_scratch, calib_scratch, calib_alpha;
   // launch overrides (0 = automatic), set by the tuner
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
   int schedule = PDD_SCHEDULE_STATIC;
@@ -158,6 +158,9 @@ pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& 
 // LUT family in float32: enqueue the cell-major copy of the table and point
 // P.coef.cells at it (no-op otherwise).
 pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
+// RBF interpolation: build (once per geometry and shape parameter) and
+// upload the inverses of the stencil matrices; point P.rbf_inv at them.
+pdd_status prepare_rbf(pdd_ctx* ctx, const Geometry& g, const pdd_run& run, AsmParams& P, bool capturing);
 pdd_status run_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_partition& part, const pdd_knots& kn,
                               const double* u_knots, int64_t n_pts, const double* xy, const pdd_run& run, double* u,
                               double* se);

@@ -71,6 +71,16 @@ __device__ __forceinline__ float fsqrt(float v) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ float fexp(float v) { return __builtin_amdgcn_exp2f(v * 1.4426950408889634f); }
 __device__ __forceinline__ float flog2(float v) { return __builtin_amdgcn_logf(v); }
 
+// 1 / sqrt(x) for x >= c^2 > 0 in float64: the hardware estimate (relative
+// error about 2^-23) refined by one Halley step for the reciprocal square
+// root, y <- y (1 + e/2 + 3 e^2/8) with e = 1 - x y^2, which cubes the
+// relative error (below the float64 rounding of the final step).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
 // Box-Muller: two N(0,1) from two uniforms, rho = sqrt(-2 ln u0), theta = 2 pi u1.
 __device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
   const float rho = fsqrt(-1.3862943611198906f * flog2(u0));   // -2 ln 2 log2(u0)

@@ -147,8 +147,11 @@ hipError_t launch_collect(const AsmParams& P, int64_t n, int32_t paths_per_knot,
 // Phase II calibration: per-path records (scratch of calibrate_scratch_bytes)
 // and their per-knot sums, stats[n * PDD_CAL_WIDTH]
 size_t calibrate_scratch_bytes(int64_t n, int32_t n_paths);
+// alpha (nullable): RBF interpolation of u0, scratch of 4 n slot_len doubles
+// for the per-side coefficients (P.rbf_inv and P.rbf_c2 set)
 hipError_t launch_calibrate(const AsmParams& P, int precision, int64_t n, int32_t n_paths, uint32_t inst,
-                            const double* u0, double* rec, double* stats, hipStream_t stream);
+                            const double* u0, double* rec, double* stats, hipStream_t stream,
+                            double* alpha = nullptr, int32_t slot_len = 0);
 hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipStream_t stream);
 // Cell-major copy of a LUT (lut.hip): cells[(j (n-1) + i) 8 + q], (n-1)^2 cells of 128 B.
 hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream);

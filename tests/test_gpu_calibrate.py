@@ -125,3 +125,29 @@ def test_persistent_claims_cover_every_path(ctx, n_paths):
         scale = n_paths * (1.0 + abs(r[1]) / n_paths) ** 2
         assert np.all(np.abs(got[k, :6] - r[:6]) <= 1e-11 * scale), k
         assert np.array_equal(got[k, 6:], r[6:]), k
+
+
+@pytest.mark.parametrize("kappa", [1e6, 1e10])
+def test_rbf_scores_fp64_same_stream(ctx, kappa):
+    """u0 at the exits interpolated with the RBF cardinal functions: the GPU
+    applies the stencil inverse to the values once per side and sums
+    alpha_i phi_i per exit, the oracle solves per exit; they agree to
+    S kappa u of the scores' scale."""
+    from oracle.rbf import shape_for_condition, condition
+    w = dict(kind="varcoef", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=3, m=4, ext=2, n_paths=120, h=2e-3, seed=33,
+             precision="fp64", exit_rule="gm")
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    S = min(2 * w["m"] + 2 * w["ext"] + 1, g.L + 1)
+    cc = shape_for_condition(S, g.dx, kappa)
+    k_ = condition(np.arange(S) * g.dx, cc)
+    w.update(interp="rbf", rbf_c=cc)
+    c = Coefficients("varcoef")
+    u0 = _u0(g, c, np.random.default_rng(6))
+    got = ctx.calibrate(w, torch.from_numpy(u0).cuda(), w["n_paths"]).cpu().numpy()
+    ctx.sync()
+    ref = oracle_calibrate(g, c, u0, w["n_paths"], w["h"], w["seed"], interp=("rbf", cc))
+    for k in range(g.n):
+        r = ref[k]
+        scale = w["n_paths"] * (1.0 + abs(r[1]) / w["n_paths"]) ** 2
+        assert np.all(np.abs(got[k, :3] - r[:3]) <= (1e-11 + S * k_ * 2.0 ** -53) * scale), k
+        assert np.array_equal(got[k, 6:], r[6:]), k

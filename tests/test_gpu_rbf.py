@@ -177,9 +177,6 @@ def test_rbf_arguments_and_unsupported_combinations(ctx):
     with pytest.raises(pdd.PddError) as e:
         ctx.assemble_batch([wr, dict(wr, instance=1)])
     assert e.value.status == pdd.EUNSUPPORTED
-    with pytest.raises(pdd.PddError) as e:
-        ctx.calibrate(wr, torch.zeros(n, dtype=torch.float64, device="cuda"), 16)
-    assert e.value.status == pdd.EUNSUPPORTED
     # the context stays usable
     out = ctx.assemble(wr)
     ctx.sync()
