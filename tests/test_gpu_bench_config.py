@@ -132,6 +132,31 @@ def test_sec5_phase1_in_the_timed_configuration(ctx):
         ctx.set_spare_rows(-1)
 
 
+def test_sec5_calibration_at_full_size(ctx):
+    """The Sec. 5 Phase II as the benchmark runs it (11,241 knots, 1000 mixed
+    paths each, RBF scores with a warm-up-like u0): the sampled knots' mean
+    scores within 3 standard errors of the oracle's and the step totals
+    close (float32 paths against float64)."""
+    from oracle.calibrate import calibrate as oracle_calibrate
+    w = workloads.sec5()
+    c = pdd.rbf_shape(191, 200.0 / 630, w["rbf_condition"])
+    w = dict(w, rbf_c=c)
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    co = Coefficients("eq43")
+    u0 = co.exact(g.x, g.y) + np.random.default_rng(12).normal(0.0, 0.02, g.n)
+    stats = ctx.calibrate(w, torch.from_numpy(u0).cuda(), w["n_paths"], seed=3).cpu().numpy()
+    ctx.sync()
+    assert np.all(np.isfinite(stats))
+    N = w["n_paths"]
+    knots = np.random.default_rng(13).choice(g.n, 2, replace=False)
+    ref = oracle_calibrate(g, co, u0, N, w["h"], 3, knots=knots, interp=("rbf", c))
+    for k in knots:
+        r = ref[int(k)]
+        mean, var = r[1] / N, max(r[2] / N - (r[1] / N) ** 2, 0.0)
+        assert abs(stats[k, 1] / N - mean) <= 3 * np.sqrt(var / N) + 1e-6, k
+        assert abs(stats[k, 7] / r[7] - 1.0) < 5e-3, k
+
+
 def test_large_lut_in_the_timed_configuration(ctx):
     w = workloads.large_lut()
     tab = workloads.poisson_lut(w["lut_n"])
