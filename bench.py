@@ -356,11 +356,14 @@ def sec5_experiment(ctx, seed=0):
     """The paper's numerical experiment (Sec. 5, eqs. 42-43) on one GPU, its
     three phases as in Sec. 4.3: Phase I, the warm-up assembly with N0 = 1000
     paths per knot at h0 = 0.08 (RBF interpolation, float32 paths) and its
-    solve; Phase II, the calibration with N0' = 1000 mixed GM/EM paths per
-    knot scored with the warm-up solution (u0 interpolated with the same RBF
-    weights, no control variate: rho^2 = 0); Phase III, the production assembly with
-    the per-knot path counts of eq. 41 and time steps of eq. 40.
-    The Phase I and III launch shapes are autotuned first.  Reports each
+    solve; the learned control variate trained on the warm-up's paths and
+    baked into a gradient table; Phase II, the calibration with N0' = 1000
+    mixed GM/EM paths per knot scored with the warm-up solution (u0
+    interpolated with the same RBF weights, xi drawn with the table); Phase
+    III, the production assembly with the control variate and
+    the per-knot path counts of eq. 41 and time steps of eq. 40.  Phases II
+    and III are repeated without the control variate (rho^2 = 0).  The
+    Phase I and III launch shapes are autotuned first.  Reports each
     phase's GPU time and path-steps and the interface errors against u* (the
     paper prints Phase I RMSE 0.016, max 0.074 and Phase III RMSE 0.0044,
     max 0.0224)."""
@@ -400,33 +403,52 @@ def sec5_experiment(ctx, seed=0):
     out1, ms1 = timed(lambda: ctx.assemble(w, out=o1))
     steps1 = float(out1["diag"].view(-1, 8)[:, 0].sum().item())
     u0, e1 = errors(out1)
-    ctx.calibrate(w, u0, w["n_paths"], seed=seed + 1)        # scratch allocation outside the timed region
-    stats, ms2 = timed(lambda: ctx.calibrate(w, u0, w["n_paths"], seed=seed + 1))
-    st = stats.cpu().numpy()
-    pl = pdd.calibration_plan(st, w["n_paths"], w["h"], w["eps"], w["n_job"])
-    h3 = float(pl["h"].min())
-    w3 = dict(w, seed=seed + 2)
-    ctx.set_launch(0, 0, 0)
-    ctx.set_refill(1)
-    ctx.set_spare_rows(-1)
-    o3, shape3 = tune(w3, n_paths_per_knot=pl["n_paths"], h_per_knot=pl["h"])
-    out3, ms3 = timed(lambda: ctx.assemble(w3, out=o3, n_paths_per_knot=pl["n_paths"], h_per_knot=pl["h"]))
-    ctx.set_launch(0, 0, 0)
-    ctx.set_refill(1)
-    ctx.set_spare_rows(-1)
-    steps3 = float(out3["diag"].view(-1, 8)[:, 0].sum().item())
-    _, e3 = errors(out3)
+    # the learned control variate (eqs. 37-38): pairs from the method's own
+    # paths scored with u0 (hat targets), Adam on the GPU, grad v baked into
+    # a 513^2 table
+    from paper_2301_05780_amd import cv as cvmod
+    params, info = cvmod.fit(ctx, dict(w, interp="hat"), u0, paths_per_knot=32, points_per_path=16, epochs=8)
+    table = ctx.mlp_bake(params, w, 513)
+    spec = pdd.CVSpec("grad_lut", table=table)
+    training = {"pairs": info["pairs"], "adam_steps": info["steps"], "gpu_ms": info["collect_ms"] + info["train_ms"]}
+
+    def phases23(cvs, seed2, seed3):
+        """Phase II (with or without the control variate) and Phase III from its plan."""
+        ctx.calibrate(w, u0, w["n_paths"], seed=seed2, cv=cvs)      # scratch allocation outside the timed region
+        stats, ms2 = timed(lambda: ctx.calibrate(w, u0, w["n_paths"], seed=seed2, cv=cvs))
+        st = stats.cpu().numpy()
+        pl = pdd.calibration_plan(st, w["n_paths"], w["h"], w["eps"], w["n_job"])
+        h3 = float(pl["h"].min())
+        w3 = dict(w, seed=seed3)
+        ctx.set_launch(0, 0, 0)
+        ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
+        o3, shape3 = tune(w3, cv=cvs, n_paths_per_knot=pl["n_paths"], h_per_knot=pl["h"])
+        out3, ms3 = timed(lambda: ctx.assemble(w3, out=o3, cv=cvs, n_paths_per_knot=pl["n_paths"], h_per_knot=pl["h"]))
+        ctx.set_launch(0, 0, 0)
+        ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
+        steps3 = float(out3["diag"].view(-1, 8)[:, 0].sum().item())
+        _, e3 = errors(out3)
+        p2 = {"gpu_ms": ms2, "path_steps": float(st[:, 7].sum()), "mean_bias_bound": float(pl["bias"].mean()),
+              "mean_rho2": float(pl["rho2"].mean()), "knots_with_h_below_h0": int(np.sum(pl["h"] < w["h"])),
+              "h_min": h3, "paths_total": int(pl["n_paths"].sum()), "paths_median": float(np.median(pl["n_paths"]))}
+        p3 = dict(e3, h_min=h3, h_median=float(np.median(pl["h"])), gpu_ms=ms3, path_steps=steps3,
+                  path_steps_per_s=steps3 / ms3 * 1e3, launch=list(shape3))
+        return p2, p3
+
+    p2, p3 = phases23(spec, seed + 1, seed + 2)
+    p2_plain, p3_plain = phases23(None, seed + 1, seed + 2)
     return {
         "workload": ("Lap u = f on [-100,100]^2, u* of eq. 43, 10x10 subdomains, 63 lattice intervals per "
                      f"subdomain side, stencils widened by {w['ext']}, {len(ue)} knots, RBF c = {w['rbf_c']:.4g} "
                      f"(condition number {w['rbf_condition']:.0e} at {S} points)"),
         "phase1": dict(e1, n_paths=w["n_paths"], h=w["h"], gpu_ms=ms1, path_steps=steps1,
                        path_steps_per_s=steps1 / ms1 * 1e3, launch=list(shape1)),
-        "phase2": {"gpu_ms": ms2, "path_steps": float(st[:, 7].sum()), "mean_bias_bound": float(pl["bias"].mean()),
-                   "knots_with_h_below_h0": int(np.sum(pl["h"] < w["h"])), "h_min": h3,
-                   "paths_total": int(pl["n_paths"].sum()), "paths_median": float(np.median(pl["n_paths"]))},
-        "phase3": dict(e3, h_min=h3, h_median=float(np.median(pl["h"])), gpu_ms=ms3, path_steps=steps3,
-                       path_steps_per_s=steps3 / ms3 * 1e3, launch=list(shape3)),
+        "cv_training": training,
+        "phase2": p2,
+        "phase3": p3,
+        "without_control_variate": {"phase2": p2_plain, "phase3": p3_plain},
         "paper": {"phase1": {"rmse": 0.016, "max_error": 0.074}, "phase3": {"rmse": 0.0044, "max_error": 0.0224}},
     }
 

@@ -133,7 +133,10 @@ enum { PDD_CAL_WIDTH = 8 };    /* per knot: sum(phi_EM - phi_GM), sum phi_GM, su
 /* Control variate of eqs. (37)-(38): Xi accumulates -Y (sigma^T grad v) . dW
  * and is added to b only; the mean of the estimator is unchanged for any v.
  * NETWORK: params = float32[PDD_MLP_PARAMS] laid out W1[64][2], b1[64],
- * W2[64][64] (out, in), b2[64], w3[64], b3 (device).
+ * W2[64][64] (out, in), b2[64], w3[64], b3 (device).  The network's input is
+ * the point in the domain's unit coordinates ((x - x0)/(x1 - x0),
+ * (y - y0)/(y1 - y0)), so one architecture serves any domain; grad v is
+ * taken with respect to x and y (chain rule).
  * GRAD_LUT: grad_lut = float32 [lut_n][lut_n][2] node-centred over the domain
  * (device). */
 typedef struct pdd_cv {
@@ -389,7 +392,9 @@ pdd_status pdd_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed);
 
 /* v and/or grad v of the 2-64-64-1 tanh network at n points (float32, device
  * arrays: params[PDD_MLP_PARAMS], xy[2n], v[n] nullable, grad[2n] nullable;
- * n = 0 does nothing, and xy, v and grad may then all be NULL). */
+ * n = 0 does nothing, and xy, v and grad may then all be NULL).  xy and grad
+ * are in the network's own (unit) coordinates, as pdd_collect_training
+ * writes them. */
 pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad);
 
 /* Gradient of the loss L = mean_i (v(x_i) - t_i)^2 / 2 over the n points with
@@ -411,7 +416,9 @@ pdd_status pdd_mlp_train(pdd_ctx* ctx, float* params, float* adam_m, float* adam
                          int32_t steps, int32_t step0, float lr, float* losses);
 
 /* grad v on the lut_n x lut_n node grid of the partition's domain, the table
- * read by PDD_CV_GRAD_LUT: grad_lut[(j lut_n + i) 2 + d] (device). */
+ * read by PDD_CV_GRAD_LUT: grad_lut[(j lut_n + i) 2 + d] (device); node
+ * (i, j) is the network input (i, j)/(lut_n - 1), and the gradient is scaled
+ * to the domain's coordinates. */
 pdd_status pdd_mlp_bake_grad_lut(pdd_ctx* ctx, const float* params, const pdd_partition* part, int32_t lut_n,
                                  float* grad_lut);
 
@@ -420,7 +427,8 @@ pdd_status pdd_mlp_bake_grad_lut(pdd_ctx* ctx, const float* params, const pdd_pa
  * assembly), the first points_per_path iterates X_n receive the tail score
  * (Z_K + Y_K u(exit) - Z_n) / Y_n, u at the exit interpolated from u0 (device,
  * the solved knot values) or the boundary datum.  Outputs (device, slot
- * (k paths_per_knot + p) points_per_path + n): xy[2 slots], target[slots];
+ * (k paths_per_knot + p) points_per_path + n): xy[2 slots] (the iterate in
+ * the domain's unit coordinates, the network's input), target[slots];
  * slots past a path's exit get a NaN target.  run.cv must be NULL and
  * run.interp PDD_INTERP_HAT (else PDD_EUNSUPPORTED). */
 pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,

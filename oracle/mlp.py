@@ -103,14 +103,20 @@ def train(theta, X, T, order, batch, lr):
 
 
 class NetworkCV:
-    """Adapter giving the assembly oracle grad v at path points."""
+    """Adapter giving the assembly oracle grad v at path points.  The
+    network's input is the point in the domain's unit coordinates
+    ((x - x0) / (x1 - x0), (y - y0) / (y1 - y0)); the gradient is taken with
+    respect to the domain's coordinates (chain rule)."""
 
-    def __init__(self, theta):
+    def __init__(self, theta, domain=(0.0, 1.0, 0.0, 1.0)):
         self.theta = np.asarray(theta, dtype=np.float64)
+        self.x0, x1, self.y0, y1 = (float(v) for v in domain)
+        self.sx, self.sy = 1.0 / (x1 - self.x0), 1.0 / (y1 - self.y0)
 
     def grad(self, x, y):
-        g = grad_input(self.theta, np.stack([x, y], axis=1))
-        return g[:, 0], g[:, 1]
+        u = np.stack([(x - self.x0) * self.sx, (y - self.y0) * self.sy], axis=1)
+        g = grad_input(self.theta, u)
+        return g[:, 0] * self.sx, g[:, 1] * self.sy
 
 
 class GradLutCV:

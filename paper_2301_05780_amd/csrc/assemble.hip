@@ -321,6 +321,9 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   R x = 0, y = 0, Y = 0, Z = 0, Xi = 0;
   R ehx = 0, ehy = 0, elx = 0, ely = 0;
   R lh = (R)P.h, lsq = (R)P.sqrt_h, la = (R)P.coef.a;   // per lane in batched launches
+  // network control variate: unit coordinates of the domain (x - x0) / (x1 - x0)
+  const R ux0 = (R)P.x0, uy0 = (R)P.y0;
+  const R usx = (R)(1.0 / (P.x1 - P.x0)), usy = (R)(1.0 / (P.y1 - P.y0));
 
   auto geo = [&](const WB& W) __attribute__((always_inline)) -> GeoView<R> {
     GeoView<R> G;
@@ -706,7 +709,12 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       R gx = 0, gy = 0;
       Coef<R> cc;
       auto prep = [&]() __attribute__((always_inline)) {
-        if constexpr (CV == PDD_CV_NETWORK) net_grad_mfma(NL, x, y, gx, gy);
+        if constexpr (CV == PDD_CV_NETWORK) {
+          // the network's input is the point in the domain's unit coordinates
+          net_grad_mfma(NL, (x - ux0) * usx, (y - uy0) * usy, gx, gy);
+          gx *= usx;
+          gy *= usy;
+        }
         if constexpr (COOP) lut_fetch_coop(cpl, x, y, CW, lane, cc);
       };
       auto step = [&](R z0, R z1) __attribute__((always_inline)) {
@@ -739,7 +747,11 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       // grad v at the current (left) point for the per-lane control variates
       auto cv_grad = [&](R& gx, R& gy) __attribute__((always_inline)) {
         if constexpr (CV == PDD_CV_GRAD_LUT) grad_lut(P, x, y, gx, gy);
-        else if constexpr (CV == PDD_CV_NETWORK) net_grad_f64(TH, x, y, gx, gy);
+        else if constexpr (CV == PDD_CV_NETWORK) {
+          net_grad_f64(TH, (x - ux0) * usx, (y - uy0) * usy, gx, gy);
+          gx *= usx;
+          gy *= usy;
+        }
         else { gx = 0; gy = 0; }
       };
       const U4 r = philox10(j, p, kn, inst, P.key0, P.key1);

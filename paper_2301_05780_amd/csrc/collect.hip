@@ -58,8 +58,9 @@ __global__ __launch_bounds__(BLK) void k_collect(CollectArgs C) {
       if (half == 0) box_muller(uniform32(r.a), uniform32(r.b), z0, z1);
       else box_muller(uniform32(r.c), uniform32(r.d), z0, z1);
       if (recorded < S) {
-        C.xy[2 * (slot0 + recorded)] = x;
-        C.xy[2 * (slot0 + recorded) + 1] = y;
+        // the network's input: the point in the domain's unit coordinates
+        C.xy[2 * (slot0 + recorded)] = (x - (float)P.x0) * (float)(1.0 / (P.x1 - P.x0));
+        C.xy[2 * (slot0 + recorded) + 1] = (y - (float)P.y0) * (float)(1.0 / (P.y1 - P.y0));
         C.yz[2 * (slot0 + recorded)] = Y;
         C.yz[2 * (slot0 + recorded) + 1] = Z;
         ++recorded;

@@ -93,12 +93,14 @@ __global__ __launch_bounds__(BLK) void k_mlp_bake(const float* __restrict__ para
   const int64_t total = (int64_t)lut_n * lut_n;
   for (int64_t q = (int64_t)blockIdx.x * BLK + threadIdx.x; q < total; q += (int64_t)gridDim.x * BLK) {
     const int i = (int)(q % lut_n), j = (int)(q / lut_n);
-    const float x = (float)(x0 + (double)i * (x1 - x0) / (double)(lut_n - 1));
-    const float y = (float)(y0 + (double)j * (y1 - y0) / (double)(lut_n - 1));
+    // the network's input: the node in the domain's unit coordinates; the
+    // gradient scaled back to the domain's
+    const float x = (float)((double)i / (double)(lut_n - 1));
+    const float y = (float)((double)j / (double)(lut_n - 1));
     float vv, gx, gy;
     net_eval_f32(th, x, y, vv, gx, gy);
-    out[2 * q] = gx;
-    out[2 * q + 1] = gy;
+    out[2 * q] = gx * (float)(1.0 / (x1 - x0));
+    out[2 * q + 1] = gy * (float)(1.0 / (y1 - y0));
   }
 }
 
