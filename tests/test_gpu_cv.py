@@ -306,3 +306,29 @@ def test_batch_rejects_mismatched_control_variates(ctx):
     with pytest.raises(pdd.PddError) as e:
         ctx.assemble_batch([dict(w, precision="fp64"), dict(w, precision="fp64", instance=1)], cv=spec)
     assert e.value.status == pdd.EUNSUPPORTED
+
+
+def test_network_on_a_non_unit_domain(ctx):
+    """The network sees the domain's unit coordinates: the baked table on
+    [-100, 100]^2 is grad v at the mapped nodes scaled by 1/200, and the
+    float64 same-stream assembly with the per-step network matches the
+    oracle's NetworkCV on that domain."""
+    th = _theta(6)
+    w = dict(kind="eq43", param=(), domain=(-100.0, 100.0, -100.0, 100.0), H=3, m=4, ext=2, n_paths=64, h=2.0,
+             seed=21, precision="fp64", exit_rule="gm")
+    n = 33
+    tab = ctx.mlp_bake(_dev(th, np.float32), w, n).cpu().numpy()
+    xs = np.arange(n) / (n - 1)
+    X, Y = np.meshgrid(xs, xs)
+    ref = omlp.grad_input(th, np.stack([X.ravel(), Y.ravel()], axis=1)).reshape(n, n, 2) / 200.0
+    assert np.allclose(tab, ref, rtol=1e-4, atol=1e-5 * np.abs(ref).max())
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    spec = pdd.CVSpec("network", params=_dev(th, np.float32))
+    ref = to_csr(g, oracle_assemble(g, Coefficients("eq43"), w["n_paths"], w["h"], w["seed"], exit_rule="gm",
+                                    cv=omlp.NetworkCV(th, w["domain"]))["rows"])
+    out = ctx.assemble(w, cv=spec)
+    ctx.sync()
+    val, b, diag = _fetch(out, g)
+    tol = 1e-12 * ref["mass"]
+    assert np.all(np.abs(b - ref["b"]) <= tol)
+    assert np.array_equal(diag[:, :6], ref["diag"][:, :6])

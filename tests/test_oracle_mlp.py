@@ -88,3 +88,24 @@ def test_grad_table_reproduces_bilinear_fields():
     # outside the domain the position is clamped to the boundary
     gx2, _ = cv.grad(np.array([dom[1] + 1.0]), np.array([dom[2]]))
     assert np.isclose(gx2[0], f0(dom[1], dom[2]), atol=1e-6)
+
+
+def test_network_cv_on_a_non_unit_domain():
+    """The control variate's network sees the domain's unit coordinates:
+    NetworkCV.grad equals finite differences, in the domain's coordinates,
+    of v at the mapped point; on the unit square the map is the identity."""
+    from oracle.mlp import NetworkCV, forward
+    rng = np.random.default_rng(8)
+    theta = rng.normal(0.0, 0.3, 4417)
+    dom = (-100.0, 100.0, -60.0, 40.0)
+    cvn = NetworkCV(theta, dom)
+    x, y = rng.uniform(-90, 90, 20), rng.uniform(-50, 30, 20)
+    v = lambda a, b: forward(theta, np.stack([(a - dom[0]) / 200.0, (b - dom[2]) / 100.0], axis=1))[0]
+    e = 1e-3
+    gx, gy = cvn.grad(x, y)
+    assert np.allclose(gx, (v(x + e, y) - v(x - e, y)) / (2 * e), rtol=1e-5, atol=1e-9)
+    assert np.allclose(gy, (v(x, y + e) - v(x, y - e)) / (2 * e), rtol=1e-5, atol=1e-9)
+    u = rng.uniform(0, 1, (20, 2))
+    a = NetworkCV(theta).grad(u[:, 0], u[:, 1])
+    b = NetworkCV(theta, (0.0, 1.0, 0.0, 1.0)).grad(u[:, 0], u[:, 1])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
