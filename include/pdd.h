@@ -409,8 +409,11 @@ pdd_status pdd_mlp_grad(pdd_ctx* ctx, const float* params, int64_t n, const floa
  * (xy[2 n_points], target[n_points]; order entries outside [0, n_points) are
  * skipped; the loss is still averaged over `batch`).  adam_m / adam_s are
  * the moment vectors (device, PDD_MLP_PARAMS each, zero before the first
- * call); losses[steps] (nullable) receives each step's loss.  One workgroup
- * runs the whole sequence (the steps are sequential). */
+ * call); losses[steps] (nullable) receives each step's loss.  Up to a batch
+ * of 1024 one workgroup runs the whole sequence (the steps are sequential);
+ * larger batches spread each step over workgroups of 256 points, whose
+ * gradients are summed in workgroup order before the update (two launches
+ * per step; scratch of about 18 KB per workgroup). */
 pdd_status pdd_mlp_train(pdd_ctx* ctx, float* params, float* adam_m, float* adam_s, int64_t n_points,
                          const float* xy, const float* target, const int32_t* order, int64_t n_order, int32_t batch,
                          int32_t steps, int32_t step0, float lr, float* losses);

@@ -118,6 +118,7 @@ struct pdd_ctx {
   pdd::DeviceBuffer partial;
   pdd::DeviceBuffer solve_scratch, solve_flag;
   pdd::DeviceBuffer collect_scratch, mlp_scratch, calib_scratch, calib_alpha;
+  pdd::DeviceBuffer mlp_wide;        // per-workgroup gradients of the multi-workgroup Adam step
   // launch overrides (0 = automatic), set by the tuner
   int force_block = 0, force_grid = 0, force_per_ticket = 0;
   int schedule = PDD_SCHEDULE_STATIC;

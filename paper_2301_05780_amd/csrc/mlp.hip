@@ -139,11 +139,17 @@ struct TrainArgs {
   int32_t update;         // 0: write the gradient of the first batch to grad_out only
   float* grad_out;
   float* losses;          // per step, nullable
+  // wide steps (update == 0, one step per launch): workgroup g takes the
+  // points [g slice, (g + 1) slice) of the batch of order step `order_step`
+  // and writes its gradient sum (and loss) to grad_out + g GPAD
+  int32_t slice;          // 0: the whole batch in one workgroup
+  int32_t order_step;
 };
 
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int TW = 4;                 // waves per workgroup
+constexpr int WIDE_BATCH = 1024;      // larger batches take the multi-workgroup step
 constexpr int H1S = 68;               // row stride of the h1 copy [point][unit] (16-byte aligned rows)
 constexpr int DZS = 36;               // row stride of the [unit][point] copies
 constexpr int PARAM_PAD = ((MLP_PARAMS + 3) / 4) * 4;
@@ -158,6 +164,7 @@ struct TrainWaveLds {
 constexpr size_t train_lds_bytes() { return PARAM_PAD * sizeof(float) + TW * sizeof(TrainWaveLds); }
 constexpr int OWN = (MLP_PARAMS + TW * 64 - 1) / (TW * 64);   // parameters per thread in Adam
 constexpr int GSTRIDE = PARAM_PAD + 4;                         // one wave's gradient slice (+ loss)
+constexpr int GPAD = PARAM_PAD + 4;                            // one workgroup's gradient (+ loss), wide steps
 static_assert(TW * GSTRIDE * sizeof(float) <= TW * sizeof(TrainWaveLds), "gradient slices fit the wave buffers");
 
 // accumulator register r of a 32 x 32 tile holds row 8 (r / 4) + 4 h + r % 4
@@ -179,7 +186,10 @@ __global__ __launch_bounds__(TW * 64) void k_mlp_train(TrainArgs A) {
   }
   __syncthreads();
   const float inv_b = 1.0f / (float)A.batch;
-  const int rounds = (A.batch + 32 * TW - 1) / (32 * TW);
+  // this workgroup's points of each batch: all of them, or one slice
+  const int pbase = A.slice > 0 ? (int)blockIdx.x * A.slice : 0;
+  const int pend = A.slice > 0 ? min(A.batch, pbase + A.slice) : A.batch;
+  const int rounds = (pend - pbase + 32 * TW - 1) / (32 * TW);
 
   for (int step = 0; step < A.steps; ++step) {
     f32x16 gw2[2][2];
@@ -190,9 +200,9 @@ __global__ __launch_bounds__(TW * 64) void k_mlp_train(TrainArgs A) {
     float g_b2 = 0.0f, g_w3 = 0.0f, g_w1x = 0.0f, g_w1y = 0.0f, g_b1 = 0.0f, g_b3 = 0.0f, loss = 0.0f;
 
     for (int rd = 0; rd < rounds; ++rd) {
-      const int p = rd * 32 * TW + 32 * w + c;
-      const bool inb = p < A.batch;
-      const int64_t oi = ((int64_t)step * A.batch + p) % A.n_order;
+      const int p = pbase + rd * 32 * TW + 32 * w + c;
+      const bool inb = p < pend;
+      const int64_t oi = ((int64_t)(step + A.order_step) * A.batch + p) % A.n_order;
       const int32_t oidx = inb ? A.order[oi] : -1;
       const bool valid = oidx >= 0 && (int64_t)oidx < A.n_points;
       const int32_t idx = valid ? oidx : 0;
@@ -350,11 +360,17 @@ __global__ __launch_bounds__(TW * 64) void k_mlp_train(TrainArgs A) {
     auto gsum = [&](int q) __attribute__((always_inline)) {
       return ((G0[q] + G0[GSTRIDE + q]) + G0[2 * GSTRIDE + q]) + G0[3 * GSTRIDE + q];
     };
-    if (tid == 0 && A.losses) A.losses[step] = gsum(MLP_PARAMS);
     if (!A.update) {
+      if (A.slice > 0) {
+        float* out = A.grad_out + (size_t)blockIdx.x * GPAD;
+        for (int q = tid; q <= MLP_PARAMS; q += TW * 64) out[q] = gsum(q);
+        return;
+      }
+      if (tid == 0 && A.losses) A.losses[step] = gsum(MLP_PARAMS);
       for (int q = tid; q < MLP_PARAMS; q += TW * 64) A.grad_out[q] = gsum(q);
       return;
     }
+    if (tid == 0 && A.losses) A.losses[step] = gsum(MLP_PARAMS);
     // Adam (bias-corrected), beta1 = 0.9, beta2 = 0.999, eps = 1e-8; each
     // thread keeps the moments of the parameters it owns in registers
     const int tstep = A.step0 + step + 1;
@@ -426,9 +442,56 @@ pdd_status run_mlp_bake(pdd_ctx* ctx, const float* params, const pdd_partition& 
   return check_hip(ctx, hipGetLastError(), "launch mlp_bake");
 }
 
+// Adam step of a wide step: the workgroups' gradients summed in workgroup
+// order (fixed), then the same bias-corrected update as the trainer, with the
+// moments in global memory.
+__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ params, float* __restrict__ m,
+                                                  float* __restrict__ s, const float* __restrict__ part, int groups,
+                                                  int tstep, float lr, float* losses) {
+  const float c1 = 1.0f - powf(0.9f, (float)tstep);
+  const float c2 = 1.0f - powf(0.999f, (float)tstep);
+  for (int q = threadIdx.x; q <= MLP_PARAMS; q += 256) {
+    float g = 0.0f;
+    for (int b = 0; b < groups; ++b) g += part[(size_t)b * GPAD + q];
+    if (q == MLP_PARAMS) {
+      if (losses) *losses = g;
+      continue;
+    }
+    const float mq = 0.9f * m[q] + 0.1f * g;
+    const float sq = 0.999f * s[q] + 0.001f * g * g;
+    m[q] = mq;
+    s[q] = sq;
+    params[q] -= lr * (mq / c1) / (sqrtf(sq / c2) + 1e-8f);
+  }
+}
+
 pdd_status run_mlp_train(pdd_ctx* ctx, float* params, float* m, float* s, int64_t n_points, const float* xy,
                          const float* target, const int32_t* order, int64_t n_order, int32_t batch, int32_t steps,
                          int32_t step0, float lr, float* losses, float* grad_out) {
+  // batches above WIDE_BATCH: every step spread over workgroups of 256 points
+  if (grad_out == nullptr && batch > WIDE_BATCH) {
+    const int groups = (batch + 255) / 256;
+    hipError_t e = ctx->mlp_wide.reserve((size_t)groups * GPAD * sizeof(float));
+    if (e != hipSuccess) return check_hip(ctx, e, "hipMalloc(mlp wide)");
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_train), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)train_lds_bytes());
+    if (e != hipSuccess) return check_hip(ctx, e, "hipFuncSetAttribute(mlp_train)");
+    TrainArgs A;
+    A.n_points = n_points;
+    A.params = params; A.m = m; A.s = s; A.xy = xy; A.target = target; A.order = order;
+    A.n_order = n_order; A.batch = batch; A.steps = 1; A.step0 = 0; A.lr = lr;
+    A.update = 0;
+    A.grad_out = ctx->mlp_wide.as<float>();
+    A.losses = nullptr;
+    A.slice = 256;
+    for (int32_t st = 0; st < steps; ++st) {
+      A.order_step = st;
+      hipLaunchKernelGGL(k_mlp_train, dim3(groups), dim3(TW * 64), train_lds_bytes(), ctx->stream, A);
+      hipLaunchKernelGGL(k_mlp_adam, dim3(1), dim3(256), 0, ctx->stream, params, m, s, A.grad_out, groups,
+                         step0 + st + 1, lr, losses ? losses + st : nullptr);
+    }
+    return check_hip(ctx, hipGetLastError(), "launch mlp_train (wide)");
+  }
   TrainArgs A;
   A.n_points = n_points;
   A.params = params; A.m = m; A.s = s; A.xy = xy; A.target = target; A.order = order;
@@ -436,6 +499,8 @@ pdd_status run_mlp_train(pdd_ctx* ctx, float* params, float* m, float* s, int64_
   A.update = grad_out ? 0 : 1;
   A.grad_out = grad_out;
   A.losses = losses;
+  A.slice = 0;
+  A.order_step = 0;
   // more than 64 KiB of LDS for one workgroup (gfx950 allows 160 KiB)
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_train),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)train_lds_bytes());

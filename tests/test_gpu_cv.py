@@ -332,3 +332,28 @@ def test_network_on_a_non_unit_domain(ctx):
     tol = 1e-12 * ref["mass"]
     assert np.all(np.abs(b - ref["b"]) <= tol)
     assert np.array_equal(diag[:, :6], ref["diag"][:, :6])
+
+
+@pytest.mark.parametrize("batch", [1536, 4096])
+def test_wide_adam_steps_against_oracle(ctx, batch):
+    """Batches above 1024 take the multi-workgroup step (gradient slices of
+    256 points summed in workgroup order, Adam in a second kernel): the loss
+    history and the parameter change follow the float64 oracle."""
+    th0 = _theta(7, noise=0.0)
+    rng = np.random.default_rng(11)
+    n = 8192
+    X = rng.uniform(0, 1, size=(n, 2))
+    T = np.cos(2 * X[:, 0]) * X[:, 1] + 0.3 * np.sin(3 * X[:, 1])
+    order = workloads.minibatch_order(n, 3, seed=6)
+    steps = 6                      # batch * steps <= 3 n: the oracle sees the same points
+    Xf, Tf = X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64)
+    th_ref, losses_ref = omlp.train(th0, Xf, Tf, order[:batch * steps], batch, 1e-3)
+    p = _dev(th0, np.float32)
+    m, s = torch.zeros_like(p), torch.zeros_like(p)
+    losses = ctx.mlp_train(p, m, s, _dev(X, np.float32), _dev(T, np.float32), _dev(order, np.int32), batch, steps, 0,
+                           1e-3)
+    ctx.sync()
+    assert np.allclose(losses.cpu().numpy(), losses_ref, rtol=1e-3)
+    d_gpu = p.cpu().numpy().astype(np.float64) - th0
+    d_ref = th_ref - th0
+    assert np.linalg.norm(d_gpu - d_ref) <= 2e-3 * np.linalg.norm(d_ref)
