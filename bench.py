@@ -573,6 +573,8 @@ def main():
     ap.add_argument("--no-rbf", action="store_true", help="skip the RBF and Sec. 5 views of the varcoef line")
     ap.add_argument("--sec5-only", action="store_true",
                     help="print only the Sec. 5 experiment's record (its three phases) and exit")
+    ap.add_argument("--rbf-only", action="store_true",
+                    help="print only the RBF-interpolation view of the varcoef workload and exit")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the launch-shape autotuner before timing (on by default)")
@@ -585,6 +587,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.rbf_only:
+        from paper_2301_05780_amd import pdd, workloads
+        ctx = pdd.Context(0)
+        print(json.dumps({"rbf_interpolation": rbf_view(ctx, workloads.varcoef(args.exit_rule))}), flush=True)
+        ctx.close()
         return
     if args.sec5_only:
         from paper_2301_05780_amd import pdd
