@@ -86,3 +86,18 @@ def test_side_types():
             s = g.side(k, o)
             assert s["boundary"] == (s["at"] in (0, g.L))
             assert 0 <= s["clo"] <= s["lo"] < s["hi"] <= s["chi"] <= g.L
+
+
+def test_sec5_discretisation_counts():
+    """The Sec. 5 partition: 10 x 10 subdomains with 64 knots per interface
+    counted with both crossings (63 lattice intervals per side).  Interior
+    knots only gives 11,241 unknowns; the paper's n = 11,277 also counts the
+    36 ends of the 18 interior grid lines on the boundary.  Stencils widened
+    by 32 lattice units reach 191 points at crossing knots."""
+    from paper_2301_05780_amd import workloads
+    w = workloads.sec5()
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    assert g.n == 11241 and g.n + 2 * 18 == 11277
+    lengths = [g.side(k, o)["chi"] - g.side(k, o)["clo"] + 1 for k in range(0, g.n, 97) for o in "ENWS"
+               if not g.side(k, o)["boundary"]]
+    assert max(lengths) == 191
