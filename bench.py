@@ -2,28 +2,37 @@
 of G and b on one MI355X, and the RMSE x time comparison of the plain and the
 control-variate estimators.
 
-Default workload: the variable-coefficient problem on [0,1]^2 with 8 x 8
-subdomains, knot spacing 1/128 (1729 knots, 229,405 structural nonzeros),
-N = 1e4 paths per knot, h = 1e-4, Gobet-Menozzi exits, float32 paths with
-float64 accumulation of G and b.  One step = one full assembly (all paths of
-all knots, CSR values and b written).  Inputs are formula-defined and resident
-on the device before timing.  Other workloads (--workload): poisson_small
-(29 knots), large_lut (4096^2 coefficient table, 62465 knots, h = 1e-5) and
-batched (64 instances in one launch, replayed from a HIP graph).
+Default workload (the largest single-GPU configuration): the Poisson
+coefficients tabulated as a 4096^2 float32 bilinear table in HBM, 32 x 32
+subdomains, knot spacing 1/1024 (62,465 knots, 19,224,317 structural
+nonzeros), N = 1e4 paths per knot (6.2e8 paths), h = 1e-5, Gobet-Menozzi
+exits, float32 paths with float64 accumulation, and the learned control
+variate: the 2-64-64-1 network, trained on the GPU before timing on the
+workload's own paths (a plain N = 1000 warm-up assembly and its solve give the
+targets), its gradient baked into a 513^2 table that every step reads (the
+paper keeps F on a table, Sec. 4.2).  One step = one full assembly (all paths
+of all knots, CSR values and b written).  Inputs are resident on the device
+before timing.  Other workloads (--workload): varcoef (8 x 8 subdomains,
+1729 knots, h = 1e-4), poisson_small (29 knots) and batched (64 instances in
+one launch, replayed from a HIP graph); --cv none|table|network picks the
+control variate of the table workload.
 
 Prints one JSON line.
-  roofline      the assembly kernel against the VALU issue peak (the path is
-                bound by plain ALU work: the counter-based generator's integer
-                multiplies, transcendentals, float32 arithmetic); `achieved` is
-                the algorithmic lane-operations per path-step (ALG_OPS) times
-                the path-steps of one launch over the launch's mean duration
-                from HIP events on the library's stream; `traffic` is the HBM
-                byte count of the committed counter summary for this kernel
-                source and workload, or null when the source has changed.
+  roofline      the assembly kernel against the float32 vector peak
+                (157.3 TFLOP/s): `achieved` is the algorithmic float32 FLOP
+                per path-step (FP32_FLOP) times the path-steps of one launch
+                over the launch's mean duration from HIP events on the
+                library's stream; `traffic` is the HBM byte count of the
+                committed counter summary for this kernel source and
+                workload, or null when the source has changed;
+                `valu_issue_frac` the committed VALU counters' busy fraction
+                for the same source, and `issue_model` the lane-issue-slot
+                view (ALG_OPS against 39.3 T lane-ops/s).
   cpu_baseline  the float64 CPU oracle on a bounded sample of the workload.
-  cv_comparison (default workload only) interface RMSE and GPU time of the
-                plain estimator and of the trained control variate on the
-                29-knot poisson problem, each the mean over 16 seeds.
+  secondary     (default run) the varcoef line, the control-variate forms on
+                the table workload, the RMSE x time comparison on the 29-knot
+                Poisson problem and on varcoef, the three phases on varcoef,
+                RBF interpolation and the paper's Sec. 5 experiment.
 """
 import argparse
 import hashlib
@@ -56,7 +65,13 @@ ALG_OPS = {
     "amplitude": 20 + 6 + 11 + 24 + 6 + 7,     # 4 trans, 2 sqrt
     "lut": 20 + 6 + 11 + 56 + 14 + 7,          # index math 14, 7 fields x 3 lerps x 2 ops
 }
+# Algorithmic float32 FLOP per path-step (the oracle's operation list):
+# poisson 25, varcoef 60, amplitude 40, table 70 (index math aside: 7 fields x
+# 3 lerps x 2 FLOP = 42, Euler update, exit test).  The gradient-table control
+# variate adds 23: 2 fields x 3 lerps x 2 FLOP, F = sigma^T grad v (6) and
+# Xi -= Y F . dW (5).
 FP32_FLOP = {"poisson": 25, "varcoef": 60, "amplitude": 40, "lut": 70}
+CV_FLOP = {"none": 0, "table": 23}
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -69,18 +84,42 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(workload):
-    """HBM bytes per launch from profiles/assemble_<workload>_hbm.txt when its
-    source hash matches the current kernel source, else None."""
-    path = os.path.join(PROFILES, f"assemble_{workload}_hbm.txt")
+def _committed(name, field):
+    """A figure of profiles/<name>.txt when the summary's source hash matches
+    the current kernel source, else None."""
+    path = os.path.join(PROFILES, f"{name}.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"source_sha256:\s*(\w+)", txt)
-    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    t = re.search(field + r":\s*([0-9.eE+-]+)", txt)
     if not m or not t or m.group(1) != kernel_source_hash():
         return None
     return float(t.group(1))
+
+
+def committed_traffic(workload):
+    """HBM bytes per launch from profiles/assemble_<workload>_hbm.txt."""
+    return _committed(f"assemble_{workload}_hbm", "hbm_bytes_per_launch")
+
+
+def committed_valu_busy(workload):
+    """VALU busy fraction from profiles/assemble_<workload>_valu.txt."""
+    return _committed(f"assemble_{workload}_valu", "valu_busy_frac")
+
+
+def host_cpu():
+    """Host CPU model and logical core count."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(model=model, nproc=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None)
 
 
 # ---- CPU oracle baseline ---------------------------------------------------
@@ -88,7 +127,10 @@ _ORACLE_INPUTS = {}
 
 
 def _oracle_inputs(w):
-    """Geometry and coefficients of the oracle, built once per process."""
+    """Geometry, coefficients and control variate of the oracle, built once
+    per process.  A gradient-table control variate (w["cv_table_n"]) is the
+    oracle's own bake of the seeded initial network on a table of the same
+    size: the work per step does not depend on the table's values."""
     from oracle.geometry import Geometry
     from oracle.coeffs import Coefficients
     key = w["name"]
@@ -99,7 +141,18 @@ def _oracle_inputs(w):
             c = Coefficients("lut", lut=workloads.poisson_lut(w["lut_n"]), lut_n=w["lut_n"])
         else:
             c = Coefficients(w["kind"], w.get("param", ()))
-        _ORACLE_INPUTS[key] = (g, c)
+        cv = None
+        if w.get("cv_table_n"):
+            import numpy as np
+            from oracle import mlp as omlp
+            from paper_2301_05780_amd import workloads
+            n = int(w["cv_table_n"])
+            xs = np.arange(n) / (n - 1)
+            X, Y = np.meshgrid(xs, xs)
+            th = workloads.mlp_init(0)
+            tab = omlp.grad_input(th, np.stack([X.ravel(), Y.ravel()], axis=1)).reshape(n, n, 2)
+            cv = omlp.GradLutCV(tab.astype(np.float32), w["domain"])
+        _ORACLE_INPUTS[key] = (g, c, cv)
     return _ORACLE_INPUTS[key]
 
 
@@ -107,8 +160,8 @@ def _oracle_sample(args):
     """Worker: run the oracle on one knot and return its path-step count."""
     w, k = args
     from oracle.assemble import integrate_knot, exit_points, knot_row
-    g, c = _oracle_inputs(w)
-    rec = integrate_knot(g, c, k, w["n_paths"], w["h"], w["seed"], w.get("instance", 0), w["exit_rule"])
+    g, c, cv = _oracle_inputs(w)
+    rec = integrate_knot(g, c, k, w["n_paths"], w["h"], w["seed"], w.get("instance", 0), w["exit_rule"], cv=cv)
     ex = exit_points(g, c, k, rec)
     knot_row(g, c, k, rec, ex)
     return int(rec["K"].sum())
@@ -158,9 +211,12 @@ def cpu_baseline(w, workers, target_s=15.0):
         if pool is not None:
             pool.terminate()
             pool.join()
+    hc = host_cpu()
     return dict(value=steps / dt, unit="path-steps/s", cores=workers, kind="oracle",
                 sample=f"{count} of {n} knots (spread over the domain), all {w['n_paths']} paths each, "
-                       f"{steps} path-steps in {dt:.1f} s wall on {workers} processes")
+                       f"{steps} path-steps in {dt:.1f} s wall on {workers} processes"
+                       + (", gradient-table control variate" if w.get("cv_table_n") else ""),
+                host_nproc=hc["nproc"], host_cpus_available=hc["affinity"], cpu_model=hc["model"])
 
 
 _TABLES = {}          # gradient tables baked by cv_comparison, by workload name
@@ -362,7 +418,10 @@ def sec5_experiment(ctx, seed=0):
     interpolated with the same RBF weights, xi drawn with the table); Phase
     III, the production assembly with the control variate and
     the per-knot path counts of eq. 41 and time steps of eq. 40.  Phases II
-    and III are repeated without the control variate (rho^2 = 0).  The
+    and III are repeated with the paper's own control variate (the
+    pseudospectral subdomain solves of the Phase I knot values give u0(x),
+    and F = sigma^T grad u0 is read from a table, Sec. 4.2) and without any
+    (rho^2 = 0).  The
     Phase I and III launch shapes are autotuned first.  Reports each
     phase's GPU time and path-steps and the interface errors against u* (the
     paper prints Phase I RMSE 0.016, max 0.074 and Phase III RMSE 0.0044,
@@ -378,6 +437,7 @@ def sec5_experiment(ctx, seed=0):
     w = dict(w, rbf_c=pdd.rbf_shape(S, dx, w["rbf_condition"]), seed=seed)
     xy = pdd.knot_xy(w)
     ue = Coefficients("eq43").exact(xy[:, 0], xy[:, 1])
+    u_star = torch.from_numpy(ue).to(ctx.device)
 
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -436,9 +496,39 @@ def sec5_experiment(ctx, seed=0):
               "h_min": h3, "paths_total": int(pl["n_paths"].sum()), "paths_median": float(np.median(pl["n_paths"]))}
         p3 = dict(e3, h_min=h3, h_median=float(np.median(pl["h"])), gpu_ms=ms3, path_steps=steps3,
                   path_steps_per_s=steps3 / ms3 * 1e3, launch=list(shape3))
+        # realised per-knot score variance of Phase III against the forecast
+        # V (1 - rho^2) of eq. 39, from an untimed re-run that keeps per-path
+        # scores against u* (hat weights: the RBF kernels keep none)
+        d3 = ctx.assemble(dict(w3, interp="hat"), cv=cvs, n_paths_per_knot=pl["n_paths"], h_per_knot=pl["h"],
+                          u_ref=u_star)
+        dd = d3["diag"].view(-1, 8).cpu().numpy()
+        vr = np.maximum(dd[:, 7] / dd[:, 1] - (dd[:, 6] / dd[:, 1]) ** 2, 1e-300)
+        forecast = pl["var"] * (1.0 - pl["rho2"])
+        p3["variance"] = {"mean_reduction_vs_phase2": float(np.mean(pl["var"] / vr)),
+                          "median_realised_over_forecast": float(np.median(vr / np.maximum(forecast, 1e-300))),
+                          "fraction_of_knots_above_forecast": float(np.mean(vr > forecast))}
         return p2, p3
 
     p2, p3 = phases23(spec, seed + 1, seed + 2)
+    # the paper's own control variate (Sec. 4.2): pseudospectral solves of the
+    # subdomains from the Phase I knot values (p = 63: 64^2 points per square,
+    # the paper's 409,600 degrees of freedom; RBF side values with the
+    # assembly's shape parameter), F = sigma^T grad u0 on a 1025^2 table
+    P_SPEC, N_TAB = 63, 1025
+    ctx.spectral_solve(w, u0, P_SPEC)                               # tables of p, outside the timing
+    grid, ms_spec = timed(lambda: ctx.spectral_solve(w, u0, P_SPEC))
+    table_sp, ms_bake = timed(lambda: ctx.spectral_grad_lut(w, grid, P_SPEC, N_TAB))
+    rng = np.random.default_rng(11)
+    pts = rng.uniform(w["domain"][0], w["domain"][1], size=(200000, 2))
+    u_pts, _ = ctx.spectral_eval(w, grid, P_SPEC, torch.from_numpy(pts).to(ctx.device))
+    e_pts = np.abs(u_pts.cpu().numpy() - Coefficients("eq43").exact(pts[:, 0], pts[:, 1]))
+    p2_sp, p3_sp = phases23(pdd.CVSpec("grad_lut", table=table_sp), seed + 1, seed + 2)
+    paper_cv = {"degree": P_SPEC, "points_per_square": (P_SPEC + 1) ** 2,
+                "degrees_of_freedom": w["H"] ** 2 * (P_SPEC + 1) ** 2,
+                "subdomain_solves_gpu_ms": ms_spec, "table_nodes": N_TAB, "table_bake_gpu_ms": ms_bake,
+                "global_u0_vs_exact": {"points": int(pts.shape[0]), "rmse": float(np.sqrt(np.mean(e_pts ** 2))),
+                                       "max_error": float(e_pts.max())},
+                "phase2": p2_sp, "phase3": p3_sp}
     p2_plain, p3_plain = phases23(None, seed + 1, seed + 2)
     return {
         "workload": ("Lap u = f on [-100,100]^2, u* of eq. 43, 10x10 subdomains, 63 lattice intervals per "
@@ -449,37 +539,38 @@ def sec5_experiment(ctx, seed=0):
         "cv_training": training,
         "phase2": p2,
         "phase3": p3,
+        "paper_control_variate": paper_cv,
         "without_control_variate": {"phase2": p2_plain, "phase3": p3_plain},
         "paper": {"phase1": {"rmse": 0.016, "max_error": 0.074}, "phase3": {"rmse": 0.0044, "max_error": 0.0224}},
     }
 
 
 # ---- runs ---------------------------------------------------------------------
-def tuned_single(ctx, w, lut=None, tune=True):
+def tuned_single(ctx, w, lut=None, tune=True, cv=None):
     """Assemble once (allocating the outputs and the context's caches), then,
     with `tune`, let the autotuner pick the launch shape, which stays set on
     the context for the timed launches.  Returns (outputs, tuning record)."""
-    out = ctx.assemble(w, lut=lut)
+    out = ctx.assemble(w, lut=lut, cv=cv)
     ctx.sync()
     tuned = None
     if tune:
-        arr, _ = ctx.batch_arrays([w], outs=[out], lut=lut)
+        arr, _ = ctx.batch_arrays([w], outs=[out], lut=lut, cv=cv)
         ms, report = ctx.autotune(arr, reps=2)
         tuned = {"best_kernel_ms": ms, "shape": ctx.last_launch()}
     return out, tuned
 
 
-def time_single(ctx, w, steps, warmup, lut=None, tune=False):
+def time_single(ctx, w, steps, warmup, lut=None, tune=False, cv=None):
     import torch
-    out, tuned = tuned_single(ctx, w, lut=lut, tune=tune)
+    out, tuned = tuned_single(ctx, w, lut=lut, tune=tune, cv=cv)
     for _ in range(warmup):
-        ctx.assemble(w, out=out, lut=lut)
+        ctx.assemble(w, out=out, lut=lut, cv=cv)
     ctx.sync()
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.assemble(w, out=out, lut=lut)
+        ctx.assemble(w, out=out, lut=lut, cv=cv)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kern_ms, launches = ctx.kernel_ms()
@@ -487,7 +578,7 @@ def time_single(ctx, w, steps, warmup, lut=None, tune=False):
     diag = out["diag"].view(-1, 8)
     return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3,
                 path_steps=float(diag[:, 0].sum().item()), paths=float(diag[:, 1].sum().item()),
-                n=int(out["n"]), nnz=int(out["nnz"]), tuned=tuned)
+                n=int(out["n"]), nnz=int(out["nnz"]), tuned=tuned, out=out)
 
 
 def tuned_batched(ctx, ws):
@@ -544,6 +635,67 @@ def time_batched(steps, warmup):
                         "graph_nodes": nodes, "autotuned_kernel_ms": tuned_ms})
 
 
+def train_table_cv(ctx, w, lut, table_n=513, warm_paths=1000):
+    """The learned control variate of the table workload, trained on the GPU
+    before timing: a plain warm-up assembly with `warm_paths` paths per knot
+    and its solve give u0; training pairs from 8 paths per knot (8 points
+    each, their own stream class), two epochs of Adam in batches of 1024, grad
+    v baked into a table_n^2 table.  Returns (table, record)."""
+    import numpy as np
+    import torch
+    from paper_2301_05780_amd import cv as cvmod
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(ctx.stream)
+    warm = ctx.assemble(dict(w, n_paths=warm_paths), lut=lut, seed=1000)
+    u0, it, rr = ctx.solve(warm["row_ptr"], warm["col_idx"], warm["val"][:warm["nnz"]], warm["b"], tol=1e-8)
+    ev[1].record(ctx.stream)
+    params, info = cvmod.fit(ctx, w, u0, paths_per_knot=8, points_per_path=8, epochs=2, batch=1024, lr=2e-3,
+                             lut=lut)
+    table = ctx.mlp_bake(params, w, table_n)
+    ev[2].record(ctx.stream)
+    ev[2].synchronize()
+    del warm
+    return params, table, {"warm_up_paths_per_knot": warm_paths, "pairs": info["pairs"], "adam_steps": info["steps"],
+                           "final_loss": float(np.mean(info["losses"][-50:])), "table_nodes": table_n,
+                           "gpu_ms_warm_up_and_solve": ev[0].elapsed_time(ev[1]),
+                           "gpu_ms_collect_train_bake": ev[1].elapsed_time(ev[2])}
+
+
+def table_cv_accuracy(ctx, w, lut, out, spec, params):
+    """Outside the timed region: per-knot score variance with and without the
+    control variate (scores against u*) on the same paths, the interface
+    RMSE of each solve (BiCGStab with float64 refinement to 1e-10), and the
+    kernel time of each control-variate form."""
+    import numpy as np
+    import torch
+    from paper_2301_05780_amd import pdd
+    from oracle.coeffs import Coefficients     # the manufactured solution only
+    xy = pdd.knot_xy(w)
+    ue = Coefficients("poisson").exact(xy[:, 0], xy[:, 1])
+    u_ref = torch.from_numpy(ue).to(ctx.device)
+    res = {}
+    for name, cvs in (("plain", None), ("table", spec), ("network", pdd.CVSpec("network", params=params))):
+        ctx.set_timing(True)
+        o = ctx.assemble(w, out=out, lut=lut, cv=cvs, u_ref=u_ref)
+        ctx.sync()
+        kms, _ = ctx.kernel_ms()
+        ctx.set_timing(False)
+        d = o["diag"].view(-1, 8).cpu().numpy()
+        N = d[:, 1]
+        var = d[:, 7] / N - (d[:, 6] / N) ** 2
+        u, iters, relres = ctx.solve(o["row_ptr"], o["col_idx"], o["val"][:o["nnz"]], o["b"], tol=1e-10)
+        err = np.abs(u.cpu().numpy() - ue)
+        res[name] = {"kernel_ms": kms, "path_steps_per_s": float(d[:, 0].sum()) / kms * 1e3,
+                     "rmse": float(np.sqrt(np.mean(err ** 2))), "max_error": float(err.max()),
+                     "solve_iterations": iters, "solve_relres": relres, "_var": var}
+    for name in ("table", "network"):
+        res[name]["median_variance_reduction"] = float(np.median(res["plain"]["_var"] /
+                                                                 np.maximum(res[name]["_var"], 1e-300)))
+    for r in res.values():
+        r.pop("_var")
+    return res
+
+
 def copy_calibration():
     """A plain device copy of known size (256 MiB, three times) for scaling the
     FETCH_SIZE and WRITE_SIZE counters."""
@@ -558,19 +710,44 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}), flush=True)
 
 
+def line_for(ctx, w, r, args, lut=None, cv_name="none"):
+    """The JSON fields of one timed single-instance workload."""
+    steps_per_launch = r["path_steps"]
+    kavg = r["kavg_s"]
+    flop = FP32_FLOP[w["kind"]] + CV_FLOP.get(cv_name, 0)
+    achieved = flop * steps_per_launch / kavg / 1e12
+    key = w["name"] + ("" if cv_name == "none" else f"_cv_{cv_name}")
+    ops = ALG_OPS[w["kind"]]
+    return {
+        "value": steps_per_launch * args.steps / r["elapsed"],
+        "ms_per_step": r["elapsed"] / args.steps * 1e3,
+        "kernel_ms_avg": kavg * 1e3,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": committed_traffic(key),
+                     "fp32_flop_per_path_step": flop, "kernel_source": kernel_source_hash(),
+                     "valu_issue_frac": committed_valu_busy(key),
+                     "issue_model": {"lane_ops_per_path_step": ops, "peak_tops": VALU_PEAK_TOPS,
+                                     "frac": ops * steps_per_launch / kavg / 1e12 / VALU_PEAK_TOPS}},
+        "counters_key": key,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="varcoef", choices=["varcoef", "poisson_small", "large_lut", "batched"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large_lut", choices=["large_lut", "varcoef", "poisson_small", "batched"])
+    ap.add_argument("--cv", default="table", choices=["table", "network", "none"],
+                    help="control variate of the table workload (large_lut)")
     ap.add_argument("--exit-rule", default="gm", choices=["gm", "naive"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall time of the timed oracle sample on the host")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-cv-compare", action="store_true")
-    ap.add_argument("--no-rbf", action="store_true", help="skip the RBF and Sec. 5 views of the varcoef line")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary records (varcoef line, control-variate studies, phases, RBF, Sec. 5)")
+    ap.add_argument("--no-rbf", action="store_true", help="skip the RBF and Sec. 5 views")
     ap.add_argument("--sec5-only", action="store_true",
                     help="print only the Sec. 5 experiment's record (its three phases) and exit")
     ap.add_argument("--rbf-only", action="store_true",
@@ -605,77 +782,102 @@ def main():
     from paper_2301_05780_amd import pdd, workloads
 
     lut = None
+    cv_name = "none"
+    extra = {}
     if args.workload == "batched":
         r = time_batched(args.steps, args.warmup)
         w = dict(workloads.batched()[0], name="batched", kind="amplitude")
         desc = ("batched: 64 amplitude-family instances (a ~ U(0, 0.8), H in {4,6,8,12,16}, knot spacing "
                 "1/64..1/256, N ~ U[2e3, 2e4], h = 1e-4) in one persistent launch, replayed from a HIP graph")
         launch = r["launch"]
+        ctx = None
     else:
+        ctx = pdd.Context(0)
+        spec = None
         if args.workload == "varcoef":
             w = workloads.varcoef(args.exit_rule)
         elif args.workload == "large_lut":
             w = workloads.large_lut(args.exit_rule)
             lut = torch.from_numpy(workloads.poisson_lut(w["lut_n"])).cuda()
+            if args.cv != "none":
+                params, table, rec = train_table_cv(ctx, w, lut)
+                extra["cv_training"] = rec
+                cv_name = args.cv
+                spec = (pdd.CVSpec("grad_lut", table=table) if args.cv == "table"
+                        else pdd.CVSpec("network", params=params))
         else:
             w = workloads.poisson_small(args.exit_rule)
             w["precision"] = "fp32"
-        ctx = pdd.Context(0)
-        r = time_single(ctx, w, args.steps, args.warmup, lut=lut, tune=args.autotune)
+        r = time_single(ctx, w, args.steps, args.warmup, lut=lut, tune=args.autotune, cv=spec)
         grid, block, tickets = ctx.last_launch()
         launch = {"grid": grid, "block": block, "tickets": tickets, "refill": ctx.refill(),
                   "spare_rows": ctx.spare_rows(), "autotuned": args.autotune}
-        ctx.set_launch(0, 0, 0)                   # later runs (control-variate comparison) size themselves
+        ctx.set_launch(0, 0, 0)                   # later runs size themselves
         ctx.set_refill(1)
         ctx.set_spare_rows(-1)
         desc = (f"{w['name']}: {w['kind']} coefficients, {w['H']}x{w['H']} subdomains, knot spacing "
                 f"1/{w['H'] * w['m']}, N={w['n_paths']}, h={w['h']}, {w['exit_rule']} exits")
         if w["kind"] == "lut":
             desc += f", {w['lut_n']}^2 float32 coefficient table"
+        if cv_name == "table":
+            desc += (", learned control variate (2-64-64-1 tanh network trained on the GPU on the workload's own "
+                     "paths before timing; grad v baked into a 513^2 float32 table read at every step)")
+        elif cv_name == "network":
+            desc += ", learned control variate (2-64-64-1 tanh network, grad v on bf16 MFMA at every step)"
+        if args.workload == "large_lut" and cv_name != "none" and not args.no_secondary:
+            extra["control_variate_forms"] = table_cv_accuracy(ctx, w, lut, r["out"], spec, params)
 
-    steps_per_launch = r["path_steps"]
-    value = steps_per_launch * args.steps / r["elapsed"]
-    kavg = r["kavg_s"]
-    ops = ALG_OPS[w["kind"]]
-    achieved = ops * steps_per_launch / kavg / 1e12
+    fields = line_for(ctx, w, r, args, lut, cv_name)
     rec = {
         "metric": "Euler-Maruyama path-steps/s building G,b; RMSE·time plain vs neural CV",
-        "value": value,
+        "value": fields["value"],
         "unit": "path-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["elapsed"] / args.steps * 1e3,
+        "ms_per_step": fields["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (formula-defined manufactured BVP; inputs resident in HBM)",
         "config": {"workload": desc, "knots": r["n"], "nnz": r["nnz"], "paths": int(r["paths"]),
-                   "path_steps_per_step": int(steps_per_launch),
-                   "mean_steps_per_path": steps_per_launch / r["paths"], "launch": launch,
-                   "accumulation": "f64"},
-        "kernel_ms_avg": kavg * 1e3,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": committed_traffic(args.workload),
-                     "ops_per_path_step": ops, "kernel_source": kernel_source_hash(),
-                     "fp32_flop_frac": FP32_FLOP[w["kind"]] * steps_per_launch / kavg / 1e12 / FP32_PEAK_TFLOPS},
+                   "path_steps_per_step": int(r["path_steps"]),
+                   "mean_steps_per_path": r["path_steps"] / r["paths"], "launch": launch,
+                   "accumulation": "f64", "control_variate": cv_name},
+        "kernel_ms_avg": fields["kernel_ms_avg"],
+        "roofline": fields["roofline"],
     }
-    if args.workload != "batched":
-        if args.workload == "varcoef" and not args.no_cv_compare:
-            rec["cv_comparison"] = {
-                "note": ("RMSE: mean over 16 seeds of the interface RMSE vs u*; gpu_ms: median assembly-kernel "
-                         "time per seed; with_training adds the whole training (pair collection + Adam) to one "
-                         "run, _amortised divides it by the 16 seeds one trained network serves"),
-                "poisson_small": cv_comparison(ctx, workloads.poisson_small("gm"), 1000,
-                                               (1000, 500, 250, 125, 63, 32)),
-                "varcoef": cv_comparison(ctx, workloads.varcoef("gm"), 10000,
-                                         (10000, 5000, 2500, 1250, 625, 313)),
-            }
-            rec["phases"] = phases(ctx, workloads.varcoef("gm"), 1000, 0.01, 100, _TABLES.get("varcoef"))
-            if not args.no_rbf:
-                rec["rbf_interpolation"] = rbf_view(ctx, w)
-                rec["sec5_experiment"] = sec5_experiment(ctx)
+    rec.update(extra)
+    if ctx is not None and not args.no_secondary and args.workload == "large_lut":
+        r.pop("out", None)
+        sec = {}
+        wv = workloads.varcoef("gm")
+        rv = time_single(ctx, wv, args.steps, args.warmup, tune=args.autotune)
+        fv = line_for(ctx, wv, rv, args)
+        sec["varcoef"] = {"path_steps_per_s": fv["value"], "ms_per_step": fv["ms_per_step"],
+                          "kernel_ms_avg": fv["kernel_ms_avg"], "roofline": fv["roofline"],
+                          "path_steps_per_step": int(rv["path_steps"])}
+        rv.pop("out", None)
+        ctx.set_launch(0, 0, 0)
+        ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
+        sec["cv_comparison"] = {
+            "note": ("RMSE: mean over 16 seeds of the interface RMSE vs u*; gpu_ms: median assembly-kernel "
+                     "time per seed; with_training adds the whole training (pair collection + Adam) to one "
+                     "run, _amortised divides it by the 16 seeds one trained network serves; the training "
+                     "pairs draw from their own stream class, apart from every timed seed"),
+            "poisson_small": cv_comparison(ctx, workloads.poisson_small("gm"), 1000,
+                                           (1000, 500, 250, 125, 63, 32)),
+            "varcoef": cv_comparison(ctx, workloads.varcoef("gm"), 10000,
+                                     (10000, 5000, 2500, 1250, 625, 313)),
+        }
+        sec["phases"] = phases(ctx, workloads.varcoef("gm"), 1000, 0.01, 100, _TABLES.get("varcoef"))
+        if not args.no_rbf:
+            sec["rbf_interpolation"] = rbf_view(ctx, wv)
+            sec["sec5_experiment"] = sec5_experiment(ctx)
+        rec["secondary"] = sec
+    if ctx is not None:
         ctx.close()
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
@@ -684,6 +886,8 @@ def main():
         cw = dict(w)
         if args.workload == "batched":
             cw = workloads.batched()[0]
+        if cv_name == "table":
+            cw["cv_table_n"] = 513
         rec["cpu_baseline"] = cpu_baseline(cw, workers, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 

@@ -127,6 +127,7 @@ enum {
 enum { PDD_DIAG_WIDTH = 8 };   /* per knot: sum K, N, exits E/N/W/S, sum s, sum s^2 */
 enum { PDD_DUMP_WIDTH = 8 };   /* per dumped path: K, x_K, y_K, Y_K, Z_K, Xi_K, knot, path */
 enum { PDD_MLP_WIDTH = 64, PDD_MLP_PARAMS = 4417 };
+#define PDD_COLLECT_STREAM 0x40000000u /* added to run.instance by pdd_collect_training */
 enum { PDD_CAL_WIDTH = 8 };    /* per knot: sum(phi_EM - phi_GM), sum phi_GM, sum phi_GM^2, sum xi,
                                   sum xi^2, sum phi_GM xi, sum K_GM, sum K_EM */
 
@@ -148,7 +149,9 @@ typedef struct pdd_cv {
 
 typedef struct pdd_run {
   uint64_t seed;                   /* Philox key = (seed lo 32 bits, seed hi 32 bits) */
-  uint32_t instance;               /* fourth Philox counter word */
+  uint32_t instance;               /* fourth Philox counter word (assemblies: below 2^30 keeps
+                                      the stream apart from the training pairs' and the point
+                                      evaluations', which add PDD_COLLECT_STREAM and 2^31) */
   int32_t precision;               /* PDD_FP64_SAME_STREAM | PDD_FP32_PRODUCTION */
   int32_t exit_rule;               /* PDD_EXIT_NAIVE | PDD_EXIT_GM */
   int32_t dump_paths;              /* >0: record the first dump_paths paths of every knot */
@@ -335,6 +338,68 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
                               const pdd_knots* knots, const double* u_knots, int64_t n_pts, const double* xy,
                               const pdd_run* run, double* u, double* se);
 
+/* ---- pseudospectral subdomain solves and the global u0(x) (Sec. 3.3) ---- */
+
+/* Once the knot values are known, every subdomain square is an independent
+ * Dirichlet problem for (6) (Sec. 3.3), which the paper solves with the
+ * pseudospectral method (Sec. 3.3, 5.1); the solutions together give the
+ * global u0(x) of Phase I (Sec. 4.3) and the control variate F =
+ * sigma^T grad u0 kept on a look-up table (Sec. 4.2, eq. 37).
+ *
+ * Discretisation: on each square the tensor grid of the p + 1
+ * Chebyshev-Gauss-Lobatto points per direction, t_j = -cos(pi j / p),
+ * j = 0..p (ascending), mapped onto the square; collocation of (6) at the
+ * interior points, u = side value at the boundary points.  Side values: g on
+ * the domain boundary; on an interface, the line's lattice values (knot
+ * values u_knots, g at the two lattice points on the domain boundary)
+ * interpolated over the side's stencil, the line's lattice points from the
+ * side's lower end minus knots->ext to its upper end plus knots->ext clipped
+ * to the domain: hat weights (interp = PDD_INTERP_HAT) or the
+ * inverse-multiquadric cardinal functions of that stencil with shape
+ * parameter rbf_c (PDD_INTERP_RBF_IMQ, eqs. 1-5).  The four corners of a
+ * square take the values of its horizontal (lower and upper) sides.
+ * Operators: constant coefficients with diagonal sigma and no drift (POISSON,
+ * EXITTIME, EQ43, or a LUT whose sigma, drift and reaction fields are
+ * constant over the table, checked on the device: the call then
+ * synchronises the stream); others give PDD_EUNSUPPORTED.  The interior
+ * system is solved by diagonalising the second-derivative block (the
+ * decomposition computed once per p on the host in extended precision):
+ * results equal the direct solve of the collocation system to float64
+ * rounding amplified by the eigenvector conditioning (about 1e-10 relative
+ * at p = 63).
+ * grid (device, float64, caller-owned): H^2 * 3 * (p+1)^2 doubles,
+ * grid[((s * 3 + f) * (p+1) + i) * (p+1) + j] for square s = a + H c (a, c
+ * its column and row), field f = 0 (u), 1 (du/dx), 2 (du/dy), at the point
+ * (x_a + S (t_i + 1) / 2, y_c + S (t_j + 1) / 2), S the side length.
+ * u_knots: device double[n] in canonical order.  2 <= p <= 63. */
+pdd_status pdd_spectral_solve(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                              const pdd_knots* knots, int32_t p, int32_t interp, double rbf_c, const double* u_knots,
+                              double* grid);
+
+/* u0 and grad u0 at n_pts points from a grid of pdd_spectral_solve (same
+ * partition and p): 2-D barycentric Chebyshev interpolation on the point's
+ * square, the square with lower-left corner index min(floor((x - x0) / S),
+ * H - 1) per direction (points outside the domain extrapolate from the
+ * nearest square).  Device arrays: xy[2 n_pts], u[n_pts] and grad[2 n_pts]
+ * (each nullable, not both). */
+pdd_status pdd_spectral_eval(pdd_ctx* ctx, const pdd_partition* part, int32_t p, const double* grid, int64_t n_pts,
+                             const double* xy, double* u, double* grad);
+
+/* grad u0 on the lut_n x lut_n node grid of the domain, the table read by
+ * PDD_CV_GRAD_LUT (the paper's F = sigma^T grad u0 on a look-up table, eq.
+ * 37; the assembly applies sigma^T): grad_lut[(j lut_n + i) 2 + d] (device
+ * float32), node (i, j) at (x0 + i (x1 - x0) / (lut_n - 1), y0 + j (y1 -
+ * y0) / (lut_n - 1)), each node evaluated on its square as pdd_spectral_eval
+ * does. */
+pdd_status pdd_spectral_grad_lut(pdd_ctx* ctx, const pdd_partition* part, int32_t p, const double* grid, int32_t lut_n,
+                                 float* grad_lut);
+
+/* Host only: accuracy of the degree-p diagonalisation that pdd_spectral_solve
+ * uses, max |E V - V diag(lam)| / max |E| and max |V V^{-1} - I| (E the
+ * interior block of the second-derivative collocation matrix).  PDD_EINVAL
+ * outside 2 <= p <= 63 or when the decomposition fails. */
+pdd_status pdd_spectral_tables(int32_t p, double* decomp_residual, double* inverse_residual);
+
 /* ---- Phase II calibration (Sec. 4.1-4.2, eqs. 32-41) ----------------------- */
 
 /* Mixed Gobet-Menozzi / Euler-Maruyama trajectories (Sec. 4.1): for every
@@ -360,17 +425,19 @@ pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_parti
                          const pdd_run* run, const double* u_knots, double* stats);
 
 /* Per-knot parameters from the calibration sums (host only; all arrays host):
- * with N = n_paths and the means over the knot's paths,
+ * with N = n_paths, h0_cal the calibration step h0' that pdd_calibrate ran
+ * with (run->h), h0 the production cap (0 < h0 <= h0_cal, Sec. 4.2; the
+ * Sec. 4.3 pseudocode takes h0_cal = h0) and the means over the knot's paths,
  *   bias[i] = |mean(phi_EM - phi_GM)| / 2                     (eqs. 35-36)
  *   var[i]  = mean(phi_GM^2) - mean(phi_GM)^2 (>= 0)
  *   rho2[i] = cov(phi_GM, xi)^2 / (var(phi_GM) var(xi)) (0 if a variance is 0)
- *   h[i]    = min(h0, 2 h0 eps / (3 |mean(phi_GM - phi_EM)|)) (eq. 40; h0 if 0)
+ *   h[i]    = min(h0, 2 h0_cal eps / (3 |mean(phi_GM - phi_EM)|)) (eq. 40; h0 if 0)
  *   paths[i]= 9 var (1 - rho2) / eps^2 rounded to the closest k n_job, k >= 1
  *                                                              (eq. 41)
  * stats: double[n * PDD_CAL_WIDTH] (pdd_calibrate's, copied to the host);
  * h, paths: outputs of n entries; bias, var, rho2 nullable. */
-pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths, double h0, double eps, int32_t n_job,
-                                double* h, int32_t* paths, double* bias, double* var, double* rho2);
+pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths, double h0_cal, double h0, double eps,
+                                int32_t n_job, double* h, int32_t* paths, double* bias, double* var, double* rho2);
 
 /* Shape parameter of the inverse multiquadric (Sec. 5.1 picks it so that the
  * interpolation matrix has a spectral condition number of about 1e10), host
@@ -396,6 +463,17 @@ pdd_status pdd_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed);
  * are in the network's own (unit) coordinates, as pdd_collect_training
  * writes them. */
 pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* grad);
+
+/* grad v of the network at n points through the routine that the float32
+ * network control variate (PDD_CV_NETWORK, PDD_FP32_PRODUCTION) runs at every
+ * Euler step of pdd_assemble (eq. 37's F = sigma^T grad v): bf16 operands on
+ * the matrix cores with float32 accumulation, layer 1 and the final
+ * contraction from hi/lo bf16 splits, tanh on the vector units.  Arguments as
+ * for pdd_mlp_eval (device: params[PDD_MLP_PARAMS], xy[2n] and grad[2n]
+ * float32 in the network's unit coordinates; n = 0 does nothing).  Results
+ * equal the float64 definition within the rounding of the bf16 operands
+ * (about 2^-9 of each product term); pdd_mlp_eval gives the float32 form. */
+pdd_status pdd_mlp_grad_bf16(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* grad);
 
 /* Gradient of the loss L = mean_i (v(x_i) - t_i)^2 / 2 over the n points with
  * respect to all parameters (device: grad[PDD_MLP_PARAMS]; loss[1] nullable),
@@ -426,8 +504,13 @@ pdd_status pdd_mlp_bake_grad_lut(pdd_ctx* ctx, const float* params, const pdd_pa
                                  float* grad_lut);
 
 /* Training pairs from the method's own paths: for every knot k and path
- * p < paths_per_knot (same random stream and float32 step as the production
- * assembly), the first points_per_path iterates X_n receive the tail score
+ * p < paths_per_knot (the float32 step of the production assembly; the
+ * Philox counter (draw, p, k, run.instance + PDD_COLLECT_STREAM) with key
+ * run.seed, run.instance < 2^30, so the pairs never share paths with an
+ * assembly whose instance word is below 2^30: a network fitted on them stays
+ * adapted to the assembly's Brownian increments, eq. 38; an assembly with
+ * instance word run.instance + PDD_COLLECT_STREAM replays the same paths),
+ * the first points_per_path iterates X_n receive the tail score
  * (Z_K + Y_K u(exit) - Z_n) / Y_n, u at the exit interpolated from u0 (device,
  * the solved knot values) or the boundary datum.  Outputs (device, slot
  * (k paths_per_knot + p) points_per_path + n): xy[2 slots] (the iterate in

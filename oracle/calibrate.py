@@ -155,9 +155,12 @@ def calibrate(geom, coef, u0, n_paths, h, seed, instance=0, cv=None, knots=None,
     return {int(k): calibrate_knot(geom, coef, int(k), u0, n_paths, h, seed, instance, cv, interp) for k in ks}
 
 
-def plan(stats, n_paths, h0, eps, n_job):
+def plan(stats, n_paths, h0, eps, n_job, h0_cal=None):
     """Eqs. 35-41 from the sums: (h_i, N_i, bias bound, variance, rho^2) per
-    knot.  stats: array [n, STATS_WIDTH]."""
+    knot.  stats: array [n, STATS_WIDTH].  h0_cal is the calibration step h0'
+    of the sums (eq. 40's numerator; default h0, as in the Sec. 4.3
+    pseudocode), h0 the cap of eq. 40."""
+    h0_cal = h0 if h0_cal is None else h0_cal
     stats = np.asarray(stats, dtype=np.float64).reshape(-1, STATS_WIDTH)
     N = float(n_paths)
     mdiff = stats[:, 0] / N
@@ -170,7 +173,7 @@ def plan(stats, n_paths, h0, eps, n_job):
     rho2 = np.where(denom > 0.0, np.minimum(cov * cov / np.where(denom > 0.0, denom, 1.0), 1.0), 0.0)
     bias = 0.5 * np.abs(mdiff)
     with np.errstate(divide="ignore"):
-        h = np.where(mdiff != 0.0, np.minimum(h0, 2.0 * h0 * eps / (3.0 * np.abs(mdiff))), h0)
+        h = np.where(mdiff != 0.0, np.minimum(h0, 2.0 * h0_cal * eps / (3.0 * np.abs(mdiff))), h0)
     n_raw = 9.0 * var * (1.0 - rho2) / (eps * eps)
     k = np.maximum(np.floor(n_raw / n_job + 0.5), 1.0)
     return dict(h=h, n_paths=(k * n_job).astype(np.int64), bias=bias, var=var, rho2=rho2)

@@ -11,6 +11,7 @@
 
 #include "context.h"
 #include "geometry.h"
+#include "spectral.h"
 #include "kernels.h"
 #include "mlp.h"
 #include "plan.h"
@@ -293,6 +294,169 @@ pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_
   return run_eval_subdomain(ctx, *coeffs, *part, *knots, u_knots, n_pts, xy, *run, u, se);
 }
 
+namespace {
+
+// Collocation tables of degree p on the context's device (built once per p).
+pdd_status get_spec(pdd_ctx* ctx, int32_t p, SpecCache** out) {
+  SpecCache* sc = ctx->spec.get();
+  if (!sc || sc->p != p) {
+    SpectralTables t;
+    std::string err;
+    if (!spectral_tables(p, t, err)) return fail(ctx, PDD_EINVAL, err);
+    auto fresh = std::make_unique<SpecCache>();
+    fresh->p = p;
+    fresh->decomp_residual = t.decomp_residual;
+    fresh->inverse_residual = t.inverse_residual;
+    const size_t nn = (size_t)SPEC_T * SPEC_T;
+    std::vector<double> all;
+    all.reserve(2 * SPEC_T + 2 * SPEC_T + 3 * nn + SPEC_T);
+    auto put = [&](const std::vector<double>& v, size_t len) {
+      const size_t off = all.size();
+      all.insert(all.end(), v.begin(), v.end());
+      all.resize(off + len, 0.0);
+      return off;
+    };
+    const size_t o_nodes = put(t.nodes, SPEC_T), o_bw = put(t.bw, SPEC_T), o_D = put(t.D, nn),
+                 o_D2b = put(t.D2b, 2 * SPEC_T), o_V = put(t.V, nn), o_Vi = put(t.Vinv, nn), o_lam = put(t.lam, SPEC_T);
+    hipError_t e = fresh->buf.reserve(all.size() * sizeof(double));
+    if (e != hipSuccess) return check_hip(ctx, e, "hipMalloc(spectral tables)");
+    if ((e = hipMemcpy(fresh->buf.ptr, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return check_hip(ctx, e, "upload spectral tables");
+    const double* b = fresh->buf.as<double>();
+    fresh->dev = SpecDev{b + o_nodes, b + o_bw, b + o_D, b + o_D2b, b + o_V, b + o_Vi, b + o_lam};
+    ctx->spec = std::move(fresh);
+    sc = ctx->spec.get();
+  }
+  *out = sc;
+  return PDD_OK;
+}
+
+bool bad_domain(const pdd_partition& part) {
+  return !(part.x1 > part.x0) || !(part.y1 > part.y0) || part.H < 2 || !std::isfinite(part.x0) ||
+         !std::isfinite(part.x1) || !std::isfinite(part.y0) || !std::isfinite(part.y1);
+}
+
+}  // namespace
+
+pdd_status pdd_spectral_solve(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
+                              const pdd_knots* knots, int32_t p, int32_t interp, double rbf_c, const double* u_knots,
+                              double* grid) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_spectral_solve: null context");
+  if (!coeffs || !part || !knots || !u_knots || !grid || bad_domain(*part))
+    return fail(ctx, PDD_EINVAL, "pdd_spectral_solve: bad arguments");
+  if (p < 2 || p > SPEC_MAX_P) return fail(ctx, PDD_EINVAL, "pdd_spectral_solve: need 2 <= p <= 63");
+  if (interp != PDD_INTERP_HAT && interp != PDD_INTERP_RBF_IMQ)
+    return fail(ctx, PDD_EINVAL, "pdd_spectral_solve: unknown interpolation");
+  if (interp == PDD_INTERP_RBF_IMQ && (!(rbf_c > 0.0) || !std::isfinite(rbf_c)))
+    return fail(ctx, PDD_EINVAL, "pdd_spectral_solve: RBF side values need a finite shape parameter > 0");
+  const int kind = coeffs->kind;
+  if (kind != PDD_COEF_POISSON && kind != PDD_COEF_EXITTIME && kind != PDD_COEF_EQ43 && kind != PDD_COEF_LUT)
+    return fail(ctx, PDD_EUNSUPPORTED,
+                "pdd_spectral_solve: constant-coefficient operators only (POISSON, EXITTIME, EQ43, or a LUT with "
+                "constant sigma, zero drift and constant reaction)");
+  pdd_run run{};
+  run.precision = PDD_FP64_SAME_STREAM;
+  run.exit_rule = PDD_EXIT_NAIVE;
+  run.n_paths = 1;
+  run.h = 1.0;
+  run.interp = interp;
+  run.rbf_c = interp == PDD_INTERP_RBF_IMQ ? rbf_c : 0.0;
+  pdd_status st = validate_run(ctx, *coeffs, run);
+  if (st != PDD_OK) return st;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  const double Sx = (part->x1 - part->x0) / part->H, Sy = (part->y1 - part->y0) / part->H;
+  double axx = 2.0, ayy = 2.0, cr = 0.0;           // a_xx, a_yy of sigma = sqrt(2) I
+  if (kind == PDD_COEF_LUT) {
+    // the operator must be constant over the table: read every field's range
+    const int64_t nodes = (int64_t)coeffs->lut_n * coeffs->lut_n;
+    if ((e = ctx->spec_range.reserve((12 + 1024 * 12) * sizeof(double))) != hipSuccess)
+      return check_hip(ctx, e, "hipMalloc(spectral range)");
+    if ((e = launch_lut_field_range(coeffs->lut, nodes, ctx->spec_range.as<double>(), ctx->stream)) != hipSuccess)
+      return check_hip(ctx, e, "launch lut range");
+    double r[12];
+    if ((e = hipMemcpyAsync(r, ctx->spec_range.ptr, sizeof(r), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
+      return check_hip(ctx, e, "read lut range");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    // fields: 0 sxx, 1 sxy, 2 syy, 3 dx, 4 dy, 5 c; r[q] = min, r[6 + q] = max
+    for (int q = 0; q < 6; ++q)
+      if (r[q] != r[6 + q])
+        return fail(ctx, PDD_EUNSUPPORTED, "pdd_spectral_solve: the table's sigma, drift and reaction must be constant");
+    if (r[1] != 0.0 || r[3] != 0.0 || r[4] != 0.0)
+      return fail(ctx, PDD_EUNSUPPORTED, "pdd_spectral_solve: the table needs a diagonal sigma and zero drift");
+    axx = r[0] * r[0];
+    ayy = r[2] * r[2];
+    cr = r[5];
+    if (cr > 0.0) return fail(ctx, PDD_EINVAL, "pdd_spectral_solve: the reaction must be <= 0");
+  }
+  GeoCache* gc = nullptr;
+  if ((st = get_geometry(ctx, *part, *knots, &gc)) != PDD_OK) return st;
+  if ((st = get_lattice(ctx, gc)) != PDD_OK) return st;
+  SpecCache* sc = nullptr;
+  if ((st = get_spec(ctx, p, &sc)) != PDD_OK) return st;
+  SpecArgs A;
+  fill_asm_params(*gc, *coeffs, run, A.P);
+  if (interp == PDD_INTERP_RBF_IMQ) {
+    if (std::min(knots->m + 2 * knots->ext, (int32_t)gc->g.L) + 1 > gc->g.slot_len)
+      return fail(ctx, PDD_EINVAL, "pdd_spectral_solve: side stencil longer than the stencil table");
+    if ((st = prepare_rbf(ctx, gc->g, run, A.P, false)) != PDD_OK) return st;
+  }
+  A.T = sc->dev;
+  A.p = p;
+  A.H = part->H;
+  A.m = knots->m;
+  A.ext = knots->ext;
+  A.rbf = interp == PDD_INTERP_RBF_IMQ;
+  A.ax = 0.5 * axx * (2.0 / Sx) * (2.0 / Sx);
+  A.ay = 0.5 * ayy * (2.0 / Sy) * (2.0 / Sy);
+  A.c = cr;
+  A.u_knots = u_knots;
+  A.grid = grid;
+  return check_hip(ctx, launch_spectral_solve(A, ctx->stream), "launch spectral solve");
+}
+
+pdd_status pdd_spectral_eval(pdd_ctx* ctx, const pdd_partition* part, int32_t p, const double* grid, int64_t n_pts,
+                             const double* xy, double* u, double* grad) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_spectral_eval: null context");
+  if (!part || !grid || bad_domain(*part) || n_pts < 0 || (n_pts > 0 && (!xy || (!u && !grad))))
+    return fail(ctx, PDD_EINVAL, "pdd_spectral_eval: bad arguments");
+  if (p < 2 || p > SPEC_MAX_P) return fail(ctx, PDD_EINVAL, "pdd_spectral_eval: need 2 <= p <= 63");
+  if (n_pts == 0) return PDD_OK;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  SpecCache* sc = nullptr;
+  pdd_status st = get_spec(ctx, p, &sc);
+  if (st != PDD_OK) return st;
+  return check_hip(ctx, launch_spectral_eval(sc->dev, p, part->H, part->x0, part->x1, part->y0, part->y1, grid, n_pts,
+                                             xy, 0, u, grad, nullptr, ctx->stream),
+                   "launch spectral eval");
+}
+
+pdd_status pdd_spectral_grad_lut(pdd_ctx* ctx, const pdd_partition* part, int32_t p, const double* grid, int32_t lut_n,
+                                 float* grad_lut) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_spectral_grad_lut: null context");
+  if (!part || !grid || !grad_lut || bad_domain(*part) || lut_n < 2 || lut_n > 65536)
+    return fail(ctx, PDD_EINVAL, "pdd_spectral_grad_lut: bad arguments");
+  if (p < 2 || p > SPEC_MAX_P) return fail(ctx, PDD_EINVAL, "pdd_spectral_grad_lut: need 2 <= p <= 63");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  SpecCache* sc = nullptr;
+  pdd_status st = get_spec(ctx, p, &sc);
+  if (st != PDD_OK) return st;
+  return check_hip(ctx, launch_spectral_eval(sc->dev, p, part->H, part->x0, part->x1, part->y0, part->y1, grid, 0,
+                                             nullptr, lut_n, nullptr, nullptr, grad_lut, ctx->stream),
+                   "launch spectral grad table");
+}
+
+pdd_status pdd_spectral_tables(int32_t p, double* decomp_residual, double* inverse_residual) {
+  SpectralTables t;
+  std::string err;
+  if (!spectral_tables(p, t, err)) return fail(nullptr, PDD_EINVAL, "pdd_spectral_tables: " + err);
+  if (decomp_residual) *decomp_residual = t.decomp_residual;
+  if (inverse_residual) *inverse_residual = t.inverse_residual;
+  return PDD_OK;
+}
+
 pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part, const pdd_knots* knots,
                          const pdd_run* run, const double* u_knots, double* stats) {
   if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_calibrate: null context");
@@ -333,10 +497,11 @@ pdd_status pdd_calibrate(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_parti
   return check_hip(ctx, e, "launch calibrate");
 }
 
-pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths, double h0, double eps, int32_t n_job,
-                                double* h, int32_t* paths, double* bias, double* var, double* rho2) {
-  if (n < 0 || (n > 0 && (!stats || !h || !paths)) || n_paths < 1 || !(h0 > 0.0) || !(eps > 0.0) || n_job < 1)
-    return fail(nullptr, PDD_EINVAL, "pdd_calibration_plan: bad arguments");
+pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths, double h0_cal, double h0, double eps,
+                                int32_t n_job, double* h, int32_t* paths, double* bias, double* var, double* rho2) {
+  if (n < 0 || (n > 0 && (!stats || !h || !paths)) || n_paths < 1 || !(h0 > 0.0) || !(h0_cal >= h0) ||
+      !std::isfinite(h0_cal) || !(eps > 0.0) || n_job < 1)
+    return fail(nullptr, PDD_EINVAL, "pdd_calibration_plan: bad arguments (need 0 < h0 <= h0_cal, eps > 0, n_job >= 1)");
   const double N = (double)n_paths;
   for (int64_t i = 0; i < n; ++i) {
     const double* s = stats + i * PDD_CAL_WIDTH;
@@ -346,7 +511,7 @@ pdd_status pdd_calibration_plan(int64_t n, const double* stats, int64_t n_paths,
     const double cov = s[5] / N - mphi * mxi;
     const double den = vphi * vxi;
     const double r2 = den > 0.0 ? std::min(cov * cov / den, 1.0) : 0.0;
-    h[i] = mdiff != 0.0 ? std::min(h0, 2.0 * h0 * eps / (3.0 * std::fabs(mdiff))) : h0;
+    h[i] = mdiff != 0.0 ? std::min(h0, 2.0 * h0_cal * eps / (3.0 * std::fabs(mdiff))) : h0;
     const double nraw = 9.0 * vphi * (1.0 - r2) / (eps * eps);
     const double k = std::max(std::floor(nraw / n_job + 0.5), 1.0);
     if (k * n_job > (double)INT32_MAX) return fail(nullptr, PDD_EINVAL, "pdd_calibration_plan: path count overflows int32");
@@ -375,6 +540,15 @@ pdd_status pdd_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const floa
   if (!params || n < 0 || (n > 0 && (!xy || (!v && !grad)))) return fail(ctx, PDD_EINVAL, "pdd_mlp_eval: bad arguments");
   if (n == 0) return PDD_OK;
   return run_mlp_eval(ctx, params, n, xy, v, grad);
+}
+
+pdd_status pdd_mlp_grad_bf16(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* grad) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_mlp_grad_bf16: null context");
+  if (!params || n < 0 || (n > 0 && (!xy || !grad))) return fail(ctx, PDD_EINVAL, "pdd_mlp_grad_bf16: bad arguments");
+  if (n == 0) return PDD_OK;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  return run_mlp_grad_bf16(ctx, params, n, xy, grad);
 }
 
 pdd_status pdd_mlp_grad(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, const float* target,
@@ -424,6 +598,8 @@ pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pd
   if (run->interp != PDD_INTERP_HAT)
     return fail(ctx, PDD_EUNSUPPORTED, "pdd_collect_training: targets use the hat interpolation (run.interp 0)");
   if (run->h_per_knot) return fail(ctx, PDD_EUNSUPPORTED, "pdd_collect_training: run.h_per_knot must be NULL");
+  if (run->instance >= PDD_COLLECT_STREAM)
+    return fail(ctx, PDD_EINVAL, "pdd_collect_training: run.instance must be below 2^30");
   pdd_status st = validate_run(ctx, *coeffs, *run);
   if (st != PDD_OK) return st;
   hipError_t e = hipSetDevice(ctx->device);
@@ -438,7 +614,9 @@ pdd_status pdd_collect_training(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pd
   AsmParams P;
   fill_asm_params(*gc, *coeffs, *run, P);
   if ((st = prepare_lut_bound(ctx, *coeffs, *run, P, false)) != PDD_OK) return st;
-  e = launch_collect(P, gc->g.n, paths_per_knot, points_per_path, run->instance, u0, xy,
+  // the pairs draw from their own stream class (instance word + 2^30), so
+  // no assembly with instance < 2^30 reuses the paths the network was fitted on
+  e = launch_collect(P, gc->g.n, paths_per_knot, points_per_path, run->instance + PDD_COLLECT_STREAM, u0, xy,
                      ctx->collect_scratch.as<float>(), target, ctx->stream);
   return check_hip(ctx, e, "launch collect");
 }

@@ -12,6 +12,7 @@
 #include "geometry.h"
 #include "kernels.h"
 #include "pdd.h"
+#include "spectral.h"
 
 namespace pdd {
 
@@ -92,6 +93,13 @@ struct AssembleJob {
 }  // namespace pdd
 
 namespace pdd {
+// Collocation tables of one spectral degree p on the device.
+struct SpecCache {
+  int32_t p = 0;
+  DeviceBuffer buf;
+  SpecDev dev{};
+  double decomp_residual = 0, inverse_residual = 0;
+};
 // Inverses of the RBF stencil matrices for one (slot length, spacing, c).
 struct RbfCache {
   int32_t slot_len = 0;
@@ -111,6 +119,8 @@ struct pdd_ctx {
   std::unique_ptr<pdd::TicketCache> tickets;
   std::unique_ptr<pdd::BatchCache> batch;
   std::unique_ptr<pdd::RbfCache> rbf;
+  std::unique_ptr<pdd::SpecCache> spec;
+  pdd::DeviceBuffer spec_range;      // LUT field ranges of the spectral solve (12 + 1024 * 12 doubles)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool capturing = false;

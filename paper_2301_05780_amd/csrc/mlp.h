@@ -17,6 +17,7 @@ static_assert(OB3 + 1 == MLP_PARAMS, "parameter layout");
 
 pdd_status run_mlp_init(pdd_ctx* ctx, float* params, uint64_t seed);
 pdd_status run_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* v, float* g);
+pdd_status run_mlp_grad_bf16(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* g);
 pdd_status run_mlp_bake(pdd_ctx* ctx, const float* params, const pdd_partition& part, int32_t lut_n, float* out);
 pdd_status run_mlp_train(pdd_ctx* ctx, float* params, float* m, float* s, int64_t n_points, const float* xy,
                          const float* target, const int32_t* order, int64_t n_order, int32_t batch, int32_t steps,

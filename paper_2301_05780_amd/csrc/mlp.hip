@@ -19,6 +19,7 @@
 #include "context.h"
 #include "device_common.h"
 #include "mlp.h"
+#include "net_grad.h"
 
 namespace pdd {
 
@@ -81,6 +82,30 @@ __global__ __launch_bounds__(BLK) void k_mlp_eval(const float* __restrict__ para
     net_eval_f32(th, xy[2 * i], xy[2 * i + 1], vv, gx, gy);
     if (v) v[i] = vv;
     if (g) { g[2 * i] = gx; g[2 * i + 1] = gy; }
+  }
+}
+
+// grad v through net_grad_mfma, the routine the float32 network control
+// variate runs at every Euler step of the assembly: each wave takes 64
+// consecutive points per pass.  Lanes past the end repeat the last point, so
+// every lane of the wave takes part in the MFMA products, and store nothing.
+__global__ __launch_bounds__(BLK) void k_mlp_grad_bf16(const float* __restrict__ params, int64_t n,
+                                                       const float* __restrict__ xy, float* __restrict__ g) {
+  __shared__ NetLds N;
+  net_stage(&N, params);
+  __syncthreads();
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t waves = (int64_t)gridDim.x * (BLK / 64);
+  const int64_t wave = (int64_t)blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
+  for (int64_t base = wave * 64; base < n; base += waves * 64) {      // wave-uniform bound
+    const int64_t i = base + lane;
+    const int64_t r = i < n ? i : n - 1;
+    float gx, gy;
+    net_grad_mfma(&N, xy[2 * r], xy[2 * r + 1], gx, gy);
+    if (i < n) {
+      g[2 * i] = gx;
+      g[2 * i + 1] = gy;
+    }
   }
 }
 
@@ -432,6 +457,13 @@ pdd_status run_mlp_eval(pdd_ctx* ctx, const float* params, int64_t n, const floa
   const int grid = (int)std::min<int64_t>(4096, (n + BLK - 1) / BLK);
   hipLaunchKernelGGL(k_mlp_eval, dim3(std::max(grid, 1)), dim3(BLK), 0, ctx->stream, params, n, xy, v, g);
   return check_hip(ctx, hipGetLastError(), "launch mlp_eval");
+}
+
+pdd_status run_mlp_grad_bf16(pdd_ctx* ctx, const float* params, int64_t n, const float* xy, float* g) {
+  const int64_t waves = (n + 63) / 64;
+  const int grid = (int)std::min<int64_t>(2048, (waves + BLK / 64 - 1) / (BLK / 64));
+  hipLaunchKernelGGL(k_mlp_grad_bf16, dim3(std::max(grid, 1)), dim3(BLK), 0, ctx->stream, params, n, xy, g);
+  return check_hip(ctx, hipGetLastError(), "launch mlp_grad_bf16");
 }
 
 pdd_status run_mlp_bake(pdd_ctx* ctx, const float* params, const pdd_partition& part, int32_t lut_n, float* out) {

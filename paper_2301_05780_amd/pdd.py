@@ -23,6 +23,7 @@ DIAG_WIDTH = 8
 DUMP_WIDTH = 8
 MLP_PARAMS = 4417
 CAL_WIDTH = 8
+COLLECT_STREAM = 0x40000000          # added to the instance word by pdd_collect_training
 INTERP = {"hat": 0, "rbf": 1}
 
 
@@ -103,7 +104,7 @@ def lib():
             "pdd_set_launch": [vp, i32, i32, i32, i32],
             "pdd_set_refill": [vp, i32],
             "pdd_calibrate": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots), C.POINTER(Run), vp, vp],
-            "pdd_calibration_plan": [i64, vp, i64, f64, f64, i32, vp, vp, vp, vp, vp],
+            "pdd_calibration_plan": [i64, vp, i64, f64, f64, f64, i32, vp, vp, vp, vp, vp],
             "pdd_rbf_shape": [i32, f64, f64, C.POINTER(f64)],
             "pdd_plan_tickets": [C.POINTER(Partition), C.POINTER(Knots), vp, i32, i32, i32, C.POINTER(i64), vp, vp,
                                  vp],
@@ -113,6 +114,12 @@ def lib():
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_init": [vp, vp, C.c_uint64],
             "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
+            "pdd_mlp_grad_bf16": [vp, vp, i64, vp, vp],
+            "pdd_spectral_solve": [vp, C.POINTER(Coeffs), C.POINTER(Partition), C.POINTER(Knots), i32, i32, f64, vp,
+                                   vp],
+            "pdd_spectral_eval": [vp, C.POINTER(Partition), i32, vp, i64, vp, vp, vp],
+            "pdd_spectral_grad_lut": [vp, C.POINTER(Partition), i32, vp, i32, vp],
+            "pdd_spectral_tables": [i32, C.POINTER(f64), C.POINTER(f64)],
             "pdd_assemble_batch": [vp, i32, vp],
             "pdd_graph_begin": [vp],
             "pdd_graph_end": [vp, C.POINTER(i32)],
@@ -203,15 +210,17 @@ def plan_tickets(w, paths_per_ticket, spatial=False, grid=0):
     return tickets[:T.value], order[:T.value], xb
 
 
-def calibration_plan(stats, n_paths, h0, eps, n_job):
+def calibration_plan(stats, n_paths, h0, eps, n_job, h0_cal=None):
     """Per-knot h_i, N_i, bias bound, variance and rho^2 from calibration sums
-    (host; stats: array [n, CAL_WIDTH])."""
+    (host; stats: array [n, CAL_WIDTH]); h0_cal is the calibration step h0'
+    (default h0), h0 the production cap."""
     st = np.ascontiguousarray(stats, dtype=np.float64).reshape(-1, CAL_WIDTH)
     n = st.shape[0]
     h = np.empty(n)
     paths = np.empty(n, dtype=np.int32)
     bias, var, rho2 = np.empty(n), np.empty(n), np.empty(n)
-    _check(lib().pdd_calibration_plan(n, st.ctypes.data, int(n_paths), float(h0), float(eps), int(n_job),
+    _check(lib().pdd_calibration_plan(n, st.ctypes.data, int(n_paths), float(h0 if h0_cal is None else h0_cal),
+                                      float(h0), float(eps), int(n_job),
                                       h.ctypes.data, paths.ctypes.data, bias.ctypes.data, var.ctypes.data,
                                       rho2.ctypes.data))
     return dict(h=h, n_paths=paths, bias=bias, var=var, rho2=rho2)
@@ -224,6 +233,14 @@ def rbf_shape(n_nodes, spacing, target_cond=1e10):
     c = C.c_double()
     _check(lib().pdd_rbf_shape(int(n_nodes), float(spacing), float(target_cond), C.byref(c)))
     return c.value
+
+
+def spectral_tables(p):
+    """Accuracy of the degree-p diagonalisation of the spectral solves (host):
+    (max |E V - V diag(lam)| / max |E|, max |V V^{-1} - I|)."""
+    a, b = C.c_double(), C.c_double()
+    _check(lib().pdd_spectral_tables(int(p), C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def _set_interp(run, w):
@@ -403,6 +420,13 @@ class Context:
         self.check(lib().pdd_mlp_eval(self.h, _ptr(params), n, _ptr(xy), _ptr(v), _ptr(g)))
         return v, g
 
+    def mlp_grad_bf16(self, params, xy):
+        """grad v at the rows of xy through the assembly's bf16-MFMA routine."""
+        n = xy.shape[0]
+        g = self.torch.empty(n, 2, dtype=self.torch.float32, device=self.device)
+        self.check(lib().pdd_mlp_grad_bf16(self.h, _ptr(params), n, _ptr(xy), _ptr(g)))
+        return g
+
     def mlp_grad(self, params, xy, target):
         grad = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.device)
         loss = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
@@ -480,6 +504,38 @@ class Context:
         par = (C.c_double * 4)(*(list(w.get("param", ())) + [0.0] * 4)[:4])
         lut_n = int(w.get("lut_n", 0)) if lut is not None else 0
         return Coeffs(KIND[w["kind"]], lut_n, par, _ptr(lut))
+
+    # ---- pseudospectral subdomain solves ---------------------------------------
+    def spectral_solve(self, w, u_knots, p, interp=None, rbf_c=None, lut=None):
+        """Grid values and derivatives of every square: tensor [H^2, 3, p+1, p+1]
+        (fields u, du/dx, du/dy).  interp defaults to the workload's
+        ("hat" or "rbf" with w["rbf_c"])."""
+        H = int(w["H"])
+        grid = self.torch.empty(H * H, 3, p + 1, p + 1, dtype=self.torch.float64, device=self.device)
+        mode = interp or w.get("interp", "hat")
+        c = float(rbf_c if rbf_c is not None else w.get("rbf_c", 0.0)) if mode == "rbf" else 0.0
+        co = self.coeffs_of(w, lut)
+        part, kn = partition_of(w), knots_of(w)
+        self.check(lib().pdd_spectral_solve(self.h, C.byref(co), C.byref(part), C.byref(kn), int(p), INTERP[mode], c,
+                                            _ptr(u_knots), _ptr(grid)))
+        return grid
+
+    def spectral_eval(self, w, grid, p, xy):
+        """u0 [n] and grad u0 [n, 2] at the rows of xy (device float64 [n, 2])."""
+        n = xy.shape[0]
+        u = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        g = self.torch.empty(n, 2, dtype=self.torch.float64, device=self.device)
+        part = partition_of(w)
+        self.check(lib().pdd_spectral_eval(self.h, C.byref(part), int(p), _ptr(grid), n, _ptr(xy), _ptr(u), _ptr(g)))
+        return u, g
+
+    def spectral_grad_lut(self, w, grid, p, lut_n):
+        """grad u0 on the lut_n^2 node grid: float32 [lut_n, lut_n, 2], the
+        gradient-table control variate's input."""
+        table = self.torch.empty(lut_n, lut_n, 2, dtype=self.torch.float32, device=self.device)
+        part = partition_of(w)
+        self.check(lib().pdd_spectral_grad_lut(self.h, C.byref(part), int(p), _ptr(grid), int(lut_n), _ptr(table)))
+        return table
 
     def assemble(self, w, out=None, lut=None, n_paths_per_knot=None, u_ref=None,
                  dump_paths=0, precision=None, exit_rule=None, seed=None, instance=None,

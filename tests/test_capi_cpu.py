@@ -57,3 +57,18 @@ def test_pattern_rejects_invalid_partitions(bad):
     with pytest.raises(pdd.PddError) as e:
         pdd.pattern(w)
     assert e.value.status == pdd.EINVAL
+
+
+@pytest.mark.parametrize("p", [2, 3, 7, 16, 31, 48, 63])
+def test_spectral_diagonalisation_is_accurate(p):
+    """The host decomposition E = V diag(lam) V^{-1} of the interior block of
+    the Chebyshev second-derivative matrix that every subdomain solve uses:
+    both residuals at extended-precision level before rounding to float64."""
+    dec, inv = pdd.spectral_tables(p)
+    assert dec < 1e-16 and inv < 1e-15
+
+
+def test_spectral_tables_reject_bad_degrees():
+    for p in (1, 64):
+        with pytest.raises(pdd.PddError):
+            pdd.spectral_tables(p)

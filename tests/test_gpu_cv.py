@@ -72,6 +72,121 @@ def test_network_eval_and_input_gradient(ctx):
     assert np.allclose(g.cpu().numpy(), g_ref, rtol=1e-4, atol=1e-5 * np.abs(g_ref).max())
 
 
+def _bf16_grad_bound(th, X):
+    """First-order bound on |grad v (bf16 MFMA routine) - grad v (float64)|
+    per point and component, from the rounding of the bf16 operands (unit
+    roundoff u = 2^-9; float32 accumulation and the hi/lo splits of layer 1
+    and of the final contraction, about 2^-16, are far below it):
+      z2:  W2 and h1 rounded           |dz2_j| <= 2.01 u sum_k |W2_jk h1_k|
+      g2 = 1 - tanh^2 z2:              |dg2_j| <= 2 |h2_j| g2_j |dz2_j| + u g2_j (storage)
+      dh1_k = sum_j W2_jk w3_j g2_j:   W2^T w3 and g2 rounded (2 u) plus dg2
+      D_k = dh1_k (1 - h1_k^2):        1 - h1^2 from the rounded h1 (2 h1^2 u), D rounded (u)
+      grad v = W1^T D:                 |d grad v| <= |W1|^T |dD|."""
+    W1, b1, W2, b2, w3, b3 = omlp.unpack(th)
+    u = 2.0 ** -9
+    h1 = np.tanh(X @ W1.T + b1)
+    h2 = np.tanh(h1 @ W2.T + b2)
+    g2 = 1.0 - h2 * h2
+    dz2 = 2.01 * u * (np.abs(h1) @ np.abs(W2).T)
+    dg2 = 2.0 * np.abs(h2) * g2 * dz2 + u * g2
+    dh1 = (g2 * w3) @ W2
+    ddh1 = (2.0 * u * g2 + dg2) @ np.abs(W2 * w3[:, None])
+    dD = ddh1 * (1.0 - h1 * h1) + np.abs(dh1) * (2.0 * h1 * h1 + 1.0) * u
+    return dD @ np.abs(W1)
+
+
+def _bf16_grad_spread(th, X):
+    """The same propagation with rounding errors taken as independent and
+    uniform on (-u, u) (variance u^2 / 3): root-sum-square instead of absolute
+    sums, the expected size of the bf16 error per point and component."""
+    W1, b1, W2, b2, w3, b3 = omlp.unpack(th)
+    v = (2.0 ** -9) ** 2 / 3.0
+    h1 = np.tanh(X @ W1.T + b1)
+    h2 = np.tanh(h1 @ W2.T + b2)
+    g2 = 1.0 - h2 * h2
+    dz2 = np.sqrt(2.0 * v * ((h1 * h1) @ (W2 * W2).T))
+    dg2 = np.sqrt((2.0 * np.abs(h2) * g2 * dz2) ** 2 + v * g2 * g2)
+    dh1 = (g2 * w3) @ W2
+    ddh1 = np.sqrt((2.0 * v * g2 * g2 + dg2 * dg2) @ ((W2 * w3[:, None]) ** 2))
+    dD = np.sqrt((ddh1 * (1.0 - h1 * h1)) ** 2 + dh1 * dh1 * (4.0 * h1 ** 4 + 1.0) * v)
+    return np.sqrt((dD * dD) @ (W1 * W1))
+
+
+@pytest.mark.parametrize("seed,n", [(1, 20011), (9, 64), (10, 1)])
+def test_bf16_mfma_gradient_against_oracle(ctx, seed, n):
+    """The routine the float32 network control variate runs at every step
+    (bf16 MFMA, float32 accumulation) against the float64 input gradient:
+    every component within twice the first-order bf16 rounding bound, the
+    whole set within 2e-2 in norm (the bf16 bar), and the errors of the
+    20011-point set no larger on average than the independent-rounding model
+    predicts (a mis-ordered fragment or a wrong scale would add a systematic
+    error far above it).  n = 20011 covers several workgroups and a ragged
+    last wave, 64 exactly one wave, 1 a single lane."""
+    th = _theta(seed)
+    rng = np.random.default_rng(seed + 40)
+    X = np.concatenate([rng.uniform(-0.2, 1.2, size=(n, 2))[:max(n - 4, 1)],
+                        np.array([[0.0, 0.0], [1.0, 1.0], [0.5, 0.25], [1.2, -0.2]])])[:n]
+    g = ctx.mlp_grad_bf16(_dev(th, np.float32), _dev(X, np.float32)).cpu().numpy().astype(np.float64)
+    Xf = X.astype(np.float32).astype(np.float64)
+    g_ref = omlp.grad_input(th, Xf)
+    bound = _bf16_grad_bound(th, Xf)
+    err = np.abs(g - g_ref)
+    assert np.all(err <= 2.0 * bound + 1e-6), float(np.max(err / (bound + 1e-12)))
+    assert np.linalg.norm(g - g_ref) <= 2e-2 * np.linalg.norm(g_ref)
+    spread = _bf16_grad_spread(th, Xf)
+    z = err / spread
+    print(f"bf16 grad: rel. norm error {np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref):.2e}, "
+          f"rms(err / spread) {np.sqrt(np.mean(z * z)):.3f}, max(err / bound) {np.max(err / bound):.3f}")
+    if n >= 1000:
+        assert np.sqrt(np.mean(z * z)) < 3.0
+
+
+def test_network_cv_fp32_paths_against_oracle(ctx):
+    """Per-path records of the float32 assembly with the per-step bf16 network
+    against the float64 oracle's run with the same network on the same
+    stream: step counts equal (float32 vs float64 exit flips excepted, at most
+    1 %), exit points within float32 drift, and Xi of every path within the
+    sum over its steps of |Y_n (sigma dW_n)| times twice the bf16 bound of
+    grad v at X_n (the replayed oracle path), plus float32 summation."""
+    from oracle.philox import normals_for_draw
+    w = workloads.poisson_small("gm")
+    w["precision"] = "fp32"
+    dumps = 16
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    c = Coefficients("poisson")
+    th = _theta(6)
+    res = oracle_assemble(g, c, w["n_paths"], w["h"], w["seed"], exit_rule="gm", cv=omlp.NetworkCV(th),
+                          keep_paths=True)
+    out = ctx.assemble(w, cv=pdd.CVSpec("network", params=_dev(th, np.float32)), dump_paths=dumps)
+    ctx.sync()
+    dump = out["dump"].cpu().numpy().reshape(g.n, dumps, pdd.DUMP_WIDTH)
+    sq = np.sqrt(w["h"])
+    sig = np.sqrt(2.0)                                  # poisson: sigma = sqrt(2) I, Y = 1
+    flips = checked = 0
+    for k in range(g.n):
+        p = res["paths"][k]
+        K = p["K"][:dumps]
+        same = dump[k, :, 0] == K
+        flips += int(np.sum(~same))
+        # replay the oracle's paths of this knot: X_n and the normals of every step
+        ids = np.arange(dumps, dtype=np.uint64)
+        x = np.tile([g.x[k], g.y[k]], (dumps, 1)).astype(np.float64)
+        tol = np.zeros(dumps)
+        for n in range(int(K.max())):
+            first, second = normals_for_draw(n // 2, ids, k, 0, w["seed"])
+            nx, ny = first if n % 2 == 0 else second
+            live = n < K
+            b = 2.0 * _bf16_grad_bound(th, x)
+            tol += np.where(live, sig * sq * (b[:, 0] * np.abs(nx) + b[:, 1] * np.abs(ny)), 0.0)
+            x = x + np.where(live[:, None], sig * sq * np.stack([nx, ny], axis=1), 0.0)
+        xi_gpu, xi_ref = dump[k, same, 5], p["Xi"][:dumps][same]
+        assert np.all(np.abs(xi_gpu - xi_ref) <= tol[same] + 1e-5 * (1 + K[same] * 1e-2)), k
+        assert np.allclose(dump[k, same, 1], p["x"][:dumps][same], rtol=0, atol=1e-4)
+        assert np.allclose(dump[k, same, 2], p["y"][:dumps][same], rtol=0, atol=1e-4)
+        checked += int(same.sum())
+    assert flips <= 0.01 * g.n * dumps and checked > 0
+
+
 def test_loss_gradient_against_oracle(ctx):
     th = _theta(2)
     rng = np.random.default_rng(3)
@@ -187,13 +302,21 @@ def test_cv_fp32_production_within_se(ctx, mode):
 def test_collected_pairs_reproduce_the_rows(ctx):
     """The first pair of every path sits at the knot and its target is the
     path's full score with u0 at the exit, so its mean over the knot's paths is
-    b_k - sum_{j != k} G_kj u0_j of the assembly that used the same paths."""
+    b_k - sum_{j != k} G_kj u0_j of the assembly that used the same paths: the
+    one with instance word PDD_COLLECT_STREAM.  The assembly with instance
+    word 0 draws other paths (the pairs' own stream class)."""
     w = workloads.poisson_small("gm")
     w["precision"] = "fp32"
-    out = ctx.assemble(w)
-    u0, _, _ = ctx.solve(out["row_ptr"], out["col_idx"], out["val"][:out["nnz"]], out["b"])
+    out0 = ctx.assemble(w)
+    u0, _, _ = ctx.solve(out0["row_ptr"], out0["col_idx"], out0["val"][:out0["nnz"]], out0["b"])
+    out = ctx.assemble(dict(w, instance=pdd.COLLECT_STREAM))
     xy, t = ctx.collect(w, u0, w["n_paths"], 8)
     ctx.sync()
+    b0 = out0["b"].cpu().numpy()
+    assert np.mean(np.abs(b0 - out["b"].cpu().numpy()) > 1e-9) > 0.9      # other paths
+    with pytest.raises(pdd.PddError) as e:
+        ctx.collect(dict(w, instance=pdd.COLLECT_STREAM), u0, 4, 2)
+    assert e.value.status == pdd.EINVAL
     n, nnz = out["n"], out["nnz"]
     rp = out["row_ptr"].cpu().numpy()
     ci = out["col_idx"].cpu().numpy()[:nnz]

@@ -1,0 +1,181 @@
+"""GPU pseudospectral subdomain solves (Sec. 3.3, 5.1) against the float64
+oracle's direct collocation solve: grid values and derivatives on several
+partitions, both side interpolations, the tabulated family; the global u0
+and the gradient table; and the paper's control variate F = sigma^T grad u0
+(Sec. 4.2) built from them."""
+import numpy as np
+import pytest
+
+from paper_2301_05780_amd import pdd, workloads
+from oracle import spectral as osp
+from oracle.coeffs import Coefficients
+from oracle.geometry import Geometry
+from oracle.rbf import shape_for_condition
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    yield c
+    c.close()
+
+
+def _knots(g, c, seed):
+    """Knot values: u* plus a smooth perturbation and noise (a solved G u = b
+    looks like this)."""
+    rng = np.random.default_rng(seed)
+    ue = c.exact(g.x, g.y)
+    if ue is None:
+        ue = np.zeros(g.n)
+    return ue + 0.05 * np.sin(3.0 * (g.x - g.x0) / (g.x1 - g.x0)) + 0.01 * rng.normal(size=g.n)
+
+
+def _solve_both(ctx, w, p, coef, interp=None, lut=None, seed=0):
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    u = _knots(g, coef, seed)
+    grid = ctx.spectral_solve(w, torch.from_numpy(u).cuda(), p, interp=interp[0] if interp else "hat",
+                              rbf_c=interp[1] if interp else None, lut=lut)
+    ctx.sync()
+    U = osp.solve_subdomains(g, coef, u, p, interp=interp)
+    gx, gy = osp.grid_gradients(g, U, p)
+    return g, grid.cpu().numpy(), U, gx, gy
+
+
+def _check(grid, U, gx, gy, p):
+    """Values within 1e-12 p^2 of the grid's magnitude (the diagonalised and
+    the direct solve differ by rounding amplified by the conditioning of the
+    collocation operator, which grows like p^4, and of the eigenvectors);
+    derivatives one factor p^2 looser (the derivative matrix has norm p^2)."""
+    scale = np.abs(U).max()
+    tol_u = 1e-12 * p * p * scale
+    assert np.max(np.abs(grid[:, 0] - U)) <= tol_u, np.max(np.abs(grid[:, 0] - U)) / scale
+    gs = max(np.abs(gx).max(), np.abs(gy).max())
+    tol_g = 1e-12 * p ** 4 * gs
+    assert np.max(np.abs(grid[:, 1] - gx)) <= tol_g, np.max(np.abs(grid[:, 1] - gx)) / gs
+    assert np.max(np.abs(grid[:, 2] - gy)) <= tol_g, np.max(np.abs(grid[:, 2] - gy)) / gs
+    return np.max(np.abs(grid[:, 0] - U)) / scale
+
+
+@pytest.mark.parametrize("p", [2, 9, 24, 63])
+def test_poisson_hat_sides_against_oracle(ctx, p):
+    """2 x 2 squares of the 29-knot problem: p = 2 (one interior point), a
+    ragged p = 9, p = 24, and p = 63 (the full 64 x 64 tile)."""
+    w = workloads.poisson_small()
+    c = Coefficients("poisson")
+    g, grid, U, gx, gy = _solve_both(ctx, w, p, c)
+    rel = _check(grid, U, gx, gy, p)
+    print(f"p={p}: max rel. difference of u {rel:.2e}")
+    # boundary points carry the side values bit for bit (same arithmetic)
+    assert np.allclose(grid[:, 0, 0, :], U[:, 0, :], rtol=0, atol=1e-14 * np.abs(U).max())
+
+
+@pytest.mark.parametrize("ext", [0, 3])
+def test_several_squares_and_the_exit_time_family(ctx, ext):
+    """3 x 3 squares on a non-unit rectangle-free domain, extended or plain
+    stencils, the exit-time problem (f = -1, g = 0)."""
+    w = dict(kind="exittime", param=(), domain=(-1.0, 2.0, 0.5, 3.5), H=3, m=6, ext=ext)
+    c = Coefficients("exittime")
+    _, grid, U, gx, gy = _solve_both(ctx, w, 17, c, seed=3)
+    _check(grid, U, gx, gy, 17)
+
+
+def test_rbf_sides_on_the_sec5_family(ctx):
+    """The Sec. 5 problem's family on [-100, 100]^2 with RBF side values over
+    extended stencils (shape parameter at condition number 1e8)."""
+    w = dict(kind="eq43", param=(), domain=(-100.0, 100.0, -100.0, 100.0), H=3, m=8, ext=4)
+    c = Coefficients("eq43")
+    S = w["m"] + 2 * w["ext"] + 1
+    cc = shape_for_condition(S, 200.0 / (w["H"] * w["m"]), 1e8)
+    g, grid, U, gx, gy = _solve_both(ctx, w, 20, c, interp=("rbf", cc), seed=4)
+    # side values: the RBF weights carry the stencil matrix's conditioning
+    scale = np.abs(U).max()
+    assert np.max(np.abs(grid[:, 0] - U)) <= (1e-12 * 400 + 1e-16 * 1e8 * S) * scale
+    gs = max(np.abs(gx).max(), np.abs(gy).max())
+    assert np.max(np.abs(grid[:, 1] - gx)) <= 1e-12 * 20 ** 4 * gs + 1e-16 * 1e8 * S * 400 * scale
+
+
+def test_tabulated_family(ctx):
+    """A table with constant sigma and a tabulated source: the source at the
+    interior points is the bilinear read of the table."""
+    w = dict(kind="lut", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=4, m=4, ext=2, lut_n=65)
+    tab = workloads.poisson_lut(65)
+    c = Coefficients("lut", lut=tab, lut_n=65)
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    u = _knots(g, c, 5)
+    grid = ctx.spectral_solve(w, torch.from_numpy(u).cuda(), 12, lut=torch.from_numpy(tab).cuda())
+    ctx.sync()
+    U = osp.solve_subdomains(g, c, u, 12)
+    gx, gy = osp.grid_gradients(g, U, 12)
+    _check(grid.cpu().numpy(), U, gx, gy, 12)
+
+
+def test_unsupported_operators_are_refused(ctx):
+    w = workloads.varcoef()
+    g = Geometry(w["domain"], w["H"], w["m"], w["ext"])
+    with pytest.raises(pdd.PddError) as e:
+        ctx.spectral_solve(w, torch.zeros(g.n, dtype=torch.float64, device="cuda"), 8)
+    assert e.value.status == pdd.EUNSUPPORTED
+    wv = dict(kind="lut", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=2, m=4, ext=2, lut_n=65)
+    g = Geometry(wv["domain"], wv["H"], wv["m"], wv["ext"])
+    with pytest.raises(pdd.PddError) as e:
+        ctx.spectral_solve(wv, torch.zeros(g.n, dtype=torch.float64, device="cuda"), 8,
+                           lut=torch.from_numpy(workloads.varied_lut(65)).cuda())
+    assert e.value.status == pdd.EUNSUPPORTED
+    for p in (1, 64):
+        with pytest.raises(pdd.PddError) as e:
+            ctx.spectral_solve(workloads.poisson_small(), torch.zeros(29, dtype=torch.float64, device="cuda"), p)
+        assert e.value.status == pdd.EINVAL
+
+
+def test_global_u0_and_gradient_table(ctx):
+    """pdd_spectral_eval at points of every square (grid lines, corners and
+    the domain's corners included) and the gradient table against the
+    oracle's barycentric interpolation of the oracle's grids."""
+    w = dict(kind="poisson", param=(), domain=(0.0, 1.0, 0.0, 1.0), H=3, m=6, ext=3)
+    c = Coefficients("poisson")
+    p = 16
+    g, grid, U, gx, gy = _solve_both(ctx, w, p, c, seed=6)
+    rng = np.random.default_rng(7)
+    pts = np.concatenate([rng.uniform(0, 1, size=(997, 2)), [[0, 0], [1, 1], [1 / 3, 0.5], [2 / 3, 2 / 3], [1, 0]]])
+    dgrid = torch.from_numpy(grid).cuda()
+    u, gr = ctx.spectral_eval(w, dgrid, p, torch.from_numpy(pts).cuda())
+    ref = osp.interpolate(g, [U, gx, gy], p, pts)
+    scale = np.abs(U).max()
+    gs = max(np.abs(gx).max(), np.abs(gy).max())
+    assert np.max(np.abs(u.cpu().numpy() - ref[0])) <= 1e-9 * scale
+    assert np.max(np.abs(gr.cpu().numpy()[:, 0] - ref[1])) <= 1e-7 * gs
+    assert np.max(np.abs(gr.cpu().numpy()[:, 1] - ref[2])) <= 1e-7 * gs
+    tab = ctx.spectral_grad_lut(w, dgrid, p, 37).cpu().numpy()
+    rtab = osp.grad_table(g, U, p, 37)
+    assert np.max(np.abs(tab - rtab)) <= 1e-6 * gs
+
+
+def test_the_papers_control_variate(ctx):
+    """F = sigma^T grad u0 with u0 from the spectral solves of a plain run's
+    knot values (Sec. 4.2): same-path b moves by the mean of Xi only (eq. 38),
+    within a few standard errors, and the per-knot score variance falls."""
+    w = dict(workloads.poisson_small("gm"), precision="fp32")
+    xy = pdd.knot_xy(w)
+    ue = Coefficients("poisson").exact(xy[:, 0], xy[:, 1])
+    u_ref = torch.from_numpy(ue).cuda()
+    plain = ctx.assemble(w, u_ref=u_ref, seed=3)
+    u0, _, _ = ctx.solve(plain["row_ptr"], plain["col_idx"], plain["val"][:plain["nnz"]], plain["b"])
+    grid = ctx.spectral_solve(w, u0, 24)
+    table = ctx.spectral_grad_lut(w, grid, 24, 257)
+    cv = ctx.assemble(w, u_ref=u_ref, seed=3, cv=pdd.CVSpec("grad_lut", table=table))
+    ctx.sync()
+    dp = plain["diag"].view(-1, pdd.DIAG_WIDTH).cpu().numpy()
+    dc = cv["diag"].view(-1, pdd.DIAG_WIDTH).cpu().numpy()
+    N = dp[:, 1]
+    vp = dp[:, 7] / N - (dp[:, 6] / N) ** 2
+    vc = dc[:, 7] / N - (dc[:, 6] / N) ** 2
+    ratio = np.median(vp / vc)
+    print(f"spectral-u0 control variate: median variance reduction {ratio:.1f}")
+    assert ratio > 3.0
+    se = np.sqrt((vp + vc) / N)
+    assert np.all(np.abs(cv["b"].cpu().numpy() - plain["b"].cpu().numpy()) <= 5 * se + 1e-9)
