@@ -826,13 +826,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   assemble_body<KIND, false, PDD_CV_NONE, false>(P);
 }
 
-// float32 table family without a control variate: capped at 128 VGPRs, i.e.
-// 4 waves per SIMD, which fits the LDS when the workgroup shares fewer tally
-// rows (the path is latency-bound on its table reads and gains with every
-// resident wave)
-template <int KIND>
+// float32 table family, plain or with the gradient-table control variate:
+// capped at 128 VGPRs, i.e. 4 waves per SIMD, which fits the LDS when the
+// workgroup shares fewer tally rows (the path is latency-bound on its table
+// reads and gains with every resident wave)
+template <int KIND, int CV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble_w4(AsmParams P) {
-  assemble_body<KIND, false, PDD_CV_NONE, false>(P);
+  assemble_body<KIND, false, CV, false>(P);
 }
 
 // Sum a knot's partial rows (ticket order, then side order) into its CSR row,
@@ -917,8 +917,8 @@ template <int KIND, bool F64, int CV, bool BATCH = false>
 const void* kernel_ptr(bool hk = false) {
   if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND != PDD_COEF_LUT) {
     if (!hk) return reinterpret_cast<const void*>(&k_assemble_w6<KIND>);
-  } else if constexpr (!F64 && CV == PDD_CV_NONE && !BATCH && KIND == PDD_COEF_LUT) {
-    if (!hk) return reinterpret_cast<const void*>(&k_assemble_w4<KIND>);
+  } else if constexpr (!F64 && (CV == PDD_CV_NONE || CV == PDD_CV_GRAD_LUT) && !BATCH && KIND == PDD_COEF_LUT) {
+    if (!hk) return reinterpret_cast<const void*>(&k_assemble_w4<KIND, CV>);
   }
   return reinterpret_cast<const void*>(&k_assemble<KIND, F64, CV, BATCH>);
 }

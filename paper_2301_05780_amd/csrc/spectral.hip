@@ -122,8 +122,10 @@ __global__ __launch_bounds__(256) void k_spec_sides(SpecArgs A, int32_t smax) {
 }
 
 // C strip of wave w (rows 16 w .. 16 w + 15) of C = A B for 64 x 64
-// operands: acc[ct] holds the 16 x 16 tile of columns 16 ct .. 16 ct + 15,
-// element q of lane l at row 16 w + 4 (l / 16) + q, column 16 ct + l % 16.
+// operands: acc[ct] holds the 16 x 16 tile of columns 16 ct .. 16 ct + 15.
+// Operands per lane l and K step: A[16 w + l % 16][k0 + l / 16] and
+// B[k0 + l / 16][16 ct + l % 16]; the float64 accumulator holds element q of
+// lane l at row 16 w + l / 16 + 4 q, column 16 ct + l % 16.
 template <class FA, class FB>
 __device__ __forceinline__ void mfma_strip(FA fa, FB fb, v4d acc[4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -145,7 +147,7 @@ __device__ __forceinline__ void strip_for_each(const v4d acc[4], F f) {
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) f(16 * w + 4 * (lane >> 4) + q, 16 * ct + (lane & 15), acc[ct][q]);
+    for (int q = 0; q < 4; ++q) f(16 * w + (lane >> 4) + 4 * q, 16 * ct + (lane & 15), acc[ct][q]);
 }
 
 // Interior solve and grid derivatives of one square per workgroup (4 waves).
