@@ -313,6 +313,20 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
                      const double* val, const double* b, double* u, double tol, int32_t max_iter,
                      int32_t* iters, double* relres);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * solve of pdd_solve, same arguments, results and errors, on a static device
+ * scratch array of 128 MiB that the library holds on every GPU it runs on
+ * (looked up once per device by pdd_create) instead of context scratch.  It
+ * allocates nothing.  Sizes beyond the array give PDD_EINVAL before any
+ * kernel runs: 4 (nnz + 7 n) + 8 n bytes plus 7 KiB must fit 128 MiB
+ * (nnz = row_ptr[n]; about 31 M nonzeros at n = 65,536).  Every call on one
+ * GPU shares that GPU's array, so calls that overlap on one GPU (several
+ * contexts or streams) race; calls in sequence do not. */
+pdd_status pdd_solve_noalloc(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                             const double* val, const double* b, double* u, double tol, int32_t max_iter,
+                             int32_t* iters, double* relres);
+
 /* ---- values inside the subdomains (Sec. 3.3; eq. 8 on each square) ------- */
 
 /* u at n_pts points from the knot values: each subdomain square is a

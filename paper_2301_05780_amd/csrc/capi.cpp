@@ -155,6 +155,9 @@ pdd_status pdd_create(pdd_ctx** out, int32_t device, void* stream) {
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return fail(nullptr, PDD_EDEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+  // the device's copy of pdd_solve_noalloc's static scratch (once per device)
+  e = solve_noalloc_setup(device);
+  if (e != hipSuccess) return fail(nullptr, PDD_EDEVICE, std::string("hipGetSymbolAddress(solve scratch): ") + hipGetErrorString(e));
   pdd_ctx* ctx = new (std::nothrow) pdd_ctx();
   if (!ctx) return fail(nullptr, PDD_ENOMEM, "pdd_create: out of host memory");
   ctx->device = device;
@@ -270,6 +273,16 @@ pdd_status pdd_solve(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int3
     return fail(ctx, PDD_EINVAL, "pdd_solve: need n >= 1 and non-null arrays");
   if (!(tol > 0.0) || max_iter < 1) return fail(ctx, PDD_EINVAL, "pdd_solve: need tol > 0 and max_iter >= 1");
   return run_solve(ctx, n, row_ptr, col_idx, val, b, u, tol, max_iter, iters, relres);
+}
+
+pdd_status pdd_solve_noalloc(pdd_ctx* ctx, int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                             const double* val, const double* b, double* u, double tol, int32_t max_iter,
+                             int32_t* iters, double* relres) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_solve_noalloc: null context");
+  if (n < 1 || !row_ptr || !col_idx || !val || !b || !u || !iters || !relres || !(tol > 0.0) || max_iter < 1)
+    return fail(ctx, PDD_EINVAL, "pdd_solve_noalloc: bad arguments");
+  if (n > INT32_MAX) return fail(ctx, PDD_EINVAL, "pdd_solve_noalloc: n must fit int32");
+  return run_solve_noalloc(ctx, n, row_ptr, col_idx, val, b, u, tol, max_iter, iters, relres);
 }
 
 pdd_status pdd_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,

@@ -177,6 +177,14 @@ pdd_status run_eval_subdomain(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_part
                               double* se);
 pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                      const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres);
+// pdd_solve_noalloc: the same solve on the library's static device scratch
+// (SOLVE_NOALLOC_BYTES per GPU); solve_noalloc_setup(device) looks up that
+// device's copy once (the device current).
+constexpr size_t SOLVE_NOALLOC_BYTES = (size_t)128 << 20;
+hipError_t solve_noalloc_setup(int device);
+pdd_status run_solve_noalloc(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
+                             const double* b, double* u, double tol, int32_t max_iter, int32_t* iters,
+                             double* relres);
 
 // Tally rows in an assembly workgroup's pool: one per wave plus the context's
 // spare rows (at most one more per wave).

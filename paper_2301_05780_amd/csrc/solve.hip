@@ -13,7 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
-#include <vector>
+#include <mutex>
 
 #include "context.h"
 
@@ -23,6 +23,15 @@ namespace {
 
 constexpr int RED_BLOCKS = 256;     // partial-dot blocks
 constexpr int BLK = 256;
+constexpr int MAX_DEVICES = 64;
+
+// Scratch of pdd_solve_noalloc: a file-scope device array, one copy per GPU
+// that runs the library, held until the process ends.  Host code uses only
+// its per-device address from hipGetSymbolAddress (solve_noalloc_setup); the
+// array's name on the host is a stand-in, not a device address.
+__device__ __align__(256) char scratch[SOLVE_NOALLOC_BYTES];
+void* g_scratch_ptr[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
 
 // Scalars of one BiCGStab recurrence (device).
 struct Scal {
@@ -207,34 +216,55 @@ __global__ __launch_bounds__(BLK) void k_zero(int64_t n, double* u) {
   GRID_LOOP(i) u[i] = 0.0;
 }
 
-}  // namespace
+__global__ void k_zero_flag(int32_t* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
 
-pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
-                     const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres) {
-  hipError_t e = hipSetDevice(ctx->device);
-  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
-  hipStream_t st = ctx->stream;
-  int32_t nnz = 0;
-  if ((e = hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return check_hip(ctx, e, "read nnz");
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
-  if (nnz < 1) { ctx->err = "pdd_solve: empty matrix (row_ptr[n] < 1)"; return PDD_EINVAL; }
-  {
-    // validate the CSR structure on the device before any kernel indexes with it
-    if ((e = ctx->solve_flag.reserve(sizeof(int32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(flag)");
-    int32_t* flag = ctx->solve_flag.as<int32_t>();
-    if ((e = hipMemsetAsync(flag, 0, sizeof(int32_t), st)) != hipSuccess) return check_hip(ctx, e, "hipMemsetAsync");
-    hipLaunchKernelGGL(k_check_csr, dim3((unsigned)std::min<int64_t>(1024, (n + BLK - 1) / BLK)), dim3(BLK), 0, st, n, rp, ci, flag);
-    int32_t hbad = 0;
-    if ((e = hipMemcpyAsync(&hbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return check_hip(ctx, e, "read flag");
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
-    if (hbad) { ctx->err = "pdd_solve: malformed CSR (row_ptr not monotone from 0, or a column outside [0, n))"; return PDD_EINVAL; }
+// Bytes of solver scratch for n unknowns and nnz entries: float32 matrix,
+// 7 float32 vectors, float64 residual, partials, scalars (and padding).
+size_t solve_bytes(int64_t n, int64_t nnz) {
+  return ((size_t)nnz + 7 * (size_t)n) * sizeof(float) + ((size_t)n + 3 * RED_BLOCKS) * sizeof(double) +
+         sizeof(Scal) + 256;
+}
+
+// nnz = row_ptr[n] (synchronises the stream)
+pdd_status read_nnz(pdd_ctx* ctx, int64_t n, const int32_t* rp, int32_t* nnz) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess)
+    return check_hip(ctx, e, "read nnz");
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+  if (*nnz < 1) {
+    ctx->err = "pdd_solve: empty matrix (row_ptr[n] < 1)";
+    return PDD_EINVAL;
   }
+  return PDD_OK;
+}
 
-  // scratch: float32 matrix, 7 float32 vectors, float64 residual, partials, scalars
-  const size_t fbytes = ((size_t)nnz + 7 * (size_t)n) * sizeof(float);
-  const size_t dbytes = ((size_t)n + 3 * RED_BLOCKS) * sizeof(double) + sizeof(Scal);
-  if ((e = ctx->solve_scratch.reserve(fbytes + dbytes + 256)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(solve scratch)");
-  char* base = ctx->solve_scratch.as<char>();
+// Validate the CSR structure on the device before any kernel indexes with it
+// (flag: one device int32, cleared here by a kernel).
+pdd_status check_csr(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, int32_t* flag) {
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, st, flag);
+  hipLaunchKernelGGL(k_check_csr, dim3((unsigned)std::min<int64_t>(1024, (n + BLK - 1) / BLK)), dim3(BLK), 0, st, n, rp, ci, flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return check_hip(ctx, e, "launch csr check");
+  int32_t hbad = 0;
+  if ((e = hipMemcpyAsync(&hbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return check_hip(ctx, e, "read flag");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+  if (hbad) {
+    ctx->err = "pdd_solve: malformed CSR (row_ptr not monotone from 0, or a column outside [0, n))";
+    return PDD_EINVAL;
+  }
+  return PDD_OK;
+}
+
+// The refinement loop on caller-provided scratch of solve_bytes(n, nnz) bytes
+// (256-byte aligned); allocates nothing.
+pdd_status solve_body(pdd_ctx* ctx, int64_t n, int32_t nnz, const int32_t* rp, const int32_t* ci, const double* val,
+                      const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres,
+                      char* base) {
+  hipError_t e;
+  hipStream_t st = ctx->stream;
   double* r64 = reinterpret_cast<double*>(base);
   double* partial = r64 + n;
   Scal* S = reinterpret_cast<Scal*>(partial + 3 * RED_BLOCKS);
@@ -255,8 +285,8 @@ pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* 
   hipLaunchKernelGGL(k_zero, dim3(RED_BLOCKS), dim3(BLK), 0, st, n, u);
   hipLaunchKernelGGL(k_norm2, dim3(RED_BLOCKS), dim3(BLK), 0, st, n, b, partial);
   if ((ps = L("solve setup")) != PDD_OK) return ps;
-  std::vector<double> hp(RED_BLOCKS);
-  if ((e = hipMemcpyAsync(hp.data(), partial, RED_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return check_hip(ctx, e, "read |b|");
+  double hp[RED_BLOCKS];
+  if ((e = hipMemcpyAsync(hp, partial, RED_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return check_hip(ctx, e, "read |b|");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
   double bb = 0.0;
   for (double q : hp) bb += q;
@@ -276,7 +306,7 @@ pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* 
     hipLaunchKernelGGL(k_residual, dim3(rows_grid), dim3(BLK), 0, st, n, rp, ci, val, u, b, r64);
     hipLaunchKernelGGL(k_norm2, dim3(RED_BLOCKS), dim3(BLK), 0, st, n, r64, partial);
     if ((ps = L("residual")) != PDD_OK) return ps;
-    if ((e = hipMemcpyAsync(hp.data(), partial, RED_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return check_hip(ctx, e, "read residual");
+    if ((e = hipMemcpyAsync(hp, partial, RED_BLOCKS * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return check_hip(ctx, e, "read residual");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
     double rr = 0.0;
     for (double q : hp) rr += q;
@@ -316,6 +346,52 @@ pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* 
     return PDD_ENOTCONV;
   }
   return PDD_OK;
+}
+
+}  // namespace
+
+pdd_status run_solve(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
+                     const double* b, double* u, double tol, int32_t max_iter, int32_t* iters, double* relres) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  int32_t nnz = 0;
+  pdd_status ps = read_nnz(ctx, n, rp, &nnz);
+  if (ps != PDD_OK) return ps;
+  if ((e = ctx->solve_flag.reserve(sizeof(int32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(flag)");
+  if ((ps = check_csr(ctx, n, rp, ci, ctx->solve_flag.as<int32_t>())) != PDD_OK) return ps;
+  if ((e = ctx->solve_scratch.reserve(solve_bytes(n, nnz))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(solve scratch)");
+  return solve_body(ctx, n, nnz, rp, ci, val, b, u, tol, max_iter, iters, relres, ctx->solve_scratch.as<char>());
+}
+
+hipError_t solve_noalloc_setup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+pdd_status run_solve_noalloc(pdd_ctx* ctx, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
+                             const double* b, double* u, double tol, int32_t max_iter, int32_t* iters,
+                             double* relres) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipSetDevice");
+  if ((e = solve_noalloc_setup(ctx->device)) != hipSuccess) return check_hip(ctx, e, "hipGetSymbolAddress(solve scratch)");
+  char* base = static_cast<char*>(g_scratch_ptr[ctx->device]);
+  int32_t nnz = 0;
+  pdd_status ps = read_nnz(ctx, n, rp, &nnz);
+  if (ps != PDD_OK) return ps;
+  // the first 256 bytes hold the CSR flag, the solver's scratch follows
+  if (solve_bytes(n, nnz) + 256 > SOLVE_NOALLOC_BYTES) {
+    ctx->err = "pdd_solve_noalloc: n and nnz need more than the static 128 MiB of scratch "
+               "(4 (nnz + 7 n) + 8 n bytes plus 7 KiB)";
+    return PDD_EINVAL;
+  }
+  if ((ps = check_csr(ctx, n, rp, ci, reinterpret_cast<int32_t*>(base))) != PDD_OK) return ps;
+  return solve_body(ctx, n, nnz, rp, ci, val, b, u, tol, max_iter, iters, relres, base + 256);
 }
 
 }  // namespace pdd

@@ -112,6 +112,7 @@ def lib():
             "pdd_set_spare_rows": [vp, i32],
             "pdd_get_spare_rows": [vp, C.POINTER(i32)],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
+            "pdd_solve_noalloc": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_init": [vp, vp, C.c_uint64],
             "pdd_mlp_eval": [vp, vp, i64, vp, vp, vp],
             "pdd_mlp_grad_bf16": [vp, vp, i64, vp, vp],
@@ -326,14 +327,16 @@ class Context:
         return ms.value, n.value
 
     # ---- solve --------------------------------------------------------------
-    def solve(self, row_ptr, col_idx, val, b, u=None, tol=1e-10, max_iter=2000, check=True):
-        """Solve G u = b (device tensors).  Returns (u, iterations, relative residual)."""
+    def solve(self, row_ptr, col_idx, val, b, u=None, tol=1e-10, max_iter=2000, check=True, noalloc=False):
+        """Solve G u = b (device tensors).  Returns (u, iterations, relative
+        residual).  noalloc: pdd_solve_noalloc (the library's static scratch)."""
         n = b.numel()
         if u is None:
             u = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
         it, rr = C.c_int32(), C.c_double()
-        st = lib().pdd_solve(self.h, n, _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(b), _ptr(u),
-                             float(tol), int(max_iter), C.byref(it), C.byref(rr))
+        fn = lib().pdd_solve_noalloc if noalloc else lib().pdd_solve
+        st = fn(self.h, n, _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(b), _ptr(u),
+                float(tol), int(max_iter), C.byref(it), C.byref(rr))
         if check or st != ENOTCONV:
             self.check(st)
         return u, it.value, rr.value
