@@ -173,7 +173,7 @@ def test_large_lut_control_variate(ctx, large):
     assert np.all(np.isfinite(info["losses"]))
     xy = pdd.knot_xy(w)
     u_ref = torch.from_numpy(Coefficients("poisson").exact(xy[:, 0], xy[:, 1])).cuda()
-    w2 = dict(w, n_paths=2000)
+    w2 = dict(w, n_paths=w["n_paths"])                   # the configuration's N = 1e4
     plain = ctx.assemble(w2, lut=lut, u_ref=u_ref)
     ctx.sync()
     d_plain = plain["diag"].view(-1, pdd.DIAG_WIDTH).cpu().numpy().copy()
