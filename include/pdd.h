@@ -63,6 +63,9 @@ typedef struct pdd_ctx pdd_ctx;
  *              A = sigma sigma^T.  Under PDD_EXIT_GM each assembly first
  *              reads the whole table once (max |sxx|, |sxy|, |syy|) to bound
  *              the shift; the exact shift uses a_nn at the projection.
+ *              Float32 production reads a cell-major copy of the table
+ *              ((lut_n - 1)^2 cells of 128 B, which must stay below 4 GiB:
+ *              lut_n <= 5793, else PDD_EUNSUPPORTED).
  *   CONSTSOL   sigma, d, c of VARCOEF, f = c, g = 1 (u = 1 is the solution)
  *   EXITTIME   sigma = sqrt(2) I, d = 0, c = 0, f = -1, g = 0 (u = mean exit
  *              time, eq. 26)

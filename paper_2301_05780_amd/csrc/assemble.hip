@@ -167,8 +167,8 @@ __device__ __forceinline__ uint32_t to_uniform_u(uint32_t v) {
 __device__ __forceinline__ void lut_fetch_coop(const CoefParams& cp, float x, float y, CoopLds* C, int lane,
                                                Coef<float>& o) {
   const int n = cp.lut_n;
-  float fx = (x - (float)cp.x0) * cp.lut_sx;
-  float fy = (y - (float)cp.y0) * cp.lut_sy;
+  float fx = (x - cp.x0f) * cp.lut_sx;
+  float fy = (y - cp.y0f) * cp.lut_sy;
   fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));     // NaN maps to 0: every address stays in the table
   fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
   const int i = min((int)fx, n - 2);
@@ -179,16 +179,19 @@ __device__ __forceinline__ void lut_fetch_coop(const CoefParams& cp, float x, fl
   C->ty[lane] = fy - (float)j;
   wave_sync();
   const int q = lane & 7, g = lane >> 3;
+  // 32-bit byte offsets from the table's base (the host keeps (n-1)^2 cells
+  // of 128 B below 4 GiB), so each load takes the base from scalar registers
+  const char* cb = reinterpret_cast<const char*>(cp.cells);
   float4 v[8];                                // all eight loads in flight
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = cp.cells[(size_t)C->cell[8 * r + g] * 8 + q];
+  for (int r = 0; r < 8; ++r)
+    v[r] = *reinterpret_cast<const float4*>(cb + (C->cell[8 * r + g] * 128u + (uint32_t)q * 16u));
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int pth = 8 * r + g;
     const float tx = C->tx[pth], ty = C->ty[pth];
-    const float lo = v[r].x + tx * (v[r].y - v[r].x);
-    const float hi = v[r].z + tx * (v[r].w - v[r].z);
-    C->res[pth * 8 + q] = lo + ty * (hi - lo);
+    // the cell holds the field's bilinear form (a, b, c, d): a + tx b + ty (c + tx d)
+    C->res[pth * 8 + q] = __builtin_fmaf(ty, __builtin_fmaf(tx, v[r].w, v[r].z), __builtin_fmaf(tx, v[r].y, v[r].x));
   }
   wave_sync();
   const float4 a = reinterpret_cast<const float4*>(C->res)[2 * lane];

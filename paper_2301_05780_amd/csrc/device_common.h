@@ -29,6 +29,11 @@ struct U4 { uint32_t a, b, c, d; };
 
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                        uint32_t k0, uint32_t k1) {
+  // The keys are uniform (kernel arguments).  Marking them as redefined here
+  // makes each call derive its round keys with scalar adds, instead of the
+  // twenty loop-invariant round keys being hoisted into scalar registers,
+  // spilled, and read back with one vector lane read each per draw.
+  __asm__ volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -135,8 +140,8 @@ __device__ __forceinline__ void lut_fetch(const CoefParams& cp, double x, double
 
 __device__ __forceinline__ void lut_fetch(const CoefParams& cp, float x, float y, Coef<float>& o) {
   const int n = cp.lut_n;
-  float fx = (x - (float)cp.x0) * cp.lut_sx;
-  float fy = (y - (float)cp.y0) * cp.lut_sy;
+  float fx = (x - cp.x0f) * cp.lut_sx;
+  float fy = (y - cp.y0f) * cp.lut_sy;
   fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
   fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
   const int i = min((int)fx, n - 2);
@@ -468,8 +473,8 @@ __device__ __forceinline__ void lut_sigma(const CoefParams& cp, double x, double
 __device__ __forceinline__ void lut_sigma(const CoefParams& cp, float x, float y, float& sxx, float& sxy,
                                           float& syy) {
   const int n = cp.lut_n;
-  float fx = (x - (float)cp.x0) * cp.lut_sx;
-  float fy = (y - (float)cp.y0) * cp.lut_sy;
+  float fx = (x - cp.x0f) * cp.lut_sx;
+  float fy = (y - cp.y0f) * cp.lut_sy;
   fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
   fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
   const int i = min((int)fx, n - 2);

@@ -74,8 +74,9 @@ pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& 
   if (co.kind != PDD_COEF_LUT || run.precision != PDD_FP32_PRODUCTION) return PDD_OK;
   if (run.cv && run.cv->mode == PDD_CV_NETWORK) return PDD_OK;     // that kernel reads the node table per lane
   const size_t bytes = (size_t)(co.lut_n - 1) * (size_t)(co.lut_n - 1) * 128;
-  if (bytes > ((size_t)64 << 30))
-    return bad(ctx, PDD_EUNSUPPORTED, "LUT too large for the float32 cell-major copy (at most 64 GiB, lut_n <= 23171)");
+  // the float32 kernels address the copy with 32-bit byte offsets
+  if (bytes >= ((size_t)1 << 32))
+    return bad(ctx, PDD_EUNSUPPORTED, "LUT too large for the float32 cell-major copy (below 4 GiB, lut_n <= 5793)");
   hipError_t e;
   if (ctx->lut_cells.bytes < bytes) {
     if (capturing) return bad(ctx, PDD_EINVAL, "LUT cell table not allocated; run the same call once before capturing");
@@ -106,6 +107,8 @@ void fill_asm_params(const GeoCache& gcr, const pdd_coeffs& co, const pdd_run& r
   P.coef.a = co.param[0];
   P.coef.lut = co.lut;
   P.coef.x0 = g.x0; P.coef.x1 = g.x1; P.coef.y0 = g.y0; P.coef.y1 = g.y1;
+  P.coef.x0f = (float)g.x0;
+  P.coef.y0f = (float)g.y0;
   if (co.kind == PDD_COEF_LUT) {
     P.coef.lut_sx = (float)((co.lut_n - 1) / (g.x1 - g.x0));
     P.coef.lut_sy = (float)((co.lut_n - 1) / (g.y1 - g.y0));

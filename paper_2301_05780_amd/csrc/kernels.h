@@ -52,12 +52,15 @@ struct CoefParams {
   const float* lut;           // LUT kind
   double x0, x1, y0, y1;      // domain (LUT node grid spans it)
   float lut_sx, lut_sy;       // (n-1)/(x1-x0), (n-1)/(y1-y0)
+  float x0f, y0f;             // (float)x0, (float)y0 for the float32 table reads
   // LUT kind under the Gobet-Menozzi rule: max |sxx|, |sxy|, |syy| over the
   // table's nodes as float bit patterns (device, written by launch_lut_bound)
   const uint32_t* lut_max;
   // float32 LUT kernels: the table re-laid cell by cell (launch_lut_cells):
-  // cell (i, j) holds 8 float4, float4 q = field q at the corners
-  // (i, j), (i+1, j), (i, j+1), (i+1, j+1); q = 7 is zero padding (128 B per cell)
+  // cell (i, j) holds 8 float4, float4 q = the bilinear form of field q on
+  // the cell, (v00, v10 - v00, v01 - v00, v11 - v10 - v01 + v00) of its
+  // corners (i, j), (i+1, j), (i, j+1), (i+1, j+1); q = 7 is zero padding
+  // (128 B per cell)
   const float4* cells;
 };
 

@@ -51,7 +51,10 @@ __global__ __launch_bounds__(BLK) void k_lut_bound(const float4* lut, int64_t no
   }
 }
 
-// One thread per output float4: cell c = j (n-1) + i, field q.
+// One thread per output float4: cell c = j (n-1) + i, field q, holding the
+// bilinear form of the field on the cell, (v00, v10 - v00, v01 - v00,
+// v11 - v10 - v01 + v00), so that v(tx, ty) = a + tx b + ty (c + tx d) is
+// three fused multiply-adds.
 __global__ __launch_bounds__(BLK) void k_lut_cells(const float* __restrict__ lut, int32_t n, float4* __restrict__ cells) {
   const int64_t m = n - 1;
   const int64_t total = m * m * 8;
@@ -64,7 +67,8 @@ __global__ __launch_bounds__(BLK) void k_lut_cells(const float* __restrict__ lut
     if (q < 7) {
       const float* p00 = lut + (j * n + i) * PDD_LUT_STRIDE + q;
       const float* p01 = p00 + (int64_t)n * PDD_LUT_STRIDE;
-      v = make_float4(p00[0], p00[PDD_LUT_STRIDE], p01[0], p01[PDD_LUT_STRIDE]);
+      const float v00 = p00[0], v10 = p00[PDD_LUT_STRIDE], v01 = p01[0], v11 = p01[PDD_LUT_STRIDE];
+      v = make_float4(v00, v10 - v00, v01 - v00, (v11 - v10) - (v01 - v00));
     }
     cells[t] = v;
   }

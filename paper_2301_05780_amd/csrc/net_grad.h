@@ -293,8 +293,8 @@ __device__ __forceinline__ void grad_lut(const AsmParams& P, double x, double y,
 
 __device__ __forceinline__ void grad_lut(const AsmParams& P, float x, float y, float& gx, float& gy) {
   const int n = P.cv_lut_n;
-  float fx = fminf(fmaxf((x - (float)P.x0) * P.cv_lut_sx, 0.0f), (float)(n - 1));
-  float fy = fminf(fmaxf((y - (float)P.y0) * P.cv_lut_sy, 0.0f), (float)(n - 1));
+  float fx = fminf(fmaxf((x - P.coef.x0f) * P.cv_lut_sx, 0.0f), (float)(n - 1));
+  float fy = fminf(fmaxf((y - P.coef.y0f) * P.cv_lut_sy, 0.0f), (float)(n - 1));
   const int i = min((int)fx, n - 2), j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
   const float2* row0 = reinterpret_cast<const float2*>(P.cv_lut) + (size_t)j * n + i;
