@@ -65,7 +65,9 @@ typedef struct pdd_ctx pdd_ctx;
  *              the shift; the exact shift uses a_nn at the projection.
  *              Float32 production reads a cell-major copy of the table
  *              ((lut_n - 1)^2 cells of 128 B, which must stay below 4 GiB:
- *              lut_n <= 5793, else PDD_EUNSUPPORTED).
+ *              lut_n <= 5793, else PDD_EUNSUPPORTED), of only the varying
+ *              fields when at most two vary (pdd_set_table_read).  The
+ *              table pointer must be 16-byte aligned (PDD_EINVAL).
  *   CONSTSOL   sigma, d, c of VARCOEF, f = c, g = 1 (u = 1 is the solution)
  *   EXITTIME   sigma = sqrt(2) I, d = 0, c = 0, f = -1, g = 0 (u = mean exit
  *              time, eq. 26)
@@ -575,6 +577,20 @@ pdd_status pdd_get_spare_rows(const pdd_ctx* ctx, int32_t* spare);
 /* The context's current refill threshold (as set by pdd_set_refill or chosen
  * by pdd_autotune). */
 pdd_status pdd_get_refill(const pdd_ctx* ctx, int32_t* min_idle);
+/* Table reads of the float32 LUT assembly.  With read_all = 0 (the
+ * default) every assembly first scans the table for fields that hold the
+ * same finite value at every node; when at most two of the seven fields
+ * vary, the cell-major copy keeps only their bilinear forms and the kernel
+ * reads them one lane per path, taking the constant fields from the
+ * table's first node.  read_all = 1 keeps the full eight-form copy and the
+ * cooperative read.  Both give the same bits (the bilinear form of a
+ * constant field evaluates to the constant exactly). */
+pdd_status pdd_set_table_read(pdd_ctx* ctx, int32_t read_all);
+/* After an assembly of the LUT family in float32 production (waits for the
+ * context's stream): *varying receives bit q set for each field q (sxx, sxy,
+ * syy, dx, dy, c, f) the scan found varying or not finite; *lane_read 1 when
+ * the lane-per-path read of the varying fields ran, 0 for the full read. */
+pdd_status pdd_table_fields(pdd_ctx* ctx, uint32_t* varying, int32_t* lane_read);
 /* Shape of the last assembly launch: grid, block and number of tickets. */
 pdd_status pdd_last_launch(const pdd_ctx* ctx, int32_t* grid, int32_t* block, int64_t* tickets);
 /* enable != 0: bracket every assembly kernel launched from now on with a pair

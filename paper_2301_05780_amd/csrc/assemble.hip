@@ -84,13 +84,20 @@ struct CoopLds {
 };
 static_assert(sizeof(CoopLds) % 16 == 0, "CoopLds alignment");
 
+// The table block of a wave's LDS: none, the cooperative-read block, or the
+// eight constant-field values of the lane-per-path kernel.
+enum { TB_NONE = 0, TB_COOP = 1, TB_LANE = 2 };
+template <int TB>
+constexpr size_t table_block_bytes() {
+  return TB == TB_COOP ? sizeof(CoopLds) : (TB == TB_LANE ? 8 * sizeof(float) : 0);
+}
+
 // per-wave LDS bytes: two row headers, the exit queue (records + meta words)
-// and the cooperative-read block when COOP; the tally rows follow all waves'
-// blocks as the workgroup's pool (a 16-byte free mask, then the rows)
-template <typename R, bool COOP, bool BATCH>
+// and the table block; the tally rows follow all waves' blocks as the
+// workgroup's pool (a 16-byte free mask, then the rows)
+template <typename R, int TB, bool BATCH>
 constexpr size_t wave_lds_bytes() {
-  return 2 * sizeof(WaveBuf<R, BATCH>) + QCAP * sizeof(ExitRec<R>) + QCAP * sizeof(uint32_t) +
-         (COOP ? sizeof(CoopLds) : 0);
+  return 2 * sizeof(WaveBuf<R, BATCH>) + QCAP * sizeof(ExitRec<R>) + QCAP * sizeof(uint32_t) + table_block_bytes<TB>();
 }
 constexpr size_t POOL_HEAD = 16;
 
@@ -200,6 +207,68 @@ __device__ __forceinline__ void lut_fetch_coop(const CoefParams& cp, float x, fl
   o.dy = b.x; o.c = b.y; o.f = b.z;
 }
 
+// Bilinear coefficients from the lane-read layout, one lane per path: the
+// stored forms at the lane's own cell, the other fields constant.  Cell,
+// weights and formula are the cooperative read's, and a constant field's
+// form (v, 0, 0, 0) evaluates to v + 0 there, the value kept for it, so both
+// reads give the same bits.
+__device__ __forceinline__ void lut_fetch_lane(const CoefParams& cp, uint32_t lay, const float* kc_lds, float x, float y,
+                                               Coef<float>& o) {
+  // the layout word (see CoefParams::lut_info), decoded at every call: the
+  // empty asm keeps the decoded fields and the field masks from being
+  // hoisted out of the path loop, where they would only occupy registers
+  __asm__ volatile("" : "+s"(lay));
+  const int k1 = (int)(lay & 15u), k2 = (int)((lay >> 4) & 15u);
+  const uint32_t stride = ((lay >> 8) & 15u) == 2u ? 32u : 16u;
+  const int n = cp.lut_n;
+  float fx = (x - cp.x0f) * cp.lut_sx;
+  float fy = (y - cp.y0f) * cp.lut_sy;
+  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
+  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  const int i = min((int)fx, n - 2);
+  const int j = min((int)fy, n - 2);
+  const float tx = fx - (float)i, ty = fy - (float)j;
+  const uint32_t off = ((uint32_t)j * (uint32_t)(n - 1) + (uint32_t)i) * stride;
+  const char* cb = reinterpret_cast<const char*>(cp.cells);
+  const float4 a = *reinterpret_cast<const float4*>(cb + off);
+  float v2 = 0.0f;
+  if (k2 < 7) {
+    const float4 b = *reinterpret_cast<const float4*>(cb + (off + 16u));
+    v2 = __builtin_fmaf(ty, __builtin_fmaf(tx, b.w, b.z), __builtin_fmaf(tx, b.y, b.x));
+  }
+  const float v1 = __builtin_fmaf(ty, __builtin_fmaf(tx, a.w, a.z), __builtin_fmaf(tx, a.y, a.x));
+  // the constant fields' values, kept in the wave's LDS
+  const float4 c0 = reinterpret_cast<const float4*>(kc_lds)[0];
+  const float4 c1 = reinterpret_cast<const float4*>(kc_lds)[1];
+  const float kc[7] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z};
+  auto pick = [&](int q) __attribute__((always_inline)) { return q == k1 ? v1 : (q == k2 ? v2 : kc[q]); };
+  o.sxx = pick(0); o.sxy = pick(1); o.syy = pick(2); o.dx = pick(3);
+  o.dy = pick(4); o.c = pick(5); o.f = pick(6);
+}
+
+// The full layout (all seven forms of the cell) read by one lane per path:
+// the lane-per-path kernel's fallback when the layout word says the copy is
+// full, the same cell, weights and formula as the cooperative read.
+__device__ __forceinline__ void lut_fetch_cell(const CoefParams& cp, float x, float y, Coef<float>& o) {
+  const int n = cp.lut_n;
+  float fx = (x - cp.x0f) * cp.lut_sx;
+  float fy = (y - cp.y0f) * cp.lut_sy;
+  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
+  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  const int i = min((int)fx, n - 2);
+  const int j = min((int)fy, n - 2);
+  const float tx = fx - (float)i, ty = fy - (float)j;
+  const char* cb = reinterpret_cast<const char*>(cp.cells) + ((uint32_t)j * (uint32_t)(n - 1) + (uint32_t)i) * 128u;
+  float v[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const float4 a = reinterpret_cast<const float4*>(cb)[q];
+    v[q] = __builtin_fmaf(ty, __builtin_fmaf(tx, a.w, a.z), __builtin_fmaf(tx, a.y, a.x));
+  }
+  o.sxx = v[0]; o.sxy = v[1]; o.syy = v[2]; o.dx = v[3];
+  o.dy = v[4]; o.c = v[5]; o.f = v[6];
+}
+
 // Per-buffer uniform values used at refill (kept in scalar registers).
 template <typename R>
 struct BufU {
@@ -217,16 +286,21 @@ struct GeoView {
   int L;
 };
 
-template <int KIND, bool F64, int CV, bool BATCH, bool RBF = false, bool HK = false>
+template <int KIND, bool F64, int CV, bool BATCH, bool RBF = false, bool HK = false, bool LANEK = false>
 __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   using R = typename std::conditional<F64, double, float>::type;
   constexpr bool CVON = CV != PDD_CV_NONE;
   // float32 table reads go through the cooperative read (except beside the
-  // network, whose registers leave no room for it); it and the network
-  // gradient are wave-wide operations, evaluated with every lane before each
-  // half step
-  constexpr bool COOP = KIND == PDD_COEF_LUT && !F64 && CV != PDD_CV_NETWORK;
-  constexpr bool WAVEWIDE = !F64 && (CV == PDD_CV_NETWORK || COOP);
+  // network, whose registers leave no room for it), or, in the lane-per-path
+  // kernel (LANEK), through the per-lane read of the varying fields; the
+  // cooperative read and the network gradient are wave-wide operations,
+  // evaluated with every lane before each half step, and the lane kernel
+  // keeps the same loop
+  static_assert(!LANEK || (KIND == PDD_COEF_LUT && !F64 && CV != PDD_CV_NETWORK && !BATCH), "lane kernel");
+  constexpr bool LANE = LANEK;
+  constexpr bool COOP = KIND == PDD_COEF_LUT && !F64 && CV != PDD_CV_NETWORK && !LANE;
+  constexpr bool WAVEWIDE = !F64 && (CV == PDD_CV_NETWORK || COOP || LANE);
+  constexpr int TB = COOP ? TB_COOP : (LANE ? TB_LANE : TB_NONE);
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -245,13 +319,14 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   }
   using WB = WaveBuf<R, BATCH>;
   unsigned char* gbase = lds0 + net_lds_bytes<F64, CV>();
-  unsigned char* wbase = gbase + (size_t)wid * wave_lds_bytes<R, COOP, BATCH>();
+  unsigned char* wbase = gbase + (size_t)wid * wave_lds_bytes<R, TB, BATCH>();
   WB* B = reinterpret_cast<WB*>(wbase);
   ExitRec<R>* Q = reinterpret_cast<ExitRec<R>*>(wbase + 2 * sizeof(WB));
   uint32_t* Qm = reinterpret_cast<uint32_t*>(wbase + 2 * sizeof(WB) + QCAP * sizeof(ExitRec<R>));
-  CoopLds* CW = reinterpret_cast<CoopLds*>(wbase + wave_lds_bytes<R, false, BATCH>());   // COOP only
+  CoopLds* CW = reinterpret_cast<CoopLds*>(wbase + wave_lds_bytes<R, TB_NONE, BATCH>());   // COOP only
+  float* KCW = reinterpret_cast<float*>(wbase + wave_lds_bytes<R, TB_NONE, BATCH>());       // LANE only
   // the workgroup's pool of tally rows and its free mask (bit r: row r free)
-  unsigned char* pbase = gbase + (size_t)waves_per_block * wave_lds_bytes<R, COOP, BATCH>();
+  unsigned char* pbase = gbase + (size_t)waves_per_block * wave_lds_bytes<R, TB, BATCH>();
   uint32_t* pool = reinterpret_cast<uint32_t*>(pbase);
   double* rows = reinterpret_cast<double*>(pbase + POOL_HEAD);
   // Batched launches and the table family share the rows through the pool;
@@ -327,6 +402,18 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   // network control variate: unit coordinates of the domain (x - x0) / (x1 - x0)
   const R ux0 = (R)P.x0, uy0 = (R)P.y0;
   const R usx = (R)(1.0 / (P.x1 - P.x0)), usy = (R)(1.0 / (P.y1 - P.y0));
+  // float32 table: the layout of its cell copy; for the lane-per-path read,
+  // the constant fields go to the wave's LDS (the cooperative block, unused
+  // then, or the lane kernel's own)
+  uint32_t lut_lay = 0u;
+  float* KC = COOP ? CW->res : KCW;
+  if constexpr (COOP || LANE) {
+    lut_lay = to_uniform_u(P.coef.lut_info[1]);
+    if (lut_lay & LUT_LANE_READ) {
+      if (lane < 8) KC[lane] = __uint_as_float(P.coef.lut_info[8 + lane]);
+      wave_sync();
+    }
+  }
 
   auto geo = [&](const WB& W) __attribute__((always_inline)) -> GeoView<R> {
     GeoView<R> G;
@@ -718,11 +805,21 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           gx *= usx;
           gy *= usy;
         }
-        if constexpr (COOP) lut_fetch_coop(cpl, x, y, CW, lane, cc);
+        if constexpr (COOP) {
+          if (lut_lay & LUT_LANE_READ) lut_fetch_lane(cpl, lut_lay, KC, x, y, cc);
+          else lut_fetch_coop(cpl, x, y, CW, lane, cc);
+        }
+        if constexpr (LANE) {
+          // only lanes that step read (the others' loads would be wasted)
+          if (active && !ex) {
+            if (lut_lay & LUT_LANE_READ) lut_fetch_lane(cpl, lut_lay, KC, x, y, cc);
+            else lut_fetch_cell(cpl, x, y, cc);
+          }
+        }
       };
       auto step = [&](R z0, R z1) __attribute__((always_inline)) {
         if constexpr (CV == PDD_CV_GRAD_LUT) grad_lut(P, x, y, gx, gy);
-        if constexpr (COOP) em_step_c<KIND, R, CVON>(cc, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
+        if constexpr (COOP || LANE) em_step_c<KIND, R, CVON>(cc, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
         else em_step<KIND, R, CVON>(cpl, lh, lsq, z0, z1, x, y, Y, Z, gx, gy, &Xi);
       };
       prep();
@@ -836,6 +933,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 template <int KIND, int CV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble_w4(AsmParams P) {
   assemble_body<KIND, false, CV, false>(P);
+}
+
+// float32 table family whose copy holds only the varying fields (at most two
+// of the seven): one lane per path reads them, with no cooperative block in
+// LDS.  Four waves per SIMD (at most 128 VGPRs, which it fits without
+// spills; capped lower, its spills cost far more than the extra waves gain)
+template <int CV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble_lane(AsmParams P) {
+  assemble_body<PDD_COEF_LUT, false, CV, false, false, false, true>(P);
 }
 
 // Sum a knot's partial rows (ticket order, then side order) into its CSR row,
@@ -1008,36 +1114,45 @@ const void* rbf_kernel(int precision, int kind, int cv) {
   return precision == PDD_FP64_SAME_STREAM ? pick_rbf<true>(kind, cv) : pick_rbf<false>(kind, cv);
 }
 
-const void* assemble_kernel(int precision, int kind, int cv, bool batch, bool hk = false) {
+// lane: the float32 table family with the lane-read layout (single launches
+// with the launch's h, hat interpolation)
+const void* assemble_kernel(int precision, int kind, int cv, bool batch, bool hk = false, bool lane = false) {
+  if (lane && !batch && !hk && precision == PDD_FP32_PRODUCTION && kind == PDD_COEF_LUT) {
+    if (cv == PDD_CV_NONE) return reinterpret_cast<const void*>(&k_assemble_lane<PDD_CV_NONE>);
+    if (cv == PDD_CV_GRAD_LUT) return reinterpret_cast<const void*>(&k_assemble_lane<PDD_CV_GRAD_LUT>);
+  }
   if (batch) return precision == PDD_FP64_SAME_STREAM ? pick_batch<true>(kind, cv) : pick_batch<false>(kind, cv);
   return precision == PDD_FP64_SAME_STREAM ? pick<true>(kind, cv, hk) : pick<false>(kind, cv, hk);
 }
 
 }  // namespace
 
-size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch, int pool_rows) {
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch, int pool_rows,
+                          bool lane) {
   const size_t waves = (size_t)block / 64;
   const size_t rows = POOL_HEAD + (size_t)(pool_rows > 0 ? pool_rows : 2 * (int)waves) * row_len * sizeof(double);
   if (precision == PDD_FP64_SAME_STREAM) {
     const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<true, PDD_CV_NETWORK>() : 0;
-    return net + rows + waves * (batch ? wave_lds_bytes<double, false, true>() : wave_lds_bytes<double, false, false>());
+    return net + rows + waves * (batch ? wave_lds_bytes<double, TB_NONE, true>() : wave_lds_bytes<double, TB_NONE, false>());
   }
   const size_t net = cv_mode == PDD_CV_NETWORK ? net_lds_bytes<false, PDD_CV_NETWORK>() : 0;
-  if (batch) return net + rows + waves * wave_lds_bytes<float, false, true>();
-  return net + rows + waves * (kind == PDD_COEF_LUT && cv_mode != PDD_CV_NETWORK ? wave_lds_bytes<float, true, false>()
-                                                                                 : wave_lds_bytes<float, false, false>());
+  if (batch) return net + rows + waves * wave_lds_bytes<float, TB_NONE, true>();
+  if (kind == PDD_COEF_LUT && cv_mode != PDD_CV_NETWORK)
+    return net + rows + waves * (lane ? wave_lds_bytes<float, TB_LANE, false>() : wave_lds_bytes<float, TB_COOP, false>());
+  return net + rows + waves * wave_lds_bytes<float, TB_NONE, false>();
 }
 
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
-                              int* blocks_per_cu, bool per_knot_h) {
-  const void* f = assemble_kernel(precision, kind, cv_mode, batch, per_knot_h);
+                              int* blocks_per_cu, bool per_knot_h, bool lane) {
+  const void* f = assemble_kernel(precision, kind, cv_mode, batch, per_knot_h, lane);
   if (!f) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 hipError_t launch_assemble(const AsmParams& p, int precision, int grid, int block, size_t lds_bytes,
                            hipStream_t stream) {
-  const void* f = assemble_kernel(precision, p.coef.kind, p.cv_mode, p.insts != nullptr, p.h_knot != nullptr);
+  const void* f = assemble_kernel(precision, p.coef.kind, p.cv_mode, p.insts != nullptr, p.h_knot != nullptr,
+                                  p.table_lane != 0);
   if (!f) return hipErrorInvalidValue;
   AsmParams arg = p;
   void* args[] = {&arg};

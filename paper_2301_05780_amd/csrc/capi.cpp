@@ -662,6 +662,27 @@ pdd_status pdd_set_spare_rows(pdd_ctx* ctx, int32_t spare) {
   return PDD_OK;
 }
 
+pdd_status pdd_set_table_read(pdd_ctx* ctx, int32_t read_all) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_set_table_read: null context");
+  if (read_all != 0 && read_all != 1) return fail(ctx, PDD_EINVAL, "pdd_set_table_read: read_all must be 0 or 1");
+  ctx->table_read_all = read_all;
+  return PDD_OK;
+}
+
+pdd_status pdd_table_fields(pdd_ctx* ctx, uint32_t* varying, int32_t* lane_read) {
+  if (!ctx) return fail(nullptr, PDD_EINVAL, "pdd_table_fields: null context");
+  if (!varying || !lane_read) return fail(ctx, PDD_EINVAL, "pdd_table_fields: null output");
+  if (!ctx->lut_info.ptr) return fail(ctx, PDD_EINVAL, "pdd_table_fields: no float32 LUT assembly has run");
+  uint32_t w[2];
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+  if ((e = hipMemcpy(w, ctx->lut_info.ptr, sizeof(w), hipMemcpyDeviceToHost)) != hipSuccess)
+    return check_hip(ctx, e, "read LUT layout");
+  *varying = w[0];
+  *lane_read = (w[1] & LUT_LANE_READ) ? 1 : 0;
+  return PDD_OK;
+}
+
 pdd_status pdd_get_spare_rows(const pdd_ctx* ctx, int32_t* spare) {
   if (!ctx || !spare) return PDD_EINVAL;
   *spare = ctx->spare_rows;

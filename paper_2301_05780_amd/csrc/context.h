@@ -137,6 +137,9 @@ struct pdd_ctx {
   pdd::DeviceBuffer ticket_counter;
   pdd::DeviceBuffer lut_max;         // LUT + GM: table-wide |sigma| maxima
   pdd::DeviceBuffer lut_cells;       // float32 LUT assembly: cell-major copy of the table
+  pdd::DeviceBuffer lut_info;        // its varying fields, layout and constant fields (16 words)
+  int32_t table_read_all = 0;        // 1: the full cooperative read even for constant fields
+  bool lut_lane = false;             // the last eager float32 table assembly found the lane-read layout
   // shape of the last assembly launch (reported by pdd_last_launch)
   int last_grid = 0, last_block = 0;
   int64_t last_tickets = 0;
@@ -168,7 +171,8 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);
 pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
 // LUT family in float32: enqueue the cell-major copy of the table and point
 // P.coef.cells at it (no-op otherwise).
-pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
+bool uses_lut_cells(const pdd_coeffs& co, const pdd_run& run);
+pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, bool capturing, bool* lane_layout);
 // RBF interpolation: build (once per geometry and shape parameter) and
 // upload the inverses of the stencil matrices; point P.rbf_inv at them.
 pdd_status prepare_rbf(pdd_ctx* ctx, const Geometry& g, const pdd_run& run, AsmParams& P, bool capturing);

@@ -28,6 +28,8 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
     return bad(ctx, PDD_EINVAL, "coeffs.param[0]: amplitude must lie in [0, 1)");
   if (c.kind == PDD_COEF_LUT && (!c.lut || c.lut_n < 2 || c.lut_n > 65536))
     return bad(ctx, PDD_EINVAL, "coeffs: LUT kind needs a device table and 2 <= lut_n <= 65536");
+  if (c.kind == PDD_COEF_LUT && (reinterpret_cast<uintptr_t>(c.lut) & 15u) != 0)
+    return bad(ctx, PDD_EINVAL, "coeffs: the LUT must be 16-byte aligned");
   if (r.precision != PDD_FP64_SAME_STREAM && r.precision != PDD_FP32_PRODUCTION)
     return bad(ctx, PDD_EINVAL, "run.precision: unknown precision mode");
   if (r.exit_rule != PDD_EXIT_NAIVE && r.exit_rule != PDD_EXIT_GM)
@@ -70,9 +72,19 @@ pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& 
   return PDD_OK;
 }
 
-pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing) {
-  if (co.kind != PDD_COEF_LUT || run.precision != PDD_FP32_PRODUCTION) return PDD_OK;
-  if (run.cv && run.cv->mode == PDD_CV_NETWORK) return PDD_OK;     // that kernel reads the node table per lane
+bool uses_lut_cells(const pdd_coeffs& co, const pdd_run& run) {
+  if (co.kind != PDD_COEF_LUT || run.precision != PDD_FP32_PRODUCTION) return false;
+  return !(run.cv && run.cv->mode == PDD_CV_NETWORK);     // that kernel reads the node table per lane
+}
+
+// The cell-major copy of the table and its layout word.  *lane_layout tells
+// whether the copy holds only the varying fields: read back from the device
+// (waiting for the stream) on eager calls, the last eager call's answer
+// while a graph is captured (the kernels read the layout word themselves,
+// so a stale answer picks the slower kernel, never a wrong result).
+pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, bool capturing, bool* lane_layout) {
+  *lane_layout = false;
+  if (!uses_lut_cells(co, run)) return PDD_OK;
   const size_t bytes = (size_t)(co.lut_n - 1) * (size_t)(co.lut_n - 1) * 128;
   // the float32 kernels address the copy with 32-bit byte offsets
   if (bytes >= ((size_t)1 << 32))
@@ -83,9 +95,22 @@ pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& 
     if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
     if ((e = ctx->lut_cells.reserve(bytes)) != hipSuccess) return check_hip(ctx, e, "hipMalloc(lut cells)");
   }
-  if ((e = launch_lut_cells(co.lut, co.lut_n, ctx->lut_cells.as<float4>(), ctx->stream)) != hipSuccess)
+  if (!ctx->lut_info.ptr) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "LUT layout word not allocated; run the same call once before capturing");
+    if ((e = ctx->lut_info.reserve(16 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(lut info)");
+  }
+  if ((e = launch_lut_cells(co.lut, co.lut_n, ctx->table_read_all, ctx->lut_info.as<uint32_t>(),
+                            ctx->lut_cells.as<float4>(), ctx->stream)) != hipSuccess)
     return check_hip(ctx, e, "launch LUT cells");
-  P.coef.cells = ctx->lut_cells.as<float4>();
+  if (!capturing) {
+    uint32_t lay = 0u;
+    if ((e = hipMemcpyAsync(&lay, ctx->lut_info.as<uint32_t>() + 1, sizeof(lay), hipMemcpyDeviceToHost, ctx->stream)) !=
+        hipSuccess)
+      return check_hip(ctx, e, "read LUT layout");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
+    ctx->lut_lane = (lay & LUT_LANE_READ) != 0u;
+  }
+  *lane_layout = ctx->lut_lane;
   return PDD_OK;
 }
 
@@ -187,6 +212,12 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
     if (st != PDD_OK) return st;
   }
 
+  // float32 table: its cell copy first, whose layout picks the kernel
+  bool lane_layout = false;
+  if ((st = prepare_lut_cells(ctx, job.coeffs, run, capturing, &lane_layout)) != PDD_OK) return st;
+  const bool rbf = run.interp == PDD_INTERP_RBF_IMQ;
+  const bool lane_kernel = lane_layout && !rbf && hk.empty();
+
   // launch shape
   const int slot_len = g.slot_len;
   const int row_len = 4 * slot_len + EX_COUNT;
@@ -195,16 +226,18 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   // the tally rows of a workgroup: a shared pool for the table family (spare
   // rows as set on the context), two per wave otherwise
   auto rows_for = [&](int blk) { return job.coeffs.kind == PDD_COEF_LUT ? pool_rows_for(ctx, blk) : 2 * (blk / 64); };
-  size_t lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false, rows_for(block));
+  size_t lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false, rows_for(block),
+                                  lane_kernel);
   while (lds > 65536 && block > 64) {
     block /= 2;
-    lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false, rows_for(block));
+    lds = assemble_lds_bytes(run.precision, job.coeffs.kind, row_len, block, cv_mode, false, rows_for(block),
+                             lane_kernel);
   }
   if (lds > 65536) return bad(ctx, PDD_EUNSUPPORTED, "tally rows exceed the LDS of one workgroup");
   int per_cu = 0;
-  const bool rbf = run.interp == PDD_INTERP_RBF_IMQ;
   e = rbf ? assemble_occupancy_rbf(run.precision, job.coeffs.kind, cv_mode, block, lds, &per_cu)
-          : assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, false, block, lds, &per_cu, !hk.empty());
+          : assemble_occupancy(run.precision, job.coeffs.kind, cv_mode, false, block, lds, &per_cu, !hk.empty(),
+                               lane_kernel);
   if (e != hipSuccess) return check_hip(ctx, e, "occupancy query");
   per_cu = std::max(per_cu, 1);
   int64_t grid = ctx->force_grid ? ctx->force_grid : (int64_t)ctx->cu_count * per_cu;
@@ -313,7 +346,11 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.dump = run.dump_paths > 0 ? run.dump : nullptr;
   P.ticket_counter = nullptr;
   if ((st = prepare_lut_bound(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
-  if ((st = prepare_lut_cells(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
+  if (uses_lut_cells(job.coeffs, run)) {
+    P.coef.cells = ctx->lut_cells.as<float4>();
+    P.coef.lut_info = ctx->lut_info.as<uint32_t>();
+  }
+  P.table_lane = lane_kernel ? 1 : 0;
   if (rbf && (st = prepare_rbf(ctx, g, run, P, capturing)) != PDD_OK) return st;
   if (ctx->schedule == PDD_SCHEDULE_DYNAMIC) {
     if (!ctx->ticket_counter.ptr) {

@@ -60,9 +60,20 @@ struct CoefParams {
   // cell (i, j) holds 8 float4, float4 q = the bilinear form of field q on
   // the cell, (v00, v10 - v00, v01 - v00, v11 - v10 - v01 + v00) of its
   // corners (i, j), (i+1, j), (i, j+1), (i+1, j+1); q = 7 is zero padding
-  // (128 B per cell)
+  // (128 B per cell).  When at most two of the seven fields vary over the
+  // table (launch_lut_cells decides, see lut_info), the copy holds only the
+  // varying fields' forms, 16 B each per cell, and the kernels read it one
+  // lane per path.
   const float4* cells;
+  // float32 LUT kernels (device, written by launch_lut_cells):
+  // [0] bit q set when field q varies over the table (or is not finite);
+  // [1] layout of `cells`: 0 = all eight forms per cell, else
+  //     LUT_LANE_READ | k1 | k2 << 4 | count << 8 (the count <= 2 varying
+  //     fields k1, k2 in that order, 15 for none; count 0 reads field k1 = 6);
+  // [8 + q] the float bits of field q at node 0, plus 0 (16 words in all)
+  const uint32_t* lut_info;
 };
+constexpr uint32_t LUT_LANE_READ = 0x80000000u;
 
 struct AsmParams {
   const KnotDesc* desc;
@@ -107,6 +118,9 @@ struct AsmParams {
   // per-knot time steps h_i (eq. 40), device, nullable: the launch's h
   // (single launches of the generic and RBF kernels)
   const double* h_knot;
+  // host only: launch the lane-per-path table kernel (the copy of the table
+  // was found in the lane-read layout)
+  int32_t table_lane;
 };
 
 // Extras stored after the 4 slot_len G slots of a partial row.
@@ -156,14 +170,20 @@ hipError_t launch_calibrate(const AsmParams& P, int precision, int64_t n, int32_
                             const double* u0, double* rec, double* stats, hipStream_t stream,
                             double* alpha = nullptr, int32_t slot_len = 0);
 hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipStream_t stream);
-// Cell-major copy of a LUT (lut.hip): cells[(j (n-1) + i) 8 + q], (n-1)^2 cells of 128 B.
-hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream);
+// Cell-major copy of a LUT (lut.hip): the varying fields of the table
+// (info[0]) and, for read_all == 0 and at most two of them, their forms
+// only (count float4 per cell, count >= 1), else all eight per cell,
+// cells[(j (n-1) + i) 8 + q]; the layout goes to info[1], node 0's values
+// to info[8..14].  `cells` holds (n-1)^2 cells of 128 B; info 16 words.
+hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, uint32_t* info, float4* cells,
+                            hipStream_t stream);
 // Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
 // LDS bytes of an assembly workgroup; pool_rows tally rows shared by its
 // waves (0: two per wave)
-size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch, int pool_rows);
+size_t assemble_lds_bytes(int precision, int kind, int row_len, int block, int cv_mode, bool batch, int pool_rows,
+                          bool lane = false);
 // Kernel attribute query for occupancy-based grid sizing.
 hipError_t assemble_occupancy(int precision, int kind, int cv_mode, bool batch, int block, size_t lds_bytes,
-                              int* blocks_per_cu, bool per_knot_h = false);
+                              int* blocks_per_cu, bool per_knot_h = false, bool lane = false);
 
 }  // namespace pdd

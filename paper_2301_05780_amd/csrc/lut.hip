@@ -5,6 +5,13 @@
 // cell: the four corners of each field contiguous, the seven fields of a cell
 // in one line.
 //
+// Tables often hold fields that do not vary at all (a constant diffusion
+// matrix, no drift, no reaction).  Such a field's bilinear form on every cell
+// is (v, 0, 0, 0), whose value is v itself, so the copy leaves it out when at
+// most two fields vary: each cell then holds only the varying fields' forms
+// (16 or 32 B), read by one lane per path, and the constant fields come from
+// the table's first node.  The values are the same bits the full read gives.
+//
 // The Gobet-Menozzi test of the LUT family (Sec. 2.3) shifts each side
 // inwards by c_GM sqrt(a_nn(P)) sqrt(h) with a_nn taken at the projection P,
 // which varies along the side.  The assembly first tests against a shift
@@ -51,17 +58,68 @@ __global__ __launch_bounds__(BLK) void k_lut_bound(const float4* lut, int64_t no
   }
 }
 
-// One thread per output float4: cell c = j (n-1) + i, field q, holding the
-// bilinear form of the field on the cell, (v00, v10 - v00, v01 - v00,
-// v11 - v10 - v01 + v00), so that v(tx, ty) = a + tx b + ty (c + tx d) is
-// three fused multiply-adds.
-__global__ __launch_bounds__(BLK) void k_lut_cells(const float* __restrict__ lut, int32_t n, float4* __restrict__ cells) {
+// Field q counts as varying when any node's value differs from node 0's in
+// its bits, or when node 0's value is not finite (an infinite constant would
+// turn into NaN differences in the full copy; such fields keep the full read).
+// Also keeps node 0's values + 0 (a constant field's value in the full read,
+// which turns -0 into +0) in info[8 + q].
+__global__ void k_lut_vary_init(const float* lut, uint32_t* info) {
+  if (threadIdx.x == 0) {
+    uint32_t m = 0u;
+    for (int q = 0; q < 7; ++q) {
+      if (!isfinite(lut[q])) m |= 1u << q;
+      info[8 + q] = __float_as_uint(lut[q] + 0.0f);
+    }
+    info[15] = 0u;
+    info[0] = m;
+    info[1] = 0u;
+  }
+}
+
+__global__ __launch_bounds__(BLK) void k_lut_vary(const float4* lut, int64_t nodes, uint32_t* info) {
+  const float4 r0 = lut[0], r1 = lut[1];
+  uint32_t m = 0u;
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < nodes; i += stride) {
+    const float4 a = lut[2 * i], b = lut[2 * i + 1];
+    m |= (__float_as_uint(a.x) != __float_as_uint(r0.x) ? 1u : 0u) |
+         (__float_as_uint(a.y) != __float_as_uint(r0.y) ? 2u : 0u) |
+         (__float_as_uint(a.z) != __float_as_uint(r0.z) ? 4u : 0u) |
+         (__float_as_uint(a.w) != __float_as_uint(r0.w) ? 8u : 0u) |
+         (__float_as_uint(b.x) != __float_as_uint(r1.x) ? 16u : 0u) |
+         (__float_as_uint(b.y) != __float_as_uint(r1.y) ? 32u : 0u) |
+         (__float_as_uint(b.z) != __float_as_uint(r1.z) ? 64u : 0u);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
+  if ((threadIdx.x & 63) == 0 && m) atomicOr(info, m);
+}
+
+// One thread per output float4, holding the bilinear form of a field on a
+// cell, (v00, v10 - v00, v01 - v00, v11 - v10 - v01 + v00), so that
+// v(tx, ty) = a + tx b + ty (c + tx d) is three fused multiply-adds.  Full
+// layout: cell c = j (n-1) + i holds the forms of fields 0..6 and a zero
+// float4; lane-read layout: the forms of the varying fields k1 (, k2).
+__global__ __launch_bounds__(BLK) void k_lut_cells(const float* __restrict__ lut, int32_t n, int32_t read_all,
+                                                   uint32_t* info, float4* __restrict__ cells) {
+  const uint32_t vm = info[0] & 0x7Fu;
+  const int cnt = __popc(vm);
+  uint32_t layout = 0u;
+  int k1 = 6, k2 = 15, shift = 3;              // shift: log2 of the float4 per cell
+  if (!read_all && cnt <= 2) {
+    if (cnt >= 1) k1 = __ffs(vm) - 1;
+    if (cnt == 2) k2 = 31 - __clz(vm);
+    layout = LUT_LANE_READ | (uint32_t)k1 | ((uint32_t)k2 << 4) | ((uint32_t)cnt << 8);
+    shift = cnt == 2 ? 1 : 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) info[1] = layout;
   const int64_t m = n - 1;
-  const int64_t total = m * m * 8;
+  const int64_t total = (m * m) << shift;
   const int64_t stride = (int64_t)gridDim.x * BLK;
   for (int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x; t < total; t += stride) {
-    const int q = (int)(t & 7);
-    const int64_t c = t >> 3;
+    const int s = (int)(t & ((1 << shift) - 1));
+    const int q = layout ? (s == 0 ? k1 : k2) : s;
+    const int64_t c = t >> shift;
     const int64_t j = c / m, i = c - j * m;
     float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (q < 7) {
@@ -76,11 +134,20 @@ __global__ __launch_bounds__(BLK) void k_lut_cells(const float* __restrict__ lut
 
 }  // namespace
 
-hipError_t launch_lut_cells(const float* lut, int32_t lut_n, float4* cells, hipStream_t stream) {
+hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, uint32_t* info, float4* cells,
+                            hipStream_t stream) {
+  const int64_t nodes = (int64_t)lut_n * lut_n;
+  const int64_t want_v = (nodes + BLK - 1) / BLK;
+  hipLaunchKernelGGL(k_lut_vary_init, dim3(1), dim3(64), 0, stream, lut, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lut_vary, dim3((unsigned)(want_v < 4096 ? want_v : 4096)), dim3(BLK), 0, stream,
+                     reinterpret_cast<const float4*>(lut), nodes, info);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t total = (int64_t)(lut_n - 1) * (lut_n - 1) * 8;
   const int64_t want = (total + BLK - 1) / BLK;
   const unsigned grid = (unsigned)(want < 16384 ? want : 16384);
-  hipLaunchKernelGGL(k_lut_cells, dim3(grid), dim3(BLK), 0, stream, lut, lut_n, cells);
+  hipLaunchKernelGGL(k_lut_cells, dim3(grid), dim3(BLK), 0, stream, lut, lut_n, read_all, info, cells);
   return hipGetLastError();
 }
 

@@ -111,6 +111,8 @@ def lib():
             "pdd_get_refill": [vp, C.POINTER(i32)],
             "pdd_set_spare_rows": [vp, i32],
             "pdd_get_spare_rows": [vp, C.POINTER(i32)],
+            "pdd_set_table_read": [vp, i32],
+            "pdd_table_fields": [vp, C.POINTER(C.c_uint32), C.POINTER(i32)],
             "pdd_solve": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_solve_noalloc": [vp, i64, vp, vp, vp, vp, vp, f64, i32, C.POINTER(i32), C.POINTER(f64)],
             "pdd_mlp_init": [vp, vp, C.c_uint64],
@@ -306,6 +308,18 @@ class Context:
         r = C.c_int32()
         self.check(lib().pdd_get_spare_rows(self.h, C.byref(r)))
         return r.value
+
+    def set_table_read(self, read_all=False):
+        """Float32 table assemblies: read only the varying fields when at most
+        two vary (default), or always all seven cooperatively."""
+        self.check(lib().pdd_set_table_read(self.h, 1 if read_all else 0))
+
+    def table_fields(self):
+        """(bit mask of the fields found varying, lane-per-path read used) of
+        the last float32 table assembly."""
+        m, r = C.c_uint32(), C.c_int32()
+        self.check(lib().pdd_table_fields(self.h, C.byref(m), C.byref(r)))
+        return m.value, bool(r.value)
 
     def refill(self):
         r = C.c_int32()
