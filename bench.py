@@ -69,7 +69,9 @@ ALG_OPS = {
 # poisson 25, varcoef 60, amplitude 40, table 70 (index math aside: 7 fields x
 # 3 lerps x 2 FLOP = 42, Euler update, exit test).  The gradient-table control
 # variate adds 23: 2 fields x 3 lerps x 2 FLOP, F = sigma^T grad v (6) and
-# Xi -= Y F . dW (5).
+# Xi -= Y F . dW (5).  `frac` uses these counts; when the table read skips
+# constant fields, `executed_flop_per_path_step` counts only the varying
+# fields' interpolations.
 FP32_FLOP = {"poisson": 25, "varcoef": 60, "amplitude": 40, "lut": 70}
 CV_FLOP = {"none": 0, "table": 23}
 FP32_PEAK_TFLOPS = 157.3
@@ -731,6 +733,13 @@ def line_for(ctx, w, r, args, lut=None, cv_name="none"):
     achieved = flop * steps_per_launch / kavg / 1e12
     key = w["name"] + ("" if cv_name == "none" else f"_cv_{cv_name}")
     ops = ALG_OPS[w["kind"]]
+    executed = None
+    if w["kind"] == "lut" and cv_name != "network":
+        # with the lane-per-path read only the varying fields are interpolated
+        # (6 FLOP each); the constant ones cost nothing
+        mask, lane = ctx.table_fields()
+        if lane:
+            executed = flop - 6 * (7 - max(bin(mask & 0x7F).count("1"), 1))
     return {
         "value": steps_per_launch * args.steps / r["elapsed"],
         "ms_per_step": r["elapsed"] / args.steps * 1e3,
@@ -739,6 +748,8 @@ def line_for(ctx, w, r, args, lut=None, cv_name="none"):
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": committed_traffic(key),
                      "fp32_flop_per_path_step": flop, "kernel_source": kernel_source_hash(),
                      "valu_issue_frac": committed_valu_busy(key),
+                     "executed_flop_per_path_step": executed,
+                     "executed_frac": None if executed is None else executed * steps_per_launch / kavg / 1e12 / FP32_PEAK_TFLOPS,
                      "issue_model": {"lane_ops_per_path_step": ops, "peak_tops": VALU_PEAK_TOPS,
                                      "frac": ops * steps_per_launch / kavg / 1e12 / VALU_PEAK_TOPS}},
         "counters_key": key,
@@ -880,6 +891,24 @@ def main():
     if ctx is not None and not args.no_secondary and args.workload == "large_lut":
         r.pop("out", None)
         sec = {}
+        # the same workload with every field read from the table at every step
+        # (the cooperative read of the full cell-major copy)
+        ctx.set_table_read(True)
+        rf = time_single(ctx, w, args.steps, args.warmup, lut=lut, tune=args.autotune, cv=spec)
+        ff = line_for(ctx, w, rf, args, lut, cv_name)
+        ff["roofline"]["traffic"] = None               # the committed counters are the lane kernel's
+        ff["roofline"]["valu_issue_frac"] = None
+        g_, b_, t_ = ctx.last_launch()
+        sec["large_lut_full_table_read"] = {
+            "note": ("the headline workload with the table scan's shortcut off: all seven fields (six of them "
+                     "constant here) read from the full cell-major copy by the cooperative read"),
+            "path_steps_per_s": ff["value"], "ms_per_step": ff["ms_per_step"], "kernel_ms_avg": ff["kernel_ms_avg"],
+            "roofline": ff["roofline"], "launch": {"grid": g_, "block": b_, "tickets": t_}}
+        rf.pop("out", None)
+        ctx.set_table_read(False)
+        ctx.set_launch(0, 0, 0)
+        ctx.set_refill(1)
+        ctx.set_spare_rows(-1)
         wv = workloads.varcoef("gm")
         rv = time_single(ctx, wv, args.steps, args.warmup, tune=args.autotune)
         fv = line_for(ctx, wv, rv, args)

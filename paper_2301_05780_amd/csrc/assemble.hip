@@ -269,6 +269,28 @@ __device__ __forceinline__ void lut_fetch_cell(const CoefParams& cp, float x, fl
   o.dy = v[4]; o.c = v[5]; o.f = v[6];
 }
 
+// Exact Gobet-Menozzi threshold of side o for a table whose sigma fields are
+// constant (scan word bits 0-2 clear; the values at lut_info[8..10]): a_nn is
+// then the same at every projection, so the threshold is fixed per knot as
+// for the closed-form families, and the exact test at the projection that
+// the general table needs would decide every point the same way (its
+// bilinear reads of a constant field give the constant, and its arithmetic
+// is this one).
+template <typename R>
+__device__ __forceinline__ R lut_const_threshold(const uint32_t* info, double sqrt_h, const KnotDesc& d, int o) {
+  const double line = d.line[o];
+  const bool vert = (o == 0 || o == 2);
+  const R sxx = (R)__uint_as_float(info[8]), sxy = (R)__uint_as_float(info[9]), syy = (R)__uint_as_float(info[10]);
+  R thr;
+  {
+#pragma clang fp contract(off)
+    const R ann = vert ? (sxx * sxx + sxy * sxy) : (sxy * sxy + syy * syy);
+    const R delta = (R)kGM * sqrt(ann) * (R)sqrt_h;
+    thr = (o < 2) ? (R)line - delta : (R)line + delta;
+  }
+  return (o < 2) ? nextafter(thr, (R)-INFINITY) : nextafter(thr, (R)INFINITY);
+}
+
 // Per-buffer uniform values used at refill (kept in scalar registers).
 template <typename R>
 struct BufU {
@@ -407,8 +429,12 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   // then, or the lane kernel's own)
   uint32_t lut_lay = 0u;
   float* KC = COOP ? CW->res : KCW;
+  // GM exits on a table with constant sigma: exact thresholds, no refinement
+  // (kept as bit 16 of lut_lay, a bit the layout word leaves clear)
+  constexpr uint32_t SIG_EXACT = 1u << 16;
   if constexpr (COOP || LANE) {
     lut_lay = to_uniform_u(P.coef.lut_info[1]);
+    if (P.exit_rule == PDD_EXIT_GM && (to_uniform_u(P.coef.lut_info[0]) & 7u) == 0u) lut_lay |= SIG_EXACT;
     if (lut_lay & LUT_LANE_READ) {
       if (lane < 8) KC[lane] = __uint_as_float(P.coef.lut_info[8 + lane]);
       wave_sync();
@@ -440,6 +466,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         const uint32_t cand = (uint32_t)(x > ehx) | ((uint32_t)(y > ehy) << 1) | ((uint32_t)(x < elx) << 2) |
                               ((uint32_t)(y < ely) << 3);
         if (cand == 0) { fl = 0; return true; }
+        if (lut_lay & SIG_EXACT) { fl = cand; return true; }   // the thresholds are exact
         fl = lut_gm_refine<R>(P.coef, lsq, B[buf].d.line, x, y, cand);
         return fl != 0;
       }
@@ -692,7 +719,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       CoefParams cp = P.coef;
       double sqh = sqk;
       if constexpr (BATCH) { cp.a = W.I.a; sqh = W.I.sqrt_h; }
-      W.ebox[lane] = exit_threshold<KIND, R>(cp, P.exit_rule, sqh, W.d, lane);
+      W.ebox[lane] = (lut_lay & SIG_EXACT) ? lut_const_threshold<R>(P.coef.lut_info, sqh, W.d, lane)
+                                           : exit_threshold<KIND, R>(cp, P.exit_rule, sqh, W.d, lane);
     }
     wave_sync();
     BufU<R> u;

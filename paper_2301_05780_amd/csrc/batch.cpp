@@ -397,6 +397,7 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
              q.run.cv ? q.run.cv->mode : PDD_CV_NONE, q.run.interp, q.run.rbf_c, hn, hh);
     sig += buf;
   }
+  sig += ctx->table_read_all ? "|table:all" : "|table:scan";
   auto run_once = [&]() -> pdd_status {
     if (n_inst == 1) {
       const pdd_instance& q = inst[0];

@@ -124,3 +124,29 @@ def test_stale_lane_choice_in_a_graph_reads_the_full_layout():
                 g.sync()
         finally:
             g.close()
+
+
+def test_constant_sigma_thresholds_equal_the_exact_test():
+    """With sigma constant over the table, float32 GM exits use fixed exact
+    thresholds instead of the candidate test plus the exact test at the
+    projection.  Against a table whose sxy holds -0 at one node (a varying
+    field to the scan, so the exact test runs, but every interpolated value
+    and a_nn are the same), G, b and the per-knot sums agree bit for bit."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pdd.Context(0)
+    try:
+        w = _work("gm")
+        a = workloads.poisson_lut(N)
+        b = a.copy()
+        b[N // 2, N // 2, 1] = -0.0
+        outs = []
+        for tab, mask in ((a, 1 << 6), (b, (1 << 1) | (1 << 6))):
+            out = c.assemble(w, lut=torch.from_numpy(tab).cuda())
+            c.sync()
+            assert c.table_fields() == (mask, True)
+            outs.append(out)
+        for k in ("val", "b", "diag"):
+            assert torch.equal(outs[0][k], outs[1][k]), k
+    finally:
+        c.close()
