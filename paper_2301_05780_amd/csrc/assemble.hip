@@ -237,13 +237,19 @@ __device__ __forceinline__ void lut_fetch_lane(const CoefParams& cp, uint32_t la
     v2 = __builtin_fmaf(ty, __builtin_fmaf(tx, b.w, b.z), __builtin_fmaf(tx, b.y, b.x));
   }
   const float v1 = __builtin_fmaf(ty, __builtin_fmaf(tx, a.w, a.z), __builtin_fmaf(tx, a.y, a.x));
-  // the constant fields' values, kept in the wave's LDS
+  // the constant fields' values, kept in the wave's LDS; the second stored
+  // field's selects only when there is one (a uniform branch)
   const float4 c0 = reinterpret_cast<const float4*>(kc_lds)[0];
   const float4 c1 = reinterpret_cast<const float4*>(kc_lds)[1];
-  const float kc[7] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z};
-  auto pick = [&](int q) __attribute__((always_inline)) { return q == k1 ? v1 : (q == k2 ? v2 : kc[q]); };
-  o.sxx = pick(0); o.sxy = pick(1); o.syy = pick(2); o.dx = pick(3);
-  o.dy = pick(4); o.c = pick(5); o.f = pick(6);
+  float f[7] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z};
+#pragma unroll
+  for (int q = 0; q < 7; ++q) f[q] = q == k1 ? v1 : f[q];
+  if (k2 < 7) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = q == k2 ? v2 : f[q];
+  }
+  o.sxx = f[0]; o.sxy = f[1]; o.syy = f[2]; o.dx = f[3];
+  o.dy = f[4]; o.c = f[5]; o.f = f[6];
 }
 
 // The full layout (all seven forms of the cell) read by one lane per path:

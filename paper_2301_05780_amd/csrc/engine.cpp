@@ -53,6 +53,8 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
     if (cv.mode == PDD_CV_NETWORK && !cv.params) return bad(ctx, PDD_EINVAL, "run.cv: network mode needs params");
     if (cv.mode == PDD_CV_GRAD_LUT && (!cv.grad_lut || cv.lut_n < 2 || cv.lut_n > 65536))
       return bad(ctx, PDD_EINVAL, "run.cv: grad-table mode needs a table and 2 <= lut_n <= 65536");
+    if (cv.mode == PDD_CV_GRAD_LUT && (reinterpret_cast<uintptr_t>(cv.grad_lut) & 7u) != 0)
+      return bad(ctx, PDD_EINVAL, "run.cv: the gradient table must be 8-byte aligned");
     if (cv.mode != PDD_CV_NONE && (c.kind == PDD_COEF_CONSTSOL || c.kind == PDD_COEF_EXITTIME))
       return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variates are built for the poisson, varcoef, amplitude, LUT and eq43 families");
   }
