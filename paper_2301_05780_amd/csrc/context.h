@@ -168,7 +168,8 @@ void fill_asm_params(const GeoCache& gc, const pdd_coeffs& co, const pdd_run& ru
 pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job);
 // LUT family under the GM rule: enqueue the table-bound kernels and point
 // P.coef.lut_max at their result (no-op otherwise).
-pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing);
+pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing,
+                             bool scanned = false);
 // LUT family in float32: enqueue the cell-major copy of the table and point
 // P.coef.cells at it (no-op otherwise).
 bool uses_lut_cells(const pdd_coeffs& co, const pdd_run& run);

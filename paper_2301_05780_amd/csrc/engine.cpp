@@ -61,14 +61,18 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
   return PDD_OK;
 }
 
-pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing) {
+// The table-wide sigma maxima of the Gobet-Menozzi bound; `scanned`: the
+// table scan of prepare_lut_cells has gathered them already (the float32
+// table assembly).
+pdd_status prepare_lut_bound(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& run, AsmParams& P, bool capturing,
+                             bool scanned) {
   if (co.kind != PDD_COEF_LUT || run.exit_rule != PDD_EXIT_GM) return PDD_OK;
   hipError_t e;
   if (!ctx->lut_max.ptr) {
     if (capturing) return bad(ctx, PDD_EINVAL, "LUT bound scratch not allocated; run the same call once before capturing");
     if ((e = ctx->lut_max.reserve(4 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(lut bound)");
   }
-  if ((e = launch_lut_bound(co.lut, co.lut_n, ctx->lut_max.as<uint32_t>(), ctx->stream)) != hipSuccess)
+  if (!scanned && (e = launch_lut_bound(co.lut, co.lut_n, ctx->lut_max.as<uint32_t>(), ctx->stream)) != hipSuccess)
     return check_hip(ctx, e, "launch LUT bound");
   P.coef.lut_max = ctx->lut_max.as<uint32_t>();
   return PDD_OK;
@@ -101,8 +105,14 @@ pdd_status prepare_lut_cells(pdd_ctx* ctx, const pdd_coeffs& co, const pdd_run& 
     if (capturing) return bad(ctx, PDD_EINVAL, "LUT layout word not allocated; run the same call once before capturing");
     if ((e = ctx->lut_info.reserve(16 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(lut info)");
   }
+  const bool gm = run.exit_rule == PDD_EXIT_GM;
+  if (gm && !ctx->lut_max.ptr) {
+    if (capturing) return bad(ctx, PDD_EINVAL, "LUT bound scratch not allocated; run the same call once before capturing");
+    if ((e = ctx->lut_max.reserve(4 * sizeof(uint32_t))) != hipSuccess) return check_hip(ctx, e, "hipMalloc(lut bound)");
+  }
   if ((e = launch_lut_cells(co.lut, co.lut_n, ctx->table_read_all, ctx->lut_info.as<uint32_t>(),
-                            ctx->lut_cells.as<float4>(), ctx->stream)) != hipSuccess)
+                            gm ? ctx->lut_max.as<uint32_t>() : nullptr, ctx->lut_cells.as<float4>(), ctx->stream)) !=
+      hipSuccess)
     return check_hip(ctx, e, "launch LUT cells");
   if (!capturing) {
     uint32_t lay = 0u;
@@ -347,7 +357,8 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   P.dump_paths = run.dump_paths;
   P.dump = run.dump_paths > 0 ? run.dump : nullptr;
   P.ticket_counter = nullptr;
-  if ((st = prepare_lut_bound(ctx, job.coeffs, run, P, capturing)) != PDD_OK) return st;
+  if ((st = prepare_lut_bound(ctx, job.coeffs, run, P, capturing, uses_lut_cells(job.coeffs, run))) != PDD_OK)
+    return st;
   if (uses_lut_cells(job.coeffs, run)) {
     P.coef.cells = ctx->lut_cells.as<float4>();
     P.coef.lut_info = ctx->lut_info.as<uint32_t>();

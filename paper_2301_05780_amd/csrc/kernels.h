@@ -175,8 +175,9 @@ hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipS
 // only (count float4 per cell, count >= 1), else all eight per cell,
 // cells[(j (n-1) + i) 8 + q]; the layout goes to info[1], node 0's values
 // to info[8..14].  `cells` holds (n-1)^2 cells of 128 B; info 16 words.
-hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, uint32_t* info, float4* cells,
-                            hipStream_t stream);
+// bmax (nullable, 4 words): the same pass writes launch_lut_bound's maxima.
+hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, uint32_t* info, uint32_t* bmax,
+                            float4* cells, hipStream_t stream);
 // Dynamic LDS bytes per workgroup for a precision, row length, block size and CV mode.
 // LDS bytes of an assembly workgroup; pool_rows tally rows shared by its
 // waves (0: two per wave)

@@ -62,8 +62,10 @@ __global__ __launch_bounds__(BLK) void k_lut_bound(const float4* lut, int64_t no
 // its bits, or when node 0's value is not finite (an infinite constant would
 // turn into NaN differences in the full copy; such fields keep the full read).
 // Also keeps node 0's values + 0 (a constant field's value in the full read,
-// which turns -0 into +0) in info[8 + q].
-__global__ void k_lut_vary_init(const float* lut, uint32_t* info) {
+// which turns -0 into +0) in info[8 + q], and clears the sigma maxima (bmax,
+// nullable) that the scan gathers for the Gobet-Menozzi bound.
+__global__ void k_lut_vary_init(const float* lut, uint32_t* info, uint32_t* bmax) {
+  if (bmax && threadIdx.x < 4) bmax[threadIdx.x] = 0u;
   if (threadIdx.x == 0) {
     uint32_t m = 0u;
     for (int q = 0; q < 7; ++q) {
@@ -76,12 +78,16 @@ __global__ void k_lut_vary_init(const float* lut, uint32_t* info) {
   }
 }
 
-__global__ __launch_bounds__(BLK) void k_lut_vary(const float4* lut, int64_t nodes, uint32_t* info) {
+// With bmax, the same pass gathers max |sxx|, |sxy|, |syy| as k_lut_bound does.
+__global__ __launch_bounds__(BLK) void k_lut_vary(const float4* lut, int64_t nodes, uint32_t* info, uint32_t* bmax) {
   const float4 r0 = lut[0], r1 = lut[1];
-  uint32_t m = 0u;
+  uint32_t m = 0u, m0 = 0u, m1 = 0u, m2 = 0u;
   const int64_t stride = (int64_t)gridDim.x * BLK;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < nodes; i += stride) {
     const float4 a = lut[2 * i], b = lut[2 * i + 1];
+    m0 = max(m0, __float_as_uint(fabsf(a.x)));
+    m1 = max(m1, __float_as_uint(fabsf(a.y)));
+    m2 = max(m2, __float_as_uint(fabsf(a.z)));
     m |= (__float_as_uint(a.x) != __float_as_uint(r0.x) ? 1u : 0u) |
          (__float_as_uint(a.y) != __float_as_uint(r0.y) ? 2u : 0u) |
          (__float_as_uint(a.z) != __float_as_uint(r0.z) ? 4u : 0u) |
@@ -91,8 +97,20 @@ __global__ __launch_bounds__(BLK) void k_lut_vary(const float4* lut, int64_t nod
          (__float_as_uint(b.z) != __float_as_uint(r1.z) ? 64u : 0u);
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
-  if ((threadIdx.x & 63) == 0 && m) atomicOr(info, m);
+  for (int off = 32; off > 0; off >>= 1) {
+    m |= (uint32_t)__shfl_xor((int)m, off, 64);
+    m0 = max(m0, (uint32_t)__shfl_xor((int)m0, off, 64));
+    m1 = max(m1, (uint32_t)__shfl_xor((int)m1, off, 64));
+    m2 = max(m2, (uint32_t)__shfl_xor((int)m2, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (m) atomicOr(info, m);
+    if (bmax) {
+      atomicMax(bmax + 0, m0);
+      atomicMax(bmax + 1, m1);
+      atomicMax(bmax + 2, m2);
+    }
+  }
 }
 
 // One thread per output float4, holding the bilinear form of a field on a
@@ -134,15 +152,15 @@ __global__ __launch_bounds__(BLK) void k_lut_cells(const float* __restrict__ lut
 
 }  // namespace
 
-hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, uint32_t* info, float4* cells,
-                            hipStream_t stream) {
+hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, uint32_t* info, uint32_t* bmax,
+                            float4* cells, hipStream_t stream) {
   const int64_t nodes = (int64_t)lut_n * lut_n;
   const int64_t want_v = (nodes + BLK - 1) / BLK;
-  hipLaunchKernelGGL(k_lut_vary_init, dim3(1), dim3(64), 0, stream, lut, info);
+  hipLaunchKernelGGL(k_lut_vary_init, dim3(1), dim3(64), 0, stream, lut, info, bmax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lut_vary, dim3((unsigned)(want_v < 4096 ? want_v : 4096)), dim3(BLK), 0, stream,
-                     reinterpret_cast<const float4*>(lut), nodes, info);
+                     reinterpret_cast<const float4*>(lut), nodes, info, bmax);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t total = (int64_t)(lut_n - 1) * (lut_n - 1) * 8;
   const int64_t want = (total + BLK - 1) / BLK;
