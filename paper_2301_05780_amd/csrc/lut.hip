@@ -51,7 +51,18 @@ __global__ __launch_bounds__(BLK) void k_lut_bound(const float4* lut, int64_t no
     m1 = max(m1, (uint32_t)__shfl_xor((int)m1, off, 64));
     m2 = max(m2, (uint32_t)__shfl_xor((int)m2, off, 64));
   }
+  __shared__ uint32_t part[BLK / 64][3];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    part[w][0] = m0; part[w][1] = m1; part[w][2] = m2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < BLK / 64; ++k) {
+      m0 = max(m0, part[k][0]);
+      m1 = max(m1, part[k][1]);
+      m2 = max(m2, part[k][2]);
+    }
     atomicMax(out + 0, m0);
     atomicMax(out + 1, m1);
     atomicMax(out + 2, m2);
@@ -103,7 +114,21 @@ __global__ __launch_bounds__(BLK) void k_lut_vary(const float4* lut, int64_t nod
     m1 = max(m1, (uint32_t)__shfl_xor((int)m1, off, 64));
     m2 = max(m2, (uint32_t)__shfl_xor((int)m2, off, 64));
   }
+  // the block's waves combine in LDS, then one thread updates the words
+  // (same-address atomics from every wave serialise in the L2)
+  __shared__ uint32_t part[BLK / 64][4];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    part[w][0] = m; part[w][1] = m0; part[w][2] = m1; part[w][3] = m2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < BLK / 64; ++k) {
+      m |= part[k][0];
+      m0 = max(m0, part[k][1]);
+      m1 = max(m1, part[k][2]);
+      m2 = max(m2, part[k][3]);
+    }
     if (m) atomicOr(info, m);
     if (bmax) {
       atomicMax(bmax + 0, m0);
@@ -159,7 +184,7 @@ hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, u
   hipLaunchKernelGGL(k_lut_vary_init, dim3(1), dim3(64), 0, stream, lut, info, bmax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lut_vary, dim3((unsigned)(want_v < 4096 ? want_v : 4096)), dim3(BLK), 0, stream,
+  hipLaunchKernelGGL(k_lut_vary, dim3((unsigned)(want_v < 1024 ? want_v : 1024)), dim3(BLK), 0, stream,
                      reinterpret_cast<const float4*>(lut), nodes, info, bmax);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t total = (int64_t)(lut_n - 1) * (lut_n - 1) * 8;
@@ -172,7 +197,7 @@ hipError_t launch_lut_cells(const float* lut, int32_t lut_n, int32_t read_all, u
 hipError_t launch_lut_bound(const float* lut, int32_t lut_n, uint32_t* out, hipStream_t stream) {
   const int64_t nodes = (int64_t)lut_n * lut_n;
   const int64_t want = (nodes + BLK - 1) / BLK;
-  const unsigned grid = (unsigned)(want < 2048 ? want : 2048);
+  const unsigned grid = (unsigned)(want < 1024 ? want : 1024);
   hipLaunchKernelGGL(k_lut_zero, dim3(1), dim3(64), 0, stream, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
