@@ -938,8 +938,8 @@ def main():
         ctx.close()
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        if w["kind"] == "lut":
-            workers = 1                       # the float64 table is 1 GiB per process
+        if w["kind"] == "lut" and not args.cpu_workers:
+            workers = min(workers, 8)         # each process holds the float64 table (1 GiB, ~1.6 GB in all)
         cw = dict(w)
         if args.workload == "batched":
             cw = workloads.batched()[0]

@@ -72,3 +72,15 @@ def test_spectral_tables_reject_bad_degrees():
     for p in (1, 64):
         with pytest.raises(pdd.PddError):
             pdd.spectral_tables(p)
+
+
+def test_context_setters_reject_a_null_context():
+    """Setters and queries that take a context refuse a null one (no device
+    needed): the table-read switch and its report among them."""
+    import ctypes as C
+    L = pdd.lib()
+    assert L.pdd_set_table_read(None, 0) == pdd.EINVAL
+    m, r = C.c_uint32(), C.c_int32()
+    assert L.pdd_table_fields(None, C.byref(m), C.byref(r)) == pdd.EINVAL
+    assert L.pdd_set_spare_rows(None, 0) == pdd.EINVAL
+    assert L.pdd_set_refill(None, 1) == pdd.EINVAL

@@ -150,3 +150,29 @@ def test_constant_sigma_thresholds_equal_the_exact_test():
             assert torch.equal(outs[0][k], outs[1][k]), k
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("n", [2, 3, 6])
+def test_tiny_tables(ctx, n):
+    """Tables of one, four and 25 cells (every path in the first or last
+    cell of a row or column, the edge clamps taken on both sides): the lane
+    read equals the full read bit for bit."""
+    w = dict(_work("gm"), lut_n=n)
+    tab = workloads.poisson_lut(n)
+    lut = torch.from_numpy(tab).cuda()
+    outs = []
+    for read_all in (False, True):
+        ctx.set_table_read(read_all)
+        out = ctx.assemble(w, lut=lut)
+        ctx.sync()
+        assert ctx.table_fields() == (1 << 6, not read_all)
+        outs.append({k: out[k].clone() for k in ("val", "b", "diag")})
+    ctx.set_table_read(False)
+    for k in ("val", "b", "diag"):
+        assert torch.equal(outs[0][k], outs[1][k]), (n, k)
+
+
+def test_table_read_switch_rejects_other_values(ctx):
+    with pytest.raises(pdd.PddError) as e:
+        ctx.check(pdd.lib().pdd_set_table_read(ctx.h, 2))
+    assert e.value.status == pdd.EINVAL
