@@ -213,11 +213,28 @@ def cpu_baseline(w, workers, target_s=15.0):
         if pool is not None:
             pool.terminate()
             pool.join()
+    # the single-core rate: one process, the same knot order, about a third
+    # of the time
+    single = None
+    if workers > 1:
+        _oracle_inputs(w)
+        _oracle_sample((w, spread[-1]))                # warm-up
+        s_steps, s_count = 0, 0
+        t1 = time.perf_counter()
+        s_dt = 0.0
+        for k in spread:
+            s_steps += _oracle_sample((w, k))
+            s_count += 1
+            s_dt = time.perf_counter() - t1
+            if s_dt >= target_s / 3:
+                break
+        single = dict(value=s_steps / s_dt, sample=f"{s_count} knots, {s_steps} path-steps in {s_dt:.1f} s on 1 process")
     hc = host_cpu()
     return dict(value=steps / dt, unit="path-steps/s", cores=workers, kind="oracle",
                 sample=f"{count} of {n} knots (spread over the domain), all {w['n_paths']} paths each, "
                        f"{steps} path-steps in {dt:.1f} s wall on {workers} processes"
                        + (", gradient-table control variate" if w.get("cv_table_n") else ""),
+                single_core=single if single is not None else dict(value=steps / dt, sample="the measurement above"),
                 host_nproc=hc["nproc"], host_cpus_available=hc["affinity"], cpu_model=hc["model"])
 
 
