@@ -14,7 +14,8 @@
  *   - Asynchrony: device work is enqueued on the context's stream and the call
  *     returns; results are valid after pdd_sync or after the caller
  *     synchronises that stream.  pdd_solve is the exception: it reads back
- *     convergence scalars and therefore returns after the solve has finished.
+ *     convergence scalars and therefore returns after the solve has finished;
+ *     a float32 table assembly waits for its table scan (see pdd_assemble).
  *   - Errors: host-side validation fails fast with PDD_EINVAL before touching
  *     any output; HIP failures give PDD_EDEVICE (asynchronous kernel faults
  *     surface at the next synchronising call).  pdd_last_error returns a
@@ -240,7 +241,11 @@ pdd_status pdd_knot_xy(const pdd_partition* part, const pdd_knots* knots, double
  * Random numbers: Philox4x32-10, counter = (draw j, path p, knot k, instance),
  * draw j feeding steps 2j and 2j+1 through Box-Muller.
  * Outputs (device): row_ptr int32[n+1], col_idx int32[nnz], val double[nnz],
- * b double[n], diag double[n * PDD_DIAG_WIDTH] (nullable). */
+ * b double[n], diag double[n * PDD_DIAG_WIDTH] (nullable).
+ * A float32 assembly of the LUT family (without the network control
+ * variate) synchronises the context's stream once, after the table scan, to
+ * choose its kernel (pdd_set_table_read); while the stream is captured into
+ * a graph it keeps the previous eager call's choice instead. */
 pdd_status pdd_assemble(pdd_ctx* ctx, const pdd_coeffs* coeffs, const pdd_partition* part,
                         const pdd_knots* knots, const pdd_run* run,
                         int32_t* row_ptr, int32_t* col_idx, double* val, double* b,
