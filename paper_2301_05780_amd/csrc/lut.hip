@@ -16,8 +16,10 @@
 // inwards by c_GM sqrt(a_nn(P)) sqrt(h) with a_nn taken at the projection P,
 // which varies along the side.  The assembly first tests against a shift
 // built from a bound on a_nn over the whole table and evaluates the exact
-// shift only for the rare iterates that pass it.  These kernels produce the
-// bound's ingredients, max |sxx|, |sxy|, |syy| over the table's nodes, as
+// shift only for the iterates that pass it (the float32 kernels use exact
+// thresholds instead when sigma is constant).  These kernels produce the
+// bound's ingredients,
+// max |sxx|, |sxy|, |syy| over the table's nodes, as
 // float bit patterns (non-negative floats order like their bit patterns, so
 // an unsigned max is a float max).  A NaN anywhere yields a NaN-pattern
 // maximum, which the threshold code treats as "no bound" (every iterate is
