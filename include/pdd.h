@@ -145,7 +145,8 @@ enum { PDD_CAL_WIDTH = 8 };    /* per knot: sum(phi_EM - phi_GM), sum phi_GM, su
  * (y - y0)/(y1 - y0)), so one architecture serves any domain; grad v is
  * taken with respect to x and y (chain rule).
  * GRAD_LUT: grad_lut = float32 [lut_n][lut_n][2] node-centred over the domain
- * (device, 8-byte aligned, else PDD_EINVAL). */
+ * (device, 8-byte aligned, else PDD_EINVAL; float32 runs take lut_n <= 23170,
+ * else PDD_EUNSUPPORTED). */
 typedef struct pdd_cv {
   int32_t mode;              /* PDD_CV_* */
   int32_t lut_n;

@@ -181,7 +181,7 @@ __device__ __forceinline__ void lut_fetch_coop(const CoefParams& cp, float x, fl
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   wave_sync();
-  C->cell[lane] = (uint32_t)j * (uint32_t)(n - 1) + (uint32_t)i;
+  C->cell[lane] = __umul24((uint32_t)j, (uint32_t)(n - 1)) + (uint32_t)i;     // j, n - 1 < 2^24
   C->tx[lane] = fx - (float)i;
   C->ty[lane] = fy - (float)j;
   wave_sync();
@@ -228,7 +228,7 @@ __device__ __forceinline__ void lut_fetch_lane(const CoefParams& cp, uint32_t la
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
-  const uint32_t off = ((uint32_t)j * (uint32_t)(n - 1) + (uint32_t)i) * stride;
+  const uint32_t off = (__umul24((uint32_t)j, (uint32_t)(n - 1)) + (uint32_t)i) * stride;   // j, n - 1 < 2^24
   const char* cb = reinterpret_cast<const char*>(cp.cells);
   const float4 a = *reinterpret_cast<const float4*>(cb + off);
   float v2 = 0.0f;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void lut_fetch_cell(const CoefParams& cp, float x, fl
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
-  const char* cb = reinterpret_cast<const char*>(cp.cells) + ((uint32_t)j * (uint32_t)(n - 1) + (uint32_t)i) * 128u;
+  const char* cb = reinterpret_cast<const char*>(cp.cells) + (__umul24((uint32_t)j, (uint32_t)(n - 1)) + (uint32_t)i) * 128u;
   float v[7];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {

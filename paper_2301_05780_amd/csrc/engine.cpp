@@ -55,6 +55,8 @@ pdd_status validate_run(pdd_ctx* ctx, const pdd_coeffs& c, const pdd_run& r) {
       return bad(ctx, PDD_EINVAL, "run.cv: grad-table mode needs a table and 2 <= lut_n <= 65536");
     if (cv.mode == PDD_CV_GRAD_LUT && (reinterpret_cast<uintptr_t>(cv.grad_lut) & 7u) != 0)
       return bad(ctx, PDD_EINVAL, "run.cv: the gradient table must be 8-byte aligned");
+    if (cv.mode == PDD_CV_GRAD_LUT && r.precision == PDD_FP32_PRODUCTION && cv.lut_n > 23170)
+      return bad(ctx, PDD_EUNSUPPORTED, "run.cv: float32 runs read the gradient table with 32-bit offsets (lut_n <= 23170)");
     if (cv.mode != PDD_CV_NONE && (c.kind == PDD_COEF_CONSTSOL || c.kind == PDD_COEF_EXITTIME))
       return bad(ctx, PDD_EUNSUPPORTED, "run.cv: control variates are built for the poisson, varcoef, amplitude, LUT and eq43 families");
   }

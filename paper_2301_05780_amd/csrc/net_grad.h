@@ -297,9 +297,16 @@ __device__ __forceinline__ void grad_lut(const AsmParams& P, float x, float y, f
   float fy = fminf(fmaxf((y - P.coef.y0f) * P.cv_lut_sy, 0.0f), (float)(n - 1));
   const int i = min((int)fx, n - 2), j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
-  const float2* row0 = reinterpret_cast<const float2*>(P.cv_lut) + (size_t)j * n + i;
-  const float2* row1 = row0 + n;
-  const float2 a0 = row0[0], a1 = row0[1], b0 = row1[0], b1 = row1[1];
+  // 32-bit byte offsets from the table's base (the host keeps float32 runs'
+  // tables below 4 GiB, lut_n <= 23170), so the loads take the base from
+  // scalar registers
+  // (nodes i and i + 1 of a row are 16 contiguous bytes, 8-byte aligned)
+  struct __attribute__((aligned(8))) Pair { float2 lo, hi; };
+  const char* base = reinterpret_cast<const char*>(P.cv_lut);
+  const uint32_t o0 = (__umul24((uint32_t)j, (uint32_t)n) + (uint32_t)i) * 8u;
+  const Pair r0 = *reinterpret_cast<const Pair*>(base + o0);
+  const Pair r1 = *reinterpret_cast<const Pair*>(base + (o0 + (uint32_t)n * 8u));
+  const float2 a0 = r0.lo, a1 = r0.hi, b0 = r1.lo, b1 = r1.hi;
   const float lx = a0.x + tx * (a1.x - a0.x), hx = b0.x + tx * (b1.x - b0.x);
   const float ly = a0.y + tx * (a1.y - a0.y), hy = b0.y + tx * (b1.y - b0.y);
   gx = lx + ty * (hx - lx);
