@@ -462,17 +462,18 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   // ---- exit test at the new iterate --------------------------------------------
   // The negation of "strictly inside the thresholds", so a NaN iterate exits
   // (and is tallied as NaN) instead of running to the step cap.  For the LUT
-  // family under GM the thresholds are candidate ones: a candidate hit is
-  // decided exactly at the projection, and the flagged sides travel with the
-  // exit record.
+  // family under GM the thresholds are candidate ones (unless sigma is
+  // constant: then they are exact, and the exit processing flags the sides
+  // from them as for the closed-form families): a candidate hit is decided
+  // exactly at the projection, and the flagged sides travel with the exit
+  // record.
   auto exit_test = [&](uint32_t& fl) __attribute__((always_inline)) -> bool {
     const bool inside = (x <= ehx) & (y <= ehy) & (x >= elx) & (y >= ely);
     if constexpr (KIND == PDD_COEF_LUT) {
-      if (!inside && P.exit_rule == PDD_EXIT_GM) {
+      if (!inside && P.exit_rule == PDD_EXIT_GM && !(lut_lay & SIG_EXACT)) {
         const uint32_t cand = (uint32_t)(x > ehx) | ((uint32_t)(y > ehy) << 1) | ((uint32_t)(x < elx) << 2) |
                               ((uint32_t)(y < ely) << 3);
         if (cand == 0) { fl = 0; return true; }
-        if (lut_lay & SIG_EXACT) { fl = cand; return true; }   // the thresholds are exact
         fl = lut_gm_refine<R>(P.coef, lsq, B[buf].d.line, x, y, cand);
         return fl != 0;
       }
@@ -501,7 +502,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         const KnotDesc& d = W.d;
         const GeoView<R> G = geo(W);
         bool fE, fN, fW, fS;
-        if (KIND == PDD_COEF_LUT && P.exit_rule == PDD_EXIT_GM) {
+        if (KIND == PDD_COEF_LUT && P.exit_rule == PDD_EXIT_GM && !(lut_lay & SIG_EXACT)) {
           fE = (meta >> 26) & 1u; fN = (meta >> 27) & 1u; fW = (meta >> 28) & 1u; fS = (meta >> 29) & 1u;
         } else {
           fE = r.x > (R)W.ebox[0]; fN = r.y > (R)W.ebox[1];
