@@ -126,6 +126,16 @@ __device__ __forceinline__ double dpp_add_f64(double v) {
   return v + __hiloint2double(hi, lo);
 }
 
+// Sum of v over each row of 16 lanes, left in the row's last lane (lanes 15,
+// 31, 47, 63): shifts by 1, 2, 4 and 8 within the row.  A fixed order.
+__device__ __forceinline__ double row_total_dpp(double v) {
+  v = dpp_add_f64<0x111, 0xf>(v);    // row_shr:1
+  v = dpp_add_f64<0x112, 0xf>(v);    // row_shr:2
+  v = dpp_add_f64<0x114, 0xf>(v);    // row_shr:4
+  v = dpp_add_f64<0x118, 0xf>(v);    // row_shr:8
+  return v;
+}
+
 // Sum of v over the 64 lanes, returned to every lane: shifts by 1, 2, 4
 // and 8 within each row of 16 lanes leave the row's sum in its lane 15; the
 // row broadcasts of lanes 15 and 31 then carry the four row sums into lane
@@ -329,6 +339,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   constexpr bool COOP = KIND == PDD_COEF_LUT && !F64 && CV != PDD_CV_NETWORK && !LANE;
   constexpr bool WAVEWIDE = !F64 && (CV == PDD_CV_NETWORK || COOP || LANE);
   constexpr int TB = COOP ? TB_COOP : (LANE ? TB_LANE : TB_NONE);
+  // row extras summed per 16-lane row before the LDS atomics (see process_queue)
+  constexpr bool ROWRED = KIND == PDD_COEF_LUT || BATCH;
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -662,15 +674,43 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           vs = vb;
         }
       }
-      // row extras: b, sum s, sum s^2 and sum K through LDS atomics (the LDS
-      // pipe serialises the same-address lanes; no VALU reduction needed),
-      // exit-side counts through ballots
-      if (valid) {
-        double* ex = wrows + (size_t)row_of(rb, B[rb]) * RL + 4 * SL;
-        lds_add(ex + EX_B, vb);
-        lds_add(ex + EX_S, vs);
-        lds_add(ex + EX_S2, vs * vs);
-        lds_add(ex + EX_K, vk);
+      // row extras b, sum s, sum s^2 and sum K: every exit of a buffer adds
+      // to the same four words, and the LDS pipe serialises same-address
+      // atomics (up to 64 per word per batch, a cost shared by the CU's
+      // waves).  Where paths are short (many exits per step: the table
+      // family, batched launches) each 16-lane row of the wave first sums
+      // its exits (DPP) and the row's last lane adds the row sum; the
+      // register-capped closed-form kernels keep one atomic per exit.
+      // Without u_ref, s = b and sum s is copied from b at the flush.
+      // Exit-side counts through ballots.
+      if constexpr (!ROWRED) {
+        if (valid) {
+          double* ex = wrows + (size_t)row_of(rb, B[rb]) * RL + 4 * SL;
+          lds_add(ex + EX_B, vb);
+          if (P.u_ref) lds_add(ex + EX_S, vs);
+          lds_add(ex + EX_S2, vs * vs);
+          lds_add(ex + EX_K, vk);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const bool mine = valid && rb == b;
+        const uint64_t mm = ROWRED ? __ballot(mine) : 0ull;
+        if (mm != 0) {
+          double tb = mine ? vb : 0.0, ts = mine ? vs : 0.0, tk = mine ? vk : 0.0;
+          double t2 = ts * ts;
+          tb = row_total_dpp(tb);
+          t2 = row_total_dpp(t2);
+          tk = row_total_dpp(tk);
+          if (P.u_ref) ts = row_total_dpp(ts);
+          if ((lane & 15) == 15 && ((mm >> (lane & 48)) & 0xFFFFull) != 0) {
+            double* ex = wrows + (size_t)row_of(b, B[b]) * RL + 4 * SL;
+            lds_add(ex + EX_B, tb);
+            if (P.u_ref) lds_add(ex + EX_S, ts);
+            lds_add(ex + EX_S2, t2);
+            lds_add(ex + EX_K, tk);
+          }
+        }
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
@@ -755,7 +795,10 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     if (qn > 0) process_queue();
     const int t = b ? tk1 : tk0;
     const int prow = row_of(b, B[b]);
-    const double* row = wrows + (size_t)prow * RL;
+    double* row = wrows + (size_t)prow * RL;
+    // without u_ref every score equals its b contribution: sum s = sum b
+    if (!P.u_ref && lane == 0) row[4 * SL + EX_S] = row[4 * SL + EX_B];
+    wave_sync();
     double* dst = P.partial + (size_t)t * RL;
     for (int i = lane; i < RL; i += 64) dst[i] = row[i];
     wave_sync();
