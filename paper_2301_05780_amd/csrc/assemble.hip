@@ -41,12 +41,15 @@ constexpr uint32_t MAX_STEPS = (1u << 24) - 2;
 
 // Per-buffer header: the ticket's knot, the instance parameters (batched
 // launches only), the strict exit thresholds x > e[0], y > e[1], x < e[2],
-// y < e[3] in the path precision, the pool row holding the buffer's tallies
-// and the instance word.
+// y < e[3] in the path precision, the values a refilled lane starts from
+// (start point, step, its square root, family parameter; path precision),
+// the pool row holding the buffer's tallies and the instance word.  Refill
+// reads the header from LDS rather than keeping copies in scalar registers.
 template <typename R, bool BATCH>
 struct WaveBuf {
   KnotDesc d;
   R ebox[4];
+  R start[8];          // sx, sy, h, sqrt h, a
   int32_t row, pad0, pad1;
   uint32_t inst;
 };
@@ -55,6 +58,7 @@ struct WaveBuf<R, true> {
   KnotDesc d;
   InstDesc I;
   R ebox[4];
+  R start[8];
   int32_t row, pad0, pad1;
   uint32_t inst;
 };
@@ -160,16 +164,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ float uniform_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ double uniform_f64(double v) {
-  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
-  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float to_uniform(float v) { return uniform_f32(v); }
-__device__ __forceinline__ double to_uniform(double v) { return uniform_f64(v); }
 __device__ __forceinline__ uint32_t to_uniform_u(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
@@ -186,8 +180,8 @@ __device__ __forceinline__ void lut_fetch_coop(const CoefParams& cp, float x, fl
   const int n = cp.lut_n;
   float fx = (x - cp.x0f) * cp.lut_sx;
   float fy = (y - cp.y0f) * cp.lut_sy;
-  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));     // NaN maps to 0: every address stays in the table
-  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  fx = clamp_node(fx, (float)(n - 1));
+  fy = clamp_node(fy, (float)(n - 1));
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   wave_sync();
@@ -233,8 +227,8 @@ __device__ __forceinline__ void lut_fetch_lane(const CoefParams& cp, uint32_t la
   const int n = cp.lut_n;
   float fx = (x - cp.x0f) * cp.lut_sx;
   float fy = (y - cp.y0f) * cp.lut_sy;
-  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
-  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  fx = clamp_node(fx, (float)(n - 1));
+  fy = clamp_node(fy, (float)(n - 1));
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
@@ -249,8 +243,16 @@ __device__ __forceinline__ void lut_fetch_lane(const CoefParams& cp, uint32_t la
   const float v1 = __builtin_fmaf(ty, __builtin_fmaf(tx, a.w, a.z), __builtin_fmaf(tx, a.y, a.x));
   // the constant fields' values, kept in the wave's LDS; the second stored
   // field's selects only when there is one (a uniform branch)
-  const float4 c0 = reinterpret_cast<const float4*>(kc_lds)[0];
-  const float4 c1 = reinterpret_cast<const float4*>(kc_lds)[1];
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const v4f c0 = reinterpret_cast<const v4f*>(kc_lds)[0];
+  const v4f c1 = reinterpret_cast<const v4f*>(kc_lds)[1];
+  __asm__("" ::"v"(c0), "v"(c1));      // two whole 16-byte LDS reads at immediate offsets
+  if (k1 == 6 && k2 >= 7) {
+    // only the source term varies (a uniform branch without the selects)
+    o.sxx = c0.x; o.sxy = c0.y; o.syy = c0.z; o.dx = c0.w;
+    o.dy = c1.x; o.c = c1.y; o.f = v1;
+    return;
+  }
   float f[7] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z};
 #pragma unroll
   for (int q = 0; q < 7; ++q) f[q] = q == k1 ? v1 : f[q];
@@ -269,8 +271,8 @@ __device__ __forceinline__ void lut_fetch_cell(const CoefParams& cp, float x, fl
   const int n = cp.lut_n;
   float fx = (x - cp.x0f) * cp.lut_sx;
   float fy = (y - cp.y0f) * cp.lut_sy;
-  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
-  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  fx = clamp_node(fx, (float)(n - 1));
+  fy = clamp_node(fy, (float)(n - 1));
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
@@ -306,14 +308,6 @@ __device__ __forceinline__ R lut_const_threshold(const uint32_t* info, double sq
   }
   return (o < 2) ? nextafter(thr, (R)-INFINITY) : nextafter(thr, (R)INFINITY);
 }
-
-// Per-buffer uniform values used at refill (kept in scalar registers).
-template <typename R>
-struct BufU {
-  R sx, sy, e0, e1, e2, e3;
-  R h, sq, a;          // instance step and family parameter (batched launches)
-  uint32_t knot, inst;
-};
 
 // Geometry used when resolving exits (the launch's, or a batched instance's).
 template <typename R>
@@ -430,7 +424,6 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   int nx0 = 0, en0 = 0, nx1 = 0, en1 = 0;
   int cur = 0;
   int qn = 0;                    // queued exit records
-  BufU<R> u0{}, u1{};
 
   // lane state
   bool active = false;
@@ -769,26 +762,21 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       W.ebox[lane] = (lut_lay & SIG_EXACT) ? lut_const_threshold<R>(P.coef.lut_info, sqh, W.d, lane)
                                            : exit_threshold<KIND, R>(cp, P.exit_rule, sqh, W.d, lane);
     }
-    wave_sync();
-    BufU<R> u;
-    u.sx = to_uniform((R)W.d.sx);
-    u.sy = to_uniform((R)W.d.sy);
-    u.e0 = to_uniform((R)W.ebox[0]);
-    u.e1 = to_uniform((R)W.ebox[1]);
-    u.e2 = to_uniform((R)W.ebox[2]);
-    u.e3 = to_uniform((R)W.ebox[3]);
-    u.knot = to_uniform_u((uint32_t)W.d.knot);
-    u.inst = to_uniform_u(W.inst);
-    if constexpr (BATCH) {
-      u.h = to_uniform((R)W.I.h);
-      u.sq = to_uniform((R)W.I.sqrt_h);
-      u.a = to_uniform((R)W.I.a);
-    } else if constexpr (HK) {
-      u.h = to_uniform((R)hk);
-      u.sq = to_uniform((R)sqk);
+    if (lane == 0) {
+      W.start[0] = (R)W.d.sx;
+      W.start[1] = (R)W.d.sy;
+      if constexpr (BATCH) {
+        W.start[2] = (R)W.I.h;
+        W.start[3] = (R)W.I.sqrt_h;
+        W.start[4] = (R)W.I.a;
+      } else {
+        W.start[2] = (R)hk;
+        W.start[3] = (R)sqk;
+      }
     }
-    if (b) { tk1 = (int)t; nx1 = T.p0; en1 = T.p1; u1 = u; }
-    else { tk0 = (int)t; nx0 = T.p0; en0 = T.p1; u0 = u; }
+    wave_sync();
+    if (b) { tk1 = (int)t; nx1 = T.p0; en1 = T.p1; }
+    else { tk0 = (int)t; nx0 = T.p0; en0 = T.p1; }
   };
 
   auto flush = [&](int b) __attribute__((always_inline)) {
@@ -840,22 +828,23 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       const int take = min((int)__popcll(idle), en - nx);   // int min (mixed types pick the double overload)
       const int rank = lane_rank(idle);
       if (!active && rank < take) {
+        const WB& U = B[cur];
         p = (uint32_t)(nx + rank);
-        kn = cur ? u1.knot : u0.knot;
-        inst = cur ? u1.inst : u0.inst;
+        kn = (uint32_t)U.d.knot;
+        inst = U.inst;
         j = 0;
-        x = cur ? u1.sx : u0.sx;
-        y = cur ? u1.sy : u0.sy;
+        x = U.start[0];
+        y = U.start[1];
         Y = (R)1; Z = (R)0; Xi = (R)0;
-        ehx = cur ? u1.e0 : u0.e0;
-        ehy = cur ? u1.e1 : u0.e1;
-        elx = cur ? u1.e2 : u0.e2;
-        ely = cur ? u1.e3 : u0.e3;
+        ehx = U.ebox[0];
+        ehy = U.ebox[1];
+        elx = U.ebox[2];
+        ely = U.ebox[3];
         if constexpr (BATCH || HK) {
-          lh = cur ? u1.h : u0.h;
-          lsq = cur ? u1.sq : u0.sq;
+          lh = U.start[2];
+          lsq = U.start[3];
         }
-        if constexpr (BATCH) la = cur ? u1.a : u0.a;
+        if constexpr (BATCH) la = U.start[4];
         active = true;
         buf = cur;
       }

@@ -114,6 +114,13 @@ template <int KIND> struct Traits {
   static constexpr bool offdiag = (KIND == PDD_COEF_LUT);
 };
 
+// Float32 node coordinate clamped to [0, hi] in one instruction (the median
+// of v, 0 and hi; fmaxf/fminf take three with the IEEE-mode quieting of hi).
+// For a finite or infinite v it is the two-sided clamp; a NaN yields 0 or
+// NaN, and the index conversion turns either into node 0, so every address
+// stays in the table.
+__device__ __forceinline__ float clamp_node(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
+
 // Bilinear read of the node-centred LUT (seven fields).  Position -> node
 // coordinate clamped to [0, n-1], cell index clamped to n-2.
 __device__ __forceinline__ void lut_fetch(const CoefParams& cp, double x, double y, Coef<double>& o) {
@@ -142,8 +149,8 @@ __device__ __forceinline__ void lut_fetch(const CoefParams& cp, float x, float y
   const int n = cp.lut_n;
   float fx = (x - cp.x0f) * cp.lut_sx;
   float fy = (y - cp.y0f) * cp.lut_sy;
-  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
-  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  fx = clamp_node(fx, (float)(n - 1));
+  fy = clamp_node(fy, (float)(n - 1));
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
@@ -475,8 +482,8 @@ __device__ __forceinline__ void lut_sigma(const CoefParams& cp, float x, float y
   const int n = cp.lut_n;
   float fx = (x - cp.x0f) * cp.lut_sx;
   float fy = (y - cp.y0f) * cp.lut_sy;
-  fx = fminf(fmaxf(fx, 0.0f), (float)(n - 1));
-  fy = fminf(fmaxf(fy, 0.0f), (float)(n - 1));
+  fx = clamp_node(fx, (float)(n - 1));
+  fy = clamp_node(fy, (float)(n - 1));
   const int i = min((int)fx, n - 2);
   const int j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;

@@ -293,8 +293,8 @@ __device__ __forceinline__ void grad_lut(const AsmParams& P, double x, double y,
 
 __device__ __forceinline__ void grad_lut(const AsmParams& P, float x, float y, float& gx, float& gy) {
   const int n = P.cv_lut_n;
-  float fx = fminf(fmaxf((x - P.coef.x0f) * P.cv_lut_sx, 0.0f), (float)(n - 1));
-  float fy = fminf(fmaxf((y - P.coef.y0f) * P.cv_lut_sy, 0.0f), (float)(n - 1));
+  const float fx = clamp_node((x - P.coef.x0f) * P.cv_lut_sx, (float)(n - 1));
+  const float fy = clamp_node((y - P.coef.y0f) * P.cv_lut_sy, (float)(n - 1));
   const int i = min((int)fx, n - 2), j = min((int)fy, n - 2);
   const float tx = fx - (float)i, ty = fy - (float)j;
   // 32-bit byte offsets from the table's base (the host keeps float32 runs'

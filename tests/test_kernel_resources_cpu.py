@@ -48,12 +48,7 @@ LISTED = {
     "_ZN3pdd12_GLOBAL__N_111k_calibrateILi6ELb0ELb1EEEvNS0_7CalArgsE": (136, 0),
     "_ZN3pdd12_GLOBAL__N_111k_calibrateILi6ELb1ELb0EEEvNS0_7CalArgsE": (136, 0),
     "_ZN3pdd12_GLOBAL__N_111k_calibrateILi6ELb1ELb1EEEvNS0_7CalArgsE": (136, 0),
-    "_ZN3pdd12_GLOBAL__N_113k_assemble_w4ILi3ELi2EEEvNS_9AsmParamsE": (20, 4),
-    "_ZN3pdd12_GLOBAL__N_113k_assemble_w6ILi0EEEvNS_9AsmParamsE": (36, 8),
-    "_ZN3pdd12_GLOBAL__N_113k_assemble_w6ILi1EEEvNS_9AsmParamsE": (36, 8),
-    "_ZN3pdd12_GLOBAL__N_113k_assemble_w6ILi2EEEvNS_9AsmParamsE": (40, 9),
-    "_ZN3pdd12_GLOBAL__N_113k_assemble_w6ILi5EEEvNS_9AsmParamsE": (12, 2),
-    "_ZN3pdd12_GLOBAL__N_113k_assemble_w6ILi6EEEvNS_9AsmParamsE": (144, 55),
+    "_ZN3pdd12_GLOBAL__N_113k_assemble_w6ILi6EEEvNS_9AsmParamsE": (88, 25),
     "_ZN3pdd12_GLOBAL__N_16k_evalILi0ELb0EEEvNS0_8EvalArgsE": (136, 0),
     "_ZN3pdd12_GLOBAL__N_16k_evalILi0ELb1EEEvNS0_8EvalArgsE": (136, 0),
     "_ZN3pdd12_GLOBAL__N_16k_evalILi1ELb0EEEvNS0_8EvalArgsE": (136, 0),
