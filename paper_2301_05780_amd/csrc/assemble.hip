@@ -333,8 +333,11 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   constexpr bool COOP = KIND == PDD_COEF_LUT && !F64 && CV != PDD_CV_NETWORK && !LANE;
   constexpr bool WAVEWIDE = !F64 && (CV == PDD_CV_NETWORK || COOP || LANE);
   constexpr int TB = COOP ? TB_COOP : (LANE ? TB_LANE : TB_NONE);
-  // row extras summed per 16-lane row before the LDS atomics (see process_queue)
-  constexpr bool ROWRED = KIND == PDD_COEF_LUT || BATCH;
+  // row extras (sum b, sum s^2, sum K): per-lane float64 sums flushed once
+  // per ticket (LACC), or summed per 16-lane row before the LDS atomics
+  // (ROWRED), or one atomic per exit (see process_queue)
+  constexpr bool LACC = LANE || BATCH;
+  constexpr bool ROWRED = !LACC && KIND == PDD_COEF_LUT;
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -377,6 +380,10 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   auto row_of = [&](int b, const WaveBuf<R, BATCH>& W) __attribute__((always_inline)) -> int {
     if constexpr (POOL) return W.row;
     else return b;
+  };
+  // offset of that row in the LDS rows (pool rows < 64 and RL < 2^16: 24-bit multiply)
+  auto row_off = [&](int b, const WaveBuf<R, BATCH>& W) __attribute__((always_inline)) -> uint32_t {
+    return __umul24((uint32_t)row_of(b, W), (uint32_t)RL);
   };
   // a free row of the pool (wave-uniform), or -1 when every row is taken
   auto pool_take = [&]() __attribute__((always_inline)) -> int {
@@ -424,6 +431,8 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   int nx0 = 0, en0 = 0, nx1 = 0, en1 = 0;
   int cur = 0;
   int qn = 0;                    // queued exit records
+  // LACC: this lane's sums of b, s^2 and K over the exits it processed, per buffer
+  double ab0 = 0.0, aq0 = 0.0, ak0 = 0.0, ab1 = 0.0, aq1 = 0.0, ak1 = 0.0;
 
   // lane state
   bool active = false;
@@ -546,7 +555,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           R w;
           hat_weights<R, F64>(along, vert ? G.y0 : G.x0, vert ? G.dy : G.dx, vert ? G.inv_dy : G.inv_dx,
                               clo, chi, q0, w);
-          double* row = wrows + (size_t)row_of(rb, W) * RL + o * SL;
+          double* row = wrows + row_off(rb, W) + __umul24((uint32_t)o, (uint32_t)SL);
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int q = q0 + e;
@@ -605,7 +614,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           const double da = vert ? Gg.dy : Gg.dx;
           const bool b0 = clo == 0, bL = chi == Gg.L;
           const double* Mi = P.rbf_inv + (vert ? P.rbf_half : 0) + rbf_block_offset(S);
-          double* row = wrows + (size_t)row_of(gb, W) * RL + go * SL;
+          double* row = wrows + row_off(gb, W) + __umul24((uint32_t)go, (uint32_t)SL);
           // g at the stencil's boundary points (q = 0, q = L)
           const R lpos = (R)d.line[go];
           auto g_end = [&](int q) __attribute__((always_inline)) -> double {
@@ -671,14 +680,26 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       // to the same four words, and the LDS pipe serialises same-address
       // atomics (up to 64 per word per batch, a cost shared by the CU's
       // waves).  Where paths are short (many exits per step: the table
-      // family, batched launches) each 16-lane row of the wave first sums
-      // its exits (DPP) and the row's last lane adds the row sum; the
-      // register-capped closed-form kernels keep one atomic per exit.
-      // Without u_ref, s = b and sum s is copied from b at the flush.
+      // family, batched launches) the lane-per-path table kernel and
+      // batched launches keep per-lane float64 sums in registers, summed
+      // over the wave when the ticket is flushed; the cooperative table
+      // kernels first sum each 16-lane row of the wave (DPP) and the row's
+      // last lane adds the row sum; the register-capped closed-form kernels
+      // keep one atomic per exit.  Without u_ref, s = b and sum s is copied
+      // from b at the flush (with u_ref, LACC adds s per exit).
       // Exit-side counts through ballots.
-      if constexpr (!ROWRED) {
+      if constexpr (LACC) {
         if (valid) {
-          double* ex = wrows + (size_t)row_of(rb, B[rb]) * RL + 4 * SL;
+          if (P.u_ref) lds_add(wrows + row_off(rb, B[rb]) + 4 * SL + EX_S, vs);
+          // both buffers' sums take an addend (0 for the other buffer): a
+          // branch here lets the compiler index the sums through memory
+          const double q = vs * vs;
+          ab0 += rb ? 0.0 : vb; aq0 += rb ? 0.0 : q; ak0 += rb ? 0.0 : vk;
+          ab1 += rb ? vb : 0.0; aq1 += rb ? q : 0.0; ak1 += rb ? vk : 0.0;
+        }
+      } else if constexpr (!ROWRED) {
+        if (valid) {
+          double* ex = wrows + row_off(rb, B[rb]) + 4 * SL;
           lds_add(ex + EX_B, vb);
           if (P.u_ref) lds_add(ex + EX_S, vs);
           lds_add(ex + EX_S2, vs * vs);
@@ -697,7 +718,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           tk = row_total_dpp(tk);
           if (P.u_ref) ts = row_total_dpp(ts);
           if ((lane & 15) == 15 && ((mm >> (lane & 48)) & 0xFFFFull) != 0) {
-            double* ex = wrows + (size_t)row_of(b, B[b]) * RL + 4 * SL;
+            double* ex = wrows + row_off(b, B[b]) + 4 * SL;
             lds_add(ex + EX_B, tb);
             if (P.u_ref) lds_add(ex + EX_S, ts);
             lds_add(ex + EX_S2, t2);
@@ -713,7 +734,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
         const int cW = __popcll(__ballot(mine && o == 2));
         const int cS = __popcll(__ballot(mine && o == 3));
         if (lane == 0 && (cE | cN | cW | cS) != 0) {
-          double* ex = wrows + (size_t)row_of(b, B[b]) * RL + 4 * SL;
+          double* ex = wrows + row_off(b, B[b]) + 4 * SL;
           ex[EX_E] += (double)cE;
           ex[EX_N] += (double)cN;
           ex[EX_W] += (double)cW;
@@ -784,6 +805,17 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
     const int t = b ? tk1 : tk0;
     const int prow = row_of(b, B[b]);
     double* row = wrows + (size_t)prow * RL;
+    if constexpr (LACC) {
+      // the lanes' sums of this buffer, summed over the wave (a fixed order)
+      const double tb = wave_sum(b ? ab1 : ab0), tq = wave_sum(b ? aq1 : aq0), tk = wave_sum(b ? ak1 : ak0);
+      if (lane == 0) {
+        row[4 * SL + EX_B] += tb;
+        row[4 * SL + EX_S2] += tq;
+        row[4 * SL + EX_K] += tk;
+      }
+      if (b) { ab1 = 0.0; aq1 = 0.0; ak1 = 0.0; }
+      else { ab0 = 0.0; aq0 = 0.0; ak0 = 0.0; }
+    }
     // without u_ref every score equals its b contribution: sum s = sum b
     if (!P.u_ref && lane == 0) row[4 * SL + EX_S] = row[4 * SL + EX_B];
     wave_sync();

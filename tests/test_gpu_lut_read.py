@@ -4,9 +4,12 @@ the full cooperative read of all seven.
 A field that holds one value at every node has the bilinear form
 (v, 0, 0, 0) on every cell, which evaluates to v, so reading only the
 varying fields changes no bit of any path: the two reads must give the same
-G, b and per-knot sums exactly (static schedule, fixed launch shape).  The
-scan that decides between them is checked on tables with zero, one, two and
-seven varying fields, a constant -0 (the full read turns it into +0) and a
+paths (the dumped exit records), the same G and the same integer per-knot
+sums exactly (static schedule, fixed launch shape).  The two kernels add
+b, sum s and sum s^2 in different orders (per-lane sums flushed per ticket
+against per-row sums), so those agree to float64 rounding.  The scan that
+decides between them is checked on tables with zero, one, two and seven
+varying fields, a constant -0 (the full read turns it into +0) and a
 misaligned table pointer.
 """
 import numpy as np
@@ -28,6 +31,22 @@ def ctx():
     yield c
     c.set_table_read(False)
     c.close()
+
+
+DUMP = 16
+
+
+def _assert_same(a, b, what):
+    """G, the dumped paths and the integer per-knot sums (sum K, N, the exit
+    counts) bit for bit; b and the score sums to float64 rounding."""
+    for k in ("val", "dump"):
+        if k in a and k in b:
+            x, y = a[k], b[k]
+            assert torch.equal(torch.nan_to_num(x, nan=-7.0), torch.nan_to_num(y, nan=-7.0)), (what, k)
+    da, db = a["diag"].view(-1, pdd.DIAG_WIDTH), b["diag"].view(-1, pdd.DIAG_WIDTH)
+    assert torch.equal(da[:, :6], db[:, :6]), (what, "diag counts")
+    for x, y, k in ((a["b"], b["b"], "b"), (da[:, 6:], db[:, 6:], "diag sums")):
+        assert torch.allclose(x, y, rtol=1e-12, atol=1e-14), (what, k, float((x - y).abs().max()))
 
 
 def _work(rule):
@@ -62,16 +81,15 @@ def test_lane_read_equals_full_read(ctx, name, rule):
     outs = []
     for read_all in (False, True):
         ctx.set_table_read(read_all)
-        out = ctx.assemble(w, lut=lut)
+        out = ctx.assemble(w, lut=lut, dump_paths=DUMP)
         ctx.sync()
         got_mask, got_lane = ctx.table_fields()
         assert got_mask == mask, (name, hex(got_mask))
         assert got_lane == (lane and not read_all), name
-        outs.append({k: out[k][:out["nnz"]].clone() if k == "val" else out[k].clone() for k in ("val", "b", "diag")})
+        outs.append({k: out[k][:out["nnz"]].clone() if k == "val" else out[k].clone()
+                     for k in ("val", "b", "diag", "dump")})
     ctx.set_table_read(False)
-    for k in ("val", "b", "diag"):
-        a, b = outs[0][k], outs[1][k]
-        assert torch.equal(a, b), (name, k, float((a - b).abs().max()))
+    _assert_same(outs[0], outs[1], name)
     assert float(outs[0]["diag"].view(-1, pdd.DIAG_WIDTH)[:, 0].sum()) > 0
 
 
@@ -90,8 +108,10 @@ def test_stale_lane_choice_in_a_graph_reads_the_full_layout():
     it launches the kernel the last eager call chose.  Captured after a
     one-field table, an assembly of a seven-field table launches the
     lane-per-path kernel on the full copy; that kernel reads the layout word
-    itself and takes its full per-lane read, so every replay equals the
-    eager assembly (same launch shape, static schedule) bit for bit."""
+    itself and takes its full per-lane read, so every replay gives the eager
+    (cooperative-read) assembly's G and integer sums bit for bit and its b
+    to float64 rounding (same launch shape, static schedule), and the
+    replays equal each other bit for bit."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     stream = torch.cuda.Stream()
@@ -112,14 +132,19 @@ def test_stale_lane_choice_in_a_graph_reads_the_full_layout():
             g.graph_begin()
             g.assemble(w, out=out, lut=full)
             g.graph_end()
+            first = None
             for rep in range(2):
                 for k in ("val", "b", "diag"):
                     out[k].fill_(float("nan"))
                 g.graph_launch()
                 g.sync()
                 assert g.table_fields() == (0x7F, False)
+                got = {k: out[k].clone() for k in ("val", "b", "diag")}
+                _assert_same(got, ref, ("replay", rep))
+                if first is None:
+                    first = got
                 for k in ("val", "b", "diag"):
-                    assert torch.equal(out[k], ref[k]), (rep, k)
+                    assert torch.equal(got[k], first[k]), (rep, k)
                 g.assemble(w, out=other, lut=one)          # eager work between the replays
                 g.sync()
         finally:
@@ -156,20 +181,19 @@ def test_constant_sigma_thresholds_equal_the_exact_test():
 def test_tiny_tables(ctx, n):
     """Tables of one, four and 25 cells (every path in the first or last
     cell of a row or column, the edge clamps taken on both sides): the lane
-    read equals the full read bit for bit."""
+    read gives the full read's paths, G and counts bit for bit."""
     w = dict(_work("gm"), lut_n=n)
     tab = workloads.poisson_lut(n)
     lut = torch.from_numpy(tab).cuda()
     outs = []
     for read_all in (False, True):
         ctx.set_table_read(read_all)
-        out = ctx.assemble(w, lut=lut)
+        out = ctx.assemble(w, lut=lut, dump_paths=DUMP)
         ctx.sync()
         assert ctx.table_fields() == (1 << 6, not read_all)
-        outs.append({k: out[k].clone() for k in ("val", "b", "diag")})
+        outs.append({k: out[k].clone() for k in ("val", "b", "diag", "dump")})
     ctx.set_table_read(False)
-    for k in ("val", "b", "diag"):
-        assert torch.equal(outs[0][k], outs[1][k]), (n, k)
+    _assert_same(outs[0], outs[1], n)
 
 
 def test_table_read_switch_rejects_other_values(ctx):
