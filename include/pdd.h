@@ -287,8 +287,11 @@ pdd_status pdd_assemble_batch(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* 
  * and pdd_graph_end into a HIP graph, then replay it with pdd_graph_launch.
  * Only cached work can be captured: run the same pdd_assemble /
  * pdd_assemble_batch call once before capturing (a call that needs new
- * tables during capture fails with PDD_EINVAL).  Captured work must not call
- * pdd_solve.  *n_nodes receives the node count of the graph (nullable). */
+ * tables during capture fails with PDD_EINVAL).  The graph uses the
+ * context's scratch as sized then: a later call that needs more (a larger
+ * table, more tickets) reallocates it, after which the graph must be
+ * captured again.  Captured work must not call pdd_solve.  *n_nodes receives
+ * the node count of the graph (nullable). */
 pdd_status pdd_graph_begin(pdd_ctx* ctx);
 pdd_status pdd_graph_end(pdd_ctx* ctx, int32_t* n_nodes);
 pdd_status pdd_graph_launch(pdd_ctx* ctx);
