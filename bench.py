@@ -588,7 +588,7 @@ def tuned_single(ctx, w, lut=None, tune=True, cv=None):
     if tune:
         arr, _ = ctx.batch_arrays([w], outs=[out], lut=lut, cv=cv)
         ms, report = ctx.autotune(arr, reps=2)
-        tuned = {"best_kernel_ms": ms, "shape": ctx.last_launch()}
+        tuned = {"best_assemble_finalize_ms": ms, "shape": ctx.last_launch()}
     return out, tuned
 
 
@@ -664,7 +664,7 @@ def time_batched(steps, warmup):
     return dict(elapsed=elapsed, kavg_s=kern_ms / max(launches, 1) / 1e3, path_steps=ps, paths=paths,
                 n=sum(int(o["n"]) for o in outs), nnz=sum(int(o["nnz"]) for o in outs),
                 launch={"grid": grid, "block": block, "tickets": tickets, "refill": refill, "spare_rows": spare,
-                        "graph_nodes": nodes, "autotuned_kernel_ms": tuned_ms})
+                        "graph_nodes": nodes, "autotuned_assemble_finalize_ms": tuned_ms})
 
 
 def train_table_cv(ctx, w, lut, table_n=513, warm_paths=1000):

@@ -304,8 +304,10 @@ pdd_status pdd_graph_launch(pdd_ctx* ctx);
  * schedule -- then, on the fastest, refill thresholds (pdd_set_refill) and
  * spare tally rows with larger tickets (pdd_set_spare_rows), with `reps`
  * timed repetitions each, and keep the fastest as the context's launch shape
- * (pdd_set_launch, pdd_set_refill, pdd_set_spare_rows).  *best_ms receives its mean
- * kernel time; `report` (nullable, report_len bytes) a text table of every
+ * (pdd_set_launch, pdd_set_refill, pdd_set_spare_rows).  A shape's time is
+ * the device time of the assembly kernel and of the row sums after it (which
+ * grow with the ticket count); *best_ms receives the chosen shape's mean
+ * time; `report` (nullable, report_len bytes) a text table of every
  * shape tried.  Results are cached per workload signature in the context.
  * The call ends with one assembly in the chosen shape (also on a cache hit),
  * so pdd_last_launch reports it and its tables are ready for graph capture. */

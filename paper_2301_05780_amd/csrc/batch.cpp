@@ -287,7 +287,7 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
   }
   e = launch_assemble(P, precision, (int)grid, blk, lds, ctx->stream);
   if (e != hipSuccess) return check_hip(ctx, e, "launch batched assemble");
-  if (t1) {
+  if (t1 && !ctx->timing_with_finalize) {
     if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
     ctx->ev_used += 1;
   }
@@ -311,6 +311,10 @@ pdd_status run_assemble_batch(pdd_ctx* ctx, int32_t n, const pdd_instance* in) {
     F.ticket_counter = (i == 0) ? P.ticket_counter : nullptr;
     e = launch_finalize(F, ctx->stream);
     if (e != hipSuccess) return check_hip(ctx, e, "launch finalize");
+  }
+  if (t1 && ctx->timing_with_finalize) {
+    if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
+    ctx->ev_used += 1;
   }
   ctx->last_grid = (int)grid;
   ctx->last_block = blk;
@@ -417,12 +421,15 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   std::string rep;
   double best = 1e300;
   int bb = 0, bg = 0, bt = 0, bs = 0, br = 1;
-  // mean kernel time of `reps` launches with the context's current shape
+  // mean device time of `reps` launches with the context's current shape:
+  // the assembly kernel and the row sums after it, whose cost grows with
+  // the ticket count
   auto time_shape = [&](double* ms_out) -> pdd_status {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return check_hip(ctx, e, "hipStreamSynchronize");
     const bool was = ctx->timing;
     ctx->timing = true;
+    ctx->timing_with_finalize = true;
     ctx->ev_used = 0;
     pdd_status st = PDD_OK;
     for (int r = 0; r < reps && st == PDD_OK; ++r) st = run_once();
@@ -437,6 +444,7 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
     }
     *ms_out = ms / std::max(ctx->ev_used, 1);
     ctx->timing = was;
+    ctx->timing_with_finalize = false;
     ctx->ev_used = 0;
     return st;
   };

@@ -145,6 +145,7 @@ struct pdd_ctx {
   int64_t last_tickets = 0;
   // optional event pairs around the assembly kernels
   bool timing = false;
+  bool timing_with_finalize = false;  // the autotuner's pairs also cover the row sums
   std::vector<hipEvent_t> ev_pool;   // 2 per timed launch, reused
   int ev_used = 0;                   // pairs recorded since pdd_set_timing
   ~pdd_ctx() {

@@ -390,7 +390,7 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   e = rbf ? launch_assemble_rbf(P, run.precision, (int)grid, block, lds, ctx->stream)
           : launch_assemble(P, run.precision, (int)grid, block, lds, ctx->stream);
   if (e != hipSuccess) return check_hip(ctx, e, "launch assemble");
-  if (t1) {
+  if (t1 && !ctx->timing_with_finalize) {
     if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
     ctx->ev_used += 1;
   }
@@ -414,6 +414,10 @@ pdd_status run_assemble(pdd_ctx* ctx, const AssembleJob& job) {
   F.rbf_half = P.rbf_half;
   e = launch_finalize(F, ctx->stream);
   if (e != hipSuccess) return check_hip(ctx, e, "launch finalize");
+  if (t1 && ctx->timing_with_finalize) {
+    if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess) return check_hip(ctx, e, "hipEventRecord");
+    ctx->ev_used += 1;
+  }
   ctx->last_grid = (int)grid;
   ctx->last_block = block;
   ctx->last_tickets = tc->n_tickets;
