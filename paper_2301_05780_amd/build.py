@@ -27,6 +27,10 @@ COMMON = [
     # MFMA operands and results in ordinary VGPRs (gfx950 allows either form):
     # no accumulator-register copies before the VALU reads a product
     "-mllvm", "-amdgpu-mfma-vgpr-form",
+    # no SLP vectorisation: it packed the table kernels' four exit compares
+    # into a 16-bit lane mask built bit by bit (about 10 instructions per
+    # step where four compares and scalar ORs do)
+    "-fno-slp-vectorize",
     "-I", INCLUDE, "-I", CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]

@@ -726,13 +726,16 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
           }
         }
       }
+      // one integer code per lane (buffer and side), so that each count is a
+      // single compare into a lane mask (booleans joined from the branches
+      // above would each pass through a vector register first)
+      const int scode = valid ? 4 * rb + o : -1;
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const bool mine = valid && rb == b;
-        const int cE = __popcll(__ballot(mine && o == 0));
-        const int cN = __popcll(__ballot(mine && o == 1));
-        const int cW = __popcll(__ballot(mine && o == 2));
-        const int cS = __popcll(__ballot(mine && o == 3));
+        const int cE = __popcll(__ballot(scode == 4 * b + 0));
+        const int cN = __popcll(__ballot(scode == 4 * b + 1));
+        const int cW = __popcll(__ballot(scode == 4 * b + 2));
+        const int cS = __popcll(__ballot(scode == 4 * b + 3));
         if (lane == 0 && (cE | cN | cW | cS) != 0) {
           double* ex = wrows + row_off(b, B[b]) + 4 * SL;
           ex[EX_E] += (double)cE;
