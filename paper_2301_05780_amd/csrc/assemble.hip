@@ -1039,10 +1039,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 // float32 table family whose copy holds only the varying fields (at most two
 // of the seven): one lane per path reads them, with no cooperative block in
-// LDS.  Four waves per SIMD (at most 128 VGPRs, which it fits without
-// spills; capped lower, its spills cost far more than the extra waves gain)
+// LDS.  With the gradient-table control variate, four waves per SIMD (at most
+// 128 VGPRs, which it fits without spills; capped at five, its spills cost
+// more than the extra wave gains); without one, five (96 VGPRs, a few
+// spilled words, and the fifth wave hides more latency than they cost)
 template <int CV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble_lane(AsmParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CV == PDD_CV_NONE ? 5 : 4))) void k_assemble_lane(
+    AsmParams P) {
   assemble_body<PDD_COEF_LUT, false, CV, false, false, false, true>(P);
 }
 
