@@ -336,7 +336,7 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
   // row extras (sum b, sum s^2, sum K): per-lane float64 sums flushed once
   // per ticket (LACC), or summed per 16-lane row before the LDS atomics
   // (ROWRED), or one atomic per exit (see process_queue)
-  constexpr bool LACC = LANE || BATCH;
+  constexpr bool LACC = (LANE && CV == PDD_CV_NONE) || BATCH;
   constexpr bool ROWRED = !LACC && KIND == PDD_COEF_LUT;
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
@@ -680,12 +680,13 @@ __device__ __forceinline__ void assemble_body(const AsmParams& P) {
       // to the same four words, and the LDS pipe serialises same-address
       // atomics (up to 64 per word per batch, a cost shared by the CU's
       // waves).  Where paths are short (many exits per step: the table
-      // family, batched launches) the lane-per-path table kernel and
+      // family, batched launches) the plain lane-per-path table kernel and
       // batched launches keep per-lane float64 sums in registers, summed
-      // over the wave when the ticket is flushed; the cooperative table
-      // kernels first sum each 16-lane row of the wave (DPP) and the row's
-      // last lane adds the row sum; the register-capped closed-form kernels
-      // keep one atomic per exit.  Without u_ref, s = b and sum s is copied
+      // over the wave when the ticket is flushed; the other table kernels
+      // (cooperative read, or the control variate's registers) first sum
+      // each 16-lane row of the wave (DPP) and the row's last lane adds the
+      // row sum; the register-capped closed-form kernels keep one atomic per
+      // exit.  Without u_ref, s = b and sum s is copied
       // from b at the flush (with u_ref, LACC adds s per exit).
       // Exit-side counts through ballots.
       if constexpr (LACC) {
@@ -1039,13 +1040,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 // float32 table family whose copy holds only the varying fields (at most two
 // of the seven): one lane per path reads them, with no cooperative block in
-// LDS.  With the gradient-table control variate, four waves per SIMD (at most
-// 128 VGPRs, which it fits without spills; capped at five, its spills cost
-// more than the extra wave gains); without one, five (96 VGPRs, a few
-// spilled words, and the fifth wave hides more latency than they cost)
+// LDS.  Five waves per SIMD (at most 96 VGPRs): the fifth wave hides more
+// latency than the few spilled words cost.  With the gradient-table control
+// variate the exit tallies are row-summed rather than kept per lane, which
+// frees the twelve registers that would spill there.
 template <int CV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CV == PDD_CV_NONE ? 5 : 4))) void k_assemble_lane(
-    AsmParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_assemble_lane(AsmParams P) {
   assemble_body<PDD_COEF_LUT, false, CV, false, false, false, true>(P);
 }
 

@@ -498,30 +498,42 @@ pdd_status pdd_autotune(pdd_ctx* ctx, int32_t n_inst, const pdd_instance* inst, 
   }
   ctx->refill_min = br;
   int bt2 = bt;
-  // fewer tally rows per workgroup on the best block and schedule, with the
-  // grid the smaller LDS allows (more resident waves, which sometimes wait
-  // for a row) and larger tickets, which make those waits rarer
-  int bsp = -1;
+  // fewer tally rows per workgroup on the best schedule, with the grid the
+  // smaller LDS allows (more resident waves, which sometimes wait for a row)
+  // and larger tickets, which make those waits rarer.  Both block sizes: the
+  // waves the smaller LDS admits depend on the block size, and the two can
+  // tie within the timing noise in the sweep above
+  int bsp = -1, bb2 = bb;
   // (single-instance assemblies share rows only with tabulated coefficients)
   const bool pooled = n_inst > 1 || inst[0].coeffs.kind == PDD_COEF_LUT;
-  for (int spare : {2, 1, 0}) {
-    if (!pooled) break;
-    for (int ppt : {bt, 1024, 2048, 4096}) {
-      if (ppt != bt && ppt <= bt) continue;
-      ctx->spare_rows = spare;
-      ctx->force_grid = 0;
-      ctx->force_per_ticket = ppt;
-      double ms = 0.0;
-      pdd_status st = run_once();
-      if (st != PDD_OK) return st;
-      if ((st = time_shape(&ms)) != PDD_OK) return st;
-      snprintf(buf, sizeof(buf), "best shape, %d spare rows, ppt %5d, grid %5d: %.4f ms\n", spare, ppt,
-               ctx->last_grid, ms);
-      rep += buf;
-      if (ms < best) { best = ms; bsp = spare; bg = 0; bt2 = ppt; }
+  for (int blk : {bb, bb == 256 ? 128 : 256}) {
+    for (int spare : {2, 1, 0}) {
+      if (!pooled) break;
+      // the sweep's ticket size and the larger ones, each once
+      int cands[4], nc = 0;
+      cands[nc++] = bt;
+      for (int p : {1024, 2048, 4096})
+        if (p > bt) cands[nc++] = p;
+      for (int c = 0; c < nc; ++c) {
+        const int ppt = cands[c];
+        ctx->force_block = blk;
+        ctx->spare_rows = spare;
+        ctx->force_grid = 0;
+        ctx->force_per_ticket = ppt;
+        double ms = 0.0;
+        pdd_status st = run_once();
+        if (st != PDD_OK) return st;
+        if ((st = time_shape(&ms)) != PDD_OK) return st;
+        snprintf(buf, sizeof(buf), "block %3d, %d spare rows, ppt %5d, grid %5d: %.4f ms\n", blk, spare, ppt,
+                 ctx->last_grid, ms);
+        rep += buf;
+        if (ms < best) { best = ms; bsp = spare; bg = 0; bt2 = ppt; bb2 = blk; }
+      }
     }
   }
+  bb = bb2;
   bt = bt2;
+  ctx->force_block = bb;
   ctx->force_per_ticket = bt;
   ctx->spare_rows = bsp;
   ctx->force_grid = bg;

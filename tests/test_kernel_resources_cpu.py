@@ -50,6 +50,7 @@ LISTED = {
     "_ZN3pdd12_GLOBAL__N_111k_calibrateILi6ELb1ELb1EEEvNS0_7CalArgsE": (136, 0),
     "_ZN3pdd12_GLOBAL__N_113k_assemble_w6ILi6EEEvNS_9AsmParamsE": (92, 26),
     "_ZN3pdd12_GLOBAL__N_115k_assemble_laneILi0EEEvNS_9AsmParamsE": (20, 4),
+    "_ZN3pdd12_GLOBAL__N_115k_assemble_laneILi2EEEvNS_9AsmParamsE": (32, 7),
     "_ZN3pdd12_GLOBAL__N_16k_evalILi0ELb0EEEvNS0_8EvalArgsE": (136, 0),
     "_ZN3pdd12_GLOBAL__N_16k_evalILi0ELb1EEEvNS0_8EvalArgsE": (136, 0),
     "_ZN3pdd12_GLOBAL__N_16k_evalILi1ELb0EEEvNS0_8EvalArgsE": (136, 0),
