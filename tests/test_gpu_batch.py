@@ -125,6 +125,9 @@ def test_autotune_keeps_results(ctx):
     arr, outs = ctx.batch_arrays(ws)
     ms, report = ctx.autotune(arr, reps=2)
     assert ms > 0 and "block" in report
+    # the spare-row phase (pooled tally rows: batched launches) tries both
+    # block sizes, whatever the sweep before it preferred
+    assert "block 256, 0 spare rows" in report and "block 128, 0 spare rows" in report, report
     ctx.assemble_batch(ws, arr=arr)
     ctx.sync()
     tuned = [_host(o) for o in outs]
